@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the Moebius domain-wall solve on one MI355X.
+
+Workload (the paper's a12m310-volume ensemble shape, Table I; action values
+M5 = 1.3, b5 = 1.5, c5 = 0.5): 24^3 x 64 lattice, L5 = 8, m_q = 0.0102,
+smooth random SU(3) links exp(i 0.25 H) (average plaquette ~0.65, standing in
+for the gradient-flowed HISQ ensembles that are not available), and a point
+source at a seeded site whose 12 spin-colour columns form the right-hand
+sides.
+
+One step = one pass of the whole hot path: source preparation, the
+mixed-precision CG on the normal equations of the even-odd Schur operator for
+all 12 columns in one multi-RHS launch (fused hop kernels, reductions,
+precision conversions, FP64 reliable updates), odd-site reconstruction and the
+FP64 true-residual check of every column to 1e-10.
+
+value = algorithmic HBM bytes of the step (model of every kernel it ran) /
+step time, in GB/s.  Inputs are resident in HBM before the timed region.
+Beside it: the solve time of plain FP64 CG on the same columns, the dslash
+kernels' achieved bandwidth against the 8 TB/s HBM peak (timed with HIP events
+on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (24, 24, 24, 64)
+L5 = 8
+ACTION = dict(M5=1.3, b5=1.5, c5=0.5, mq=0.0102)
+EPS, GAUGE_SEED, SITE_SEED, SRC_SEED = 0.25, 103, 403, 303
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def time_apply(M, torch, ctx, op, prec, reps, warm=5):
+    """Average duration of one mdwf_apply_dev(op) on torch's current stream."""
+    kin, kout = M.OP_KINDS[op]
+    nb_in = M.mdwf_field_bytes(ctx, prec, kin)
+    nb_out = M.mdwf_field_bytes(ctx, prec, kout)
+    dev = torch.device("cuda:0")
+    a = torch.empty(nb_in, dtype=torch.uint8, device=dev)
+    b = torch.empty(nb_out, dtype=torch.uint8, device=dev)
+    # a valid field: pack a Gaussian canonical half/full field
+    X, Y, Z, T = DIMS
+    nsites = X * Y * Z * T * L5 // (1 if kin == M.MDWF_FULL else 2)
+    g = torch.Generator(device=dev)
+    g.manual_seed(SRC_SEED)
+    canon = torch.randn(nsites * 24, dtype=torch.float64, device=dev, generator=g)
+    st = torch.cuda.current_stream().cuda_stream
+    M.mdwf_pack_dev(ctx, prec, kin, canon.data_ptr(), a.data_ptr(), st)
+    del canon
+    for _ in range(warm):
+        M.mdwf_apply_dev(ctx, op, prec, a.data_ptr(), b.data_ptr(), st)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        M.mdwf_apply_dev(ctx, op, prec, a.data_ptr(), b.data_ptr(), st)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops, bytes_ = M.mdwf_op_model(ctx, op, prec)
+    return dict(ms=ms, GBps=bytes_ / (ms * 1e-3) / 1e9, GFLOPs=flops / (ms * 1e-3) / 1e9,
+                model_bytes=bytes_, model_flops=flops)
+
+
+def cpu_baseline(U, dims, L5_, act_kw, budget_s=25.0):
+    """The FP64 oracle (single-threaded C, as it stands) applying the Schur
+    operator on the same lattice; rate in algorithmic GB/s of that apply."""
+    import oracle
+    act = oracle.Action(dims, L5_, **act_kw)
+    psi = np.zeros(act.shape5, complex)
+    rng = np.random.default_rng(SRC_SEED)
+    psi.real = rng.standard_normal(act.shape5)
+    psi.imag = rng.standard_normal(act.shape5)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.schur(act, U, psi)
+        n += 1
+        if time.perf_counter() - t0 > budget_s * 0.5 or n >= 3:
+            break
+    dt = (time.perf_counter() - t0) / n
+    X, Y, Z, T = dims
+    Vh = X * Y * Z * T * L5_ // 2
+    bytes_fp64 = Vh * ((120 + 288 / L5_) * 8)   # the same algorithmic model as the GPU kernels
+    return dict(value=bytes_fp64 / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample="%d FP64 Schur applications (full 24^3x64x8 lattice, single thread), %.1f s each" % (n, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", choices=["f16", "f32"], default="f16")
+    ap.add_argument("--nrhs", type=int, default=12)
+    ap.add_argument("--fp64-cols", type=int, default=1, help="columns solved with plain FP64 CG for the comparison")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--graph", type=int, default=1)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_1701_07559_amd import inputs as I
+    from paper_1701_07559_amd import mdwf as M
+
+    dev = torch.device("cuda:0")
+    X, Y, Z, T = DIMS
+    V = X * Y * Z * T
+    log("generating links", DIMS)
+    U = I.random_links(DIMS, EPS, GAUGE_SEED)
+    plaq = I.plaquette(U)
+    log("plaquette %.4f" % plaq)
+    site = I.random_point_site(DIMS, SITE_SEED)
+
+    ctx = M.mdwf_create(DIMS, antiperiodic_t=True, hip_device=0,
+                        hip_stream=torch.cuda.current_stream().cuda_stream)
+    M.mdwf_set_action(ctx, ACTION["M5"], ACTION["b5"], ACTION["c5"], ACTION["mq"], L5)
+    M.mdwf_load_gauge(ctx, U)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    micro = {}
+    if not args.no_micro:
+        for pname, prec in (("f64", 0), ("f32", 1), ("f16", 2)):
+            for oname, op in (("hop", M.MDWF_OP_HOP_EO), ("schur", M.MDWF_OP_SCHUR),
+                              ("schur_dag", M.MDWF_OP_SCHUR_DAG)):
+                r = time_apply(M, torch, ctx, op, prec, reps=50)
+                micro["%s_%s" % (oname, pname)] = r
+                log("%s %s: %.3f ms  %.0f GB/s  %.0f GFLOP/s" % (oname, pname, r["ms"], r["GBps"], r["GFLOPs"]))
+
+    # right-hand sides: the 12 spin-colour columns of a point source, FP64
+    # canonical, built on the device
+    nrhs = args.nrhs
+    ncan = L5 * V * 24
+    b = torch.zeros((nrhs, ncan), dtype=torch.float64, device=dev)
+    x = torch.zeros_like(b)
+    xs, ys, zs, ts = site
+    for k in range(nrhs):
+        col = k % 12
+        spin, colour = col // 3, col % 3
+        s = L5 - 1 if spin < 2 else 0
+        idx = ((((s * T + ts) * Z + zs) * Y + ys) * X + xs) * 12 + spin * 3 + colour
+        b[k, 2 * idx] = 1.0
+    torch.cuda.synchronize()
+    inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
+    opts = dict(tol=1e-10, inner=inner, max_iter=50000, delta=0.1, use_graph=args.graph)
+    bptr = [b[k].data_ptr() for k in range(nrhs)]
+    xptr = [x[k].data_ptr() for k in range(nrhs)]
+
+    def step():
+        return M.mdwf_solve_dev(ctx, bptr, xptr, opts=opts, stream=stream)
+
+    for w in range(args.warmup):
+        st, info = step()
+        log("warmup %d: status %d iters %s" % (w, st, [i["iters"] for i in info]))
+    torch.cuda.synchronize()
+    times, infos = [], None
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts0 = time.perf_counter()
+        st, infos = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts0)
+        log("step %d: %.3f s status %d max true resid %.2e" % (k, times[-1], st,
+                                                                max(i["true_resid"] for i in infos)))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = 1e3 * total / args.steps
+    step_bytes = sum(i["model_bytes"] for i in infos)
+    step_flops = sum(i["model_flops"] for i in infos)
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    all_ok = st == M.MDWF_OK and all(i["true_resid"] <= 1e-10 for i in infos)
+
+    # plain FP64 CG on the same columns (solved one at a time)
+    fp64 = None
+    if args.fp64_cols > 0:
+        o64 = dict(tol=1e-10, inner=M.MDWF_F64, max_iter=50000, use_graph=args.graph)
+        t64 = []
+        it64 = []
+        for k in range(min(args.fp64_cols, nrhs)):
+            t_a = time.perf_counter()
+            st64, i64 = M.mdwf_solve_dev(ctx, [bptr[k]], [xptr[k]], opts=o64, stream=stream)
+            torch.cuda.synchronize()
+            t64.append(time.perf_counter() - t_a)
+            it64.append(i64[0]["iters"])
+            log("fp64 column %d: %.3f s iters %d resid %.2e" % (k, t64[-1], it64[-1], i64[0]["true_resid"]))
+        per_col = float(np.mean(t64))
+        fp64 = dict(columns_solved=len(t64), seconds_per_column=per_col, iters=it64,
+                    seconds_all_columns=per_col * nrhs,
+                    note="sum over %d columns = measured per-column time x %d" % (nrhs, nrhs)
+                    if len(t64) < nrhs else "measured")
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(U, DIMS, L5, ACTION)
+        log("cpu oracle %.3f GB/s" % cpu["value"])
+
+    key = "schur_%s" % args.inner
+    roof = None
+    if key in micro:
+        r = micro[key]
+        roof = dict(bound="hbm", kernel="Schur apply = fused hop kernels A + B (%s)" % args.inner,
+                    achieved=round(r["GBps"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(r["GBps"] / HBM_PEAK_GBS, 4), traffic=None)
+
+    out = {
+        "metric": "Moebius DWF dslash GB/s (% HBM peak); time to r=1e-10 solve, mixed vs FP64",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.inner,
+        "data": "synthetic",
+        "config": {
+            "workload": "24^3x64 L5=8 M5=1.3 b5=1.5 c5=0.5 m_q=0.0102, exp(i0.25H) links (plaquette %.3f), "
+                        "%d point-source columns, one multi-RHS %s-inner solve to true residual 1e-10" %
+                        (plaq, nrhs, args.inner),
+            "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "inner": args.inner,
+        },
+        "solve": {
+            "seconds": round(ms_per_step / 1e3, 4),
+            "iters": [i["iters"] for i in infos],
+            "reliable_updates": [i["reliable_updates"] for i in infos],
+            "max_true_resid": max(i["true_resid"] for i in infos),
+            "all_within_1e-10": bool(all_ok),
+            "model_GFLOPs": round(step_flops / (ms_per_step * 1e-3) / 1e9, 1),
+        },
+        "fp64_cg": fp64,
+        "speedup_mixed_multirhs_vs_fp64": (round(fp64["seconds_all_columns"] / (ms_per_step / 1e3), 3)
+                                           if fp64 else None),
+        "dslash": {k: dict(ms=round(v["ms"], 4), GBps=round(v["GBps"], 1), frac=round(v["GBps"] / HBM_PEAK_GBS, 4),
+                           GFLOPs=round(v["GFLOPs"], 1)) for k, v in micro.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paper": "QUDA double-half MDWF solver, 1250 GFLOP/s on 2x K40 (Surface), 1785 on 4x K80 dies "
+                 "(RZHasGPU), volume not stated (context only)",
+    }
+    print(json.dumps(out), flush=True)
+    M.mdwf_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

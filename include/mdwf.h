@@ -1,0 +1,198 @@
+/*
+ * mdwf.h -- C ABI of libmdwf, an MI355X (gfx950) solver for the Moebius
+ * domain-wall fermion operator of arXiv:1701.07559.
+ *
+ * What is computed (paper Sec. II and Sec. VII):
+ *   The 5D Moebius domain-wall operator on SU(3) links with domain-wall height
+ *   M5, fifth-dimension extent L5, Moebius parameters b5, c5 and quark mass m_q.
+ *   Its 4D kernel is the paper's Moebius kernel
+ *     D^M = (b5 + c5) D_W(M5) / (2 + (b5 - c5) D_W(M5))            (Sec. II)
+ *   realised in 5D as
+ *     D5 = D_W B + 1 - C,  B = b5 + c5 C,
+ *     (C psi)_s = P- psi_{s+1} + P+ psi_{s-1}, with -m_q on the wrap,
+ *     D_W = (4 - M5) - 1/2 Dslash,
+ *     Dslash psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu).
+ *   D5 splits into the 4D-site-local K5 = (4 - M5) B + 1 - C and the hop
+ *   -1/2 Dslash B.  The solver works on the asymmetric even-odd Schur
+ *   complement the paper names (Sec. VII):
+ *     S = K5 - 1/4 D_eo B K5^-1 D_oe B   on the even 4D sites,
+ *   and solves D5 x = b by CG on the normal equations of S (least-squares
+ *   form), optionally with an FP32 or FP16 inner solve and FP64 reliable
+ *   updates (the paper's "double-half" mixed-precision solver, Sec. VII).
+ *
+ * Conventions:
+ *   Euclidean chiral gamma basis, g5 = diag(1, 1, -1, -1); P+ = spins 0,1.
+ *   4D parity = (x + y + z + t) mod 2; every lattice extent must be even.
+ *   Time may be antiperiodic for the fermions (hops across the t boundary
+ *   carry -1); x, y, z are periodic.
+ *
+ * Host canonical layouts (all FP64, complex as re,im pairs):
+ *   gauge     U[t][z][y][x][mu][a][b]        mu = 0..3 -> x, y, z, t; row a, col b
+ *   full 5D   psi[s][t][z][y][x][spin][col]  x fastest
+ *   half 5D   psi[s][t][z][y][x/2][spin][col]  the sites of one parity, in the
+ *             same order with x compressed (used by the SCHUR and HOP ops)
+ *
+ * Device native layout (what *_dev entry points take), per half field of
+ * Vh = L5 * V/2 five-dimensional sites, 5D site index j = i * L5 + s with i
+ * the parity-compressed 4D index:
+ *   F64: 12 blocks of double2 [12][Vh]  (one complex component per block)
+ *   F32:  6 blocks of float4  [6][Vh]   (two complex components per block)
+ *   F16:  3 blocks of 8 x half [3][Vh], then one float norm per site [Vh];
+ *         a stored value is half(v / norm) with norm = max |re|,|im| of the site
+ * Component order inside a site is spin-major: c = spin * 3 + colour.
+ * A half field occupies mdwf_field_bytes(..., MDWF_HALF_*) bytes; a full field
+ * is the even half followed by the odd half.
+ *
+ * Errors: every call returns a status; nothing aborts or throws across the
+ * ABI.  mdwf_last_error() describes the last failure on a context.
+ * Threading: one context per host thread.  Ownership: the caller owns every
+ * pointer it passes; the library copies what it needs and frees only memory it
+ * allocated itself.
+ */
+#ifndef MDWF_H
+#define MDWF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdwf_ctx mdwf_ctx;
+
+typedef enum {
+    MDWF_OK = 0,
+    MDWF_ERR_ARG = 1,      /* invalid argument (extent, parameter, null pointer) */
+    MDWF_ERR_STATE = 2,    /* call out of order (no gauge field / action yet)   */
+    MDWF_ERR_OOM = 3,      /* device allocation failed                          */
+    MDWF_ERR_HIP = 4,      /* HIP runtime error                                 */
+    MDWF_ERR_NOCONV = 5,   /* solver stopped at max_iter; best x written        */
+    MDWF_ERR_NUMERIC = 6   /* NaN/Inf or breakdown in a reduction               */
+} mdwf_status;
+
+typedef enum { MDWF_F64 = 0, MDWF_F32 = 1, MDWF_F16 = 2 } mdwf_prec;
+
+typedef enum {
+    MDWF_FULL = 0,     /* both parities, even half then odd half */
+    MDWF_HALF_EVEN = 1,
+    MDWF_HALF_ODD = 2
+} mdwf_field_kind;
+
+/* Operators.  Field kinds in -> out are given for each. */
+typedef enum {
+    MDWF_OP_D5 = 0,          /* full -> full : D5                                 */
+    MDWF_OP_D5_DAG = 1,      /* full -> full : D5^+ = B^+ D_W^+ + 1 - C^+         */
+    MDWF_OP_SCHUR = 2,       /* even -> even : S                                  */
+    MDWF_OP_SCHUR_DAG = 3,   /* even -> even : S^+                                */
+    MDWF_OP_HOP_EO = 4,      /* odd -> even  : Dslash (bare hop, no factor)       */
+    MDWF_OP_HOP_OE = 5,      /* even -> odd  : Dslash                             */
+    MDWF_OP_K5 = 6,          /* full -> full : K5                                 */
+    MDWF_OP_K5INV = 7,       /* full -> full : K5^-1                              */
+    MDWF_OP_HOP_EO_DAG = 8,  /* odd -> even  : Dslash^+ = g5 Dslash g5            */
+    MDWF_OP_HOP_OE_DAG = 9,  /* even -> odd  : Dslash^+                           */
+    MDWF_OP_K5_DAG = 10,     /* full -> full : K5^+                               */
+    MDWF_OP_K5INV_DAG = 11,  /* full -> full : (K5^+)^-1                          */
+    MDWF_OP_B = 12,          /* full -> full : B = b5 + c5 C                      */
+    MDWF_OP_B_DAG = 13,      /* full -> full : B^+                                */
+    MDWF_OP_COUNT = 14
+} mdwf_op;
+
+typedef struct {
+    int X, Y, Z, T;        /* all even, >= 2 */
+    int antiperiodic_t;    /* 1: fermion fields antiperiodic in t */
+} mdwf_geometry;
+
+/* Action parameters (paper Sec. II / III.A): requires b5 > c5 >= 0,
+ * 0 <= mq <= 1, 1 <= L5 <= 32, 0 < M5 < 2. */
+typedef struct {
+    double M5, b5, c5, mq;
+    int L5;
+} mdwf_action;
+
+typedef struct {
+    double tol;          /* target ||b - D5 x|| / ||b||, e.g. 1e-10            */
+    int max_iter;        /* cap on inner CG iterations per right-hand side     */
+    mdwf_prec inner;     /* precision of the inner CG (F64 = plain FP64 CG)    */
+    double delta;        /* reliable update when ||r|| < delta * ||r_last||    */
+    int check_every;     /* host convergence check period in iterations (>=1)  */
+    int use_graph;       /* 1: replay CG iterations from a captured hipGraph   */
+} mdwf_solver_opts;
+
+typedef struct {
+    int iters;            /* inner CG iterations                                  */
+    int reliable_updates; /* FP64 residual recomputations                         */
+    int restarts;         /* true-residual checks that failed and restarted       */
+    double true_resid;    /* ||b - D5 x|| / ||b|| in FP64 on the returned x        */
+    double seconds;       /* wall time of the solve call                          */
+    double model_flops;   /* flops of the model counted for this right-hand side  */
+    double model_bytes;   /* algorithmic HBM bytes of the model for this RHS       */
+} mdwf_solve_info;
+
+/* Create a context for one lattice geometry on HIP device `hip_device`.
+ * hip_stream: a hipStream_t to run on, or NULL for a stream the library owns.
+ * Fails with ERR_ARG on odd or non-positive extents, ERR_HIP on a bad device. */
+mdwf_status mdwf_create(const mdwf_geometry *geom, int hip_device, void *hip_stream, mdwf_ctx **out);
+
+/* Release all device memory the context owns.  NULL is ignored. */
+void mdwf_destroy(mdwf_ctx *ctx);
+
+/* Description of the last error on ctx (or of the last failed create when ctx
+ * is NULL).  Valid until the next call on the same context. */
+const char *mdwf_last_error(const mdwf_ctx *ctx);
+
+/* Copy gauge links from host memory (canonical layout, FP64) to the device,
+ * in FP64, FP32 and FP16 native link layouts, with the antiperiodic time sign
+ * folded into the links on the last time slice. */
+mdwf_status mdwf_load_gauge(mdwf_ctx *ctx, const double *U);
+
+/* Same as mdwf_load_gauge from a device pointer in the canonical layout. */
+mdwf_status mdwf_load_gauge_dev(mdwf_ctx *ctx, const double *U_dev);
+
+/* Set M5, b5, c5, L5, m_q (paper Sec. II).  Validates as documented above. */
+mdwf_status mdwf_set_action(mdwf_ctx *ctx, const mdwf_action *act);
+
+/* Bytes of one field of the given kind and precision in the native layout. */
+mdwf_status mdwf_field_bytes(const mdwf_ctx *ctx, mdwf_prec prec, mdwf_field_kind kind, size_t *bytes);
+
+/* Convert between the canonical FP64 layout and the native layout, both on the
+ * device.  For MDWF_HALF_* the canonical array is the parity-compressed one. */
+mdwf_status mdwf_pack_dev(mdwf_ctx *ctx, mdwf_prec prec, mdwf_field_kind kind,
+                          const double *canon_dev, void *native_dev, void *stream);
+mdwf_status mdwf_unpack_dev(mdwf_ctx *ctx, mdwf_prec prec, mdwf_field_kind kind,
+                            const void *native_dev, double *canon_dev, void *stream);
+
+/* Apply an operator to a host canonical FP64 field; the arithmetic runs on the
+ * device in precision `prec` (input rounded to it, output widened back). */
+mdwf_status mdwf_apply(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const double *in, double *out);
+
+/* Apply an operator to device native fields in precision `prec` on `stream`
+ * (NULL = the context's stream).  in and out must not overlap.  Asynchronous:
+ * returns after enqueueing. */
+mdwf_status mdwf_apply_dev(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const void *in, void *out,
+                           void *stream);
+
+/* Solve D5 x_k = b_k for k < nrhs (host canonical full FP64 fields).
+ * mq: per-RHS quark mass (NULL = the action's m_q); all other action
+ * parameters are shared.  info: array of nrhs records (may be NULL).
+ * Returns ERR_NOCONV if any RHS hit max_iter (its best x is still written). */
+mdwf_status mdwf_solve(mdwf_ctx *ctx, int nrhs, const double *const *b, double *const *x,
+                       const double *mq, const mdwf_solver_opts *opts, mdwf_solve_info *info);
+
+/* Same as mdwf_solve with canonical FP64 fields already in device memory.
+ * Synchronous with respect to `stream` (NULL = the context's stream). */
+mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, double *const *x_dev,
+                           const double *mq, const mdwf_solver_opts *opts, mdwf_solve_info *info,
+                           void *stream);
+
+/* Fill opts with defaults: tol 1e-10, max_iter 100000, inner F64, delta 0.1,
+ * check_every 1, use_graph 0. */
+void mdwf_default_opts(mdwf_solver_opts *opts);
+
+/* Model flop and byte counts for one application of an operator (per call). */
+mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, double *flops, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDWF_H */

@@ -1,0 +1,470 @@
+// C ABI of libmdwf: context, gauge upload, action, operator application.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ctx.h"
+
+using namespace mdwf;
+
+static thread_local std::string g_create_err;
+
+namespace mdwf {
+
+mdwf_status fail(mdwf_ctx* c, mdwf_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return st;
+}
+
+mdwf_status hip_check(mdwf_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return MDWF_OK;
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? MDWF_ERR_OOM : MDWF_ERR_HIP, m);
+}
+
+void* buf(mdwf_ctx* c, const std::string& name, size_t n, mdwf_status* st) {
+    auto& b = c->bufs[name];
+    if (b.n >= n && b.p) return b.p;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n < 256 ? 256 : n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *st = fail(c, MDWF_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes for '" + name + "' failed");
+        return nullptr;
+    }
+    b.p = p;
+    b.n = n;
+    return p;
+}
+
+void* pinned(mdwf_ctx* c, size_t n, mdwf_status* st) {
+    if (c->h_pin_n >= n) return c->h_pin;
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    c->h_pin = nullptr;
+    c->h_pin_n = 0;
+    if (hipHostMalloc(&c->h_pin, n, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        *st = fail(c, MDWF_ERR_OOM, "pinned host allocation failed");
+        return nullptr;
+    }
+    c->h_pin_n = n;
+    return c->h_pin;
+}
+
+// K5 = (4 - M5) B + 1 - C = a + b C.  Its inverse on each chirality, using
+// C^L5 = -m_q: K5^-1 = [a (1 + m_q z^L5)]^-1 sum_{k<L5} z^k C^k, z = -b/a;
+// B K5^-1 is the product of the two polynomials reduced with C^L5 = -m_q.
+RhsCoef make_coef(const mdwf_action& a, double mq) {
+    RhsCoef c;
+    std::memset(&c, 0, sizeof(c));
+    const int L5 = a.L5;
+    c.mq = mq;
+    c.b5 = a.b5;
+    c.c5 = a.c5;
+    const double ka = 1.0 + a.b5 * (4.0 - a.M5);
+    const double kb = a.c5 * (4.0 - a.M5) - 1.0;
+    c.k5[0] = ka;
+    c.k5[1] = kb;
+    const double z = -kb / ka;
+    const double norm = 1.0 / (ka * (1.0 + mq * std::pow(z, L5)));
+    double zk = 1.0;
+    for (int k = 0; k < L5; ++k) {
+        c.kinv[k] = zk * norm;
+        zk *= z;
+    }
+    c.m[0] = a.b5 * c.kinv[0] - mq * a.c5 * c.kinv[L5 - 1];
+    for (int k = 1; k < L5; ++k) c.m[k] = a.b5 * c.kinv[k] + a.c5 * c.kinv[k - 1];
+    return c;
+}
+
+double spinor_site_bytes(Prec p) { return p == P64 ? 192.0 : p == P32 ? 96.0 : 52.0; }
+double link_site_bytes(Prec p, int L5) { return (p == P64 ? 8.0 : p == P32 ? 4.0 : 2.0) * 144.0 / L5; }
+
+// Algorithmic model: every field is read or written once per kernel, links
+// are 18 reals each (8 per site, shared by the L5 slices); flops count the
+// Wilson hop as 1320 per 5D site (8 directions x (12 projection + 132 SU(3))
+// + 168 accumulation), 72 for B or K5, 48 L5 for a dense L5 polynomial, 48
+// for a combine, 48 per norm.
+void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes) {
+    const double Vh = g.Vh, L5 = g.L5;
+    const double bs = spinor_site_bytes(p), bl = link_site_bytes(p, g.L5);
+    double f = 0, b = 0;
+    switch (op) {
+        case MDWF_OP_HOP_EO: case MDWF_OP_HOP_OE: case MDWF_OP_HOP_EO_DAG: case MDWF_OP_HOP_OE_DAG:
+            f = 1320; b = 2 * bs + bl; break;
+        case MDWF_OP_D5: f = 2 * (1320 + 72 + 72 + 48); b = 2 * (3 * bs + bl); break;
+        case MDWF_OP_D5_DAG: f = 2 * (1320 + 72 + 72 + 48); b = 2 * (3 * bs + bl); break;
+        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG:
+            f = (1320 + 72 + 48 * L5) + (1320 + 72 + 48); b = (2 * bs + bl) + (3 * bs + bl); break;
+        case MDWF_OP_K5: case MDWF_OP_K5_DAG: case MDWF_OP_B: case MDWF_OP_B_DAG:
+            f = 2 * 72; b = 2 * 2 * bs; break;
+        case MDWF_OP_K5INV: case MDWF_OP_K5INV_DAG:
+            f = 2 * 48 * L5; b = 2 * 2 * bs; break;
+        default: break;
+    }
+    *flops = f * Vh;
+    *bytes = b * Vh;
+}
+
+mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
+                         const RhsCoef* d_coef, const int* d_active, hipStream_t st) {
+    const Geo& g = c->geo;
+    const size_t hb = half_field_bytes(p, g.Vh);
+    const char* ie = static_cast<const char*>(in);
+    const char* io = ie + hb;
+    char* oe = static_cast<char*>(out);
+    char* oo = oe + hb;
+    HopLaunch L{};
+    L.prec = p;
+    L.stride = stride;
+    L.nrhs = nrhs;
+    L.coef = d_coef;
+    L.active = d_active;
+    L.partials = nullptr;
+    mdwf_status s = MDWF_OK;
+    switch (op) {
+        case MDWF_OP_D5:
+        case MDWF_OP_D5_DAG:
+            L.kind = (op == MDWF_OP_D5) ? HOP_D5 : HOP_D5_DAG;
+            L.out_parity = 0; L.out = oe; L.in = io; L.centre = ie;
+            launch_hop(g, c->gs, L, st);
+            L.out_parity = 1; L.out = oo; L.in = ie; L.centre = io;
+            launch_hop(g, c->gs, L, st);
+            break;
+        case MDWF_OP_SCHUR:
+        case MDWF_OP_SCHUR_DAG: {
+            void* tmp = buf(c, "apply_tmp", stride * nrhs, &s);
+            if (!tmp) return s;
+            L.kind = (op == MDWF_OP_SCHUR) ? HOP_SCHUR_A : HOP_SCHUR_A_DAG;
+            L.out_parity = 1; L.out = tmp; L.in = in; L.centre = nullptr;
+            launch_hop(g, c->gs, L, st);
+            L.kind = (op == MDWF_OP_SCHUR) ? HOP_SCHUR_B : HOP_SCHUR_B_DAG;
+            L.out_parity = 0; L.out = out; L.in = tmp; L.centre = in;
+            launch_hop(g, c->gs, L, st);
+            break;
+        }
+        case MDWF_OP_HOP_EO:
+        case MDWF_OP_HOP_EO_DAG:
+            L.kind = (op == MDWF_OP_HOP_EO) ? HOP_BARE : HOP_BARE_DAG;
+            L.out_parity = 0; L.out = out; L.in = in; L.centre = nullptr;
+            launch_hop(g, c->gs, L, st);
+            break;
+        case MDWF_OP_HOP_OE:
+        case MDWF_OP_HOP_OE_DAG:
+            L.kind = (op == MDWF_OP_HOP_OE) ? HOP_BARE : HOP_BARE_DAG;
+            L.out_parity = 1; L.out = out; L.in = in; L.centre = nullptr;
+            launch_hop(g, c->gs, L, st);
+            break;
+        case MDWF_OP_K5: case MDWF_OP_K5_DAG: case MDWF_OP_K5INV: case MDWF_OP_K5INV_DAG:
+        case MDWF_OP_B: case MDWF_OP_B_DAG: {
+            const FifthKind k = (op == MDWF_OP_K5 || op == MDWF_OP_K5_DAG) ? FIFTH_K5
+                              : (op == MDWF_OP_B || op == MDWF_OP_B_DAG) ? FIFTH_B : FIFTH_K5INV;
+            const int dag = (op == MDWF_OP_K5_DAG || op == MDWF_OP_K5INV_DAG || op == MDWF_OP_B_DAG) ? 1 : 0;
+            launch_fifth(g, p, k, dag, ie, oe, stride, nrhs, d_coef, d_active, st);
+            launch_fifth(g, p, k, dag, io, oo, stride, nrhs, d_coef, d_active, st);
+            break;
+        }
+        default:
+            return fail(c, MDWF_ERR_ARG, "unknown operator");
+    }
+    return hip_check(c, hipGetLastError(), "kernel launch");
+}
+
+}  // namespace mdwf
+
+// ------------------------------------------------------------------ helpers
+static bool op_full(mdwf_op op) {
+    return !(op == MDWF_OP_SCHUR || op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_HOP_EO || op == MDWF_OP_HOP_OE ||
+             op == MDWF_OP_HOP_EO_DAG || op == MDWF_OP_HOP_OE_DAG);
+}
+static int op_in_kind(mdwf_op op) {
+    switch (op) {
+        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: return MDWF_HALF_EVEN;
+        case MDWF_OP_HOP_EO: case MDWF_OP_HOP_EO_DAG: return MDWF_HALF_ODD;
+        case MDWF_OP_HOP_OE: case MDWF_OP_HOP_OE_DAG: return MDWF_HALF_EVEN;
+        default: return MDWF_FULL;
+    }
+}
+static int op_out_kind(mdwf_op op) {
+    switch (op) {
+        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: return MDWF_HALF_EVEN;
+        case MDWF_OP_HOP_EO: case MDWF_OP_HOP_EO_DAG: return MDWF_HALF_EVEN;
+        case MDWF_OP_HOP_OE: case MDWF_OP_HOP_OE_DAG: return MDWF_HALF_ODD;
+        default: return MDWF_FULL;
+    }
+}
+
+static mdwf_status ready(mdwf_ctx* c) {
+    if (!c) return fail(nullptr, MDWF_ERR_ARG, "null context");
+    if (!c->have_action) return fail(c, MDWF_ERR_STATE, "mdwf_set_action has not been called");
+    if (!c->have_gauge) return fail(c, MDWF_ERR_STATE, "mdwf_load_gauge has not been called");
+    return hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+}
+
+static bool valid_prec(int p) { return p == MDWF_F64 || p == MDWF_F32 || p == MDWF_F16; }
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_stream, mdwf_ctx** out) {
+    if (!out) return fail(nullptr, MDWF_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!geom) return fail(nullptr, MDWF_ERR_ARG, "geometry is null");
+    const int L[4] = {geom->X, geom->Y, geom->Z, geom->T};
+    for (int k = 0; k < 4; ++k)
+        if (L[k] < 2 || (L[k] & 1))
+            return fail(nullptr, MDWF_ERR_ARG, "every lattice extent must be even and >= 2");
+    const double V = double(geom->X) * geom->Y * geom->Z * geom->T;
+    if (V * 32 / 2 >= 2147483647.0) return fail(nullptr, MDWF_ERR_ARG, "lattice too large for 32-bit site indices");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, MDWF_ERR_HIP, "no HIP device available");
+    }
+    if (hip_device < 0 || hip_device >= ndev) return fail(nullptr, MDWF_ERR_ARG, "hip_device out of range");
+    mdwf_ctx* c = new (std::nothrow) mdwf_ctx();
+    if (!c) return fail(nullptr, MDWF_ERR_OOM, "host allocation failed");
+    c->device = hip_device;
+    c->geom = *geom;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MDWF_ERR_HIP, "hipSetDevice failed");
+    }
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, MDWF_ERR_HIP, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    Geo& g = c->geo;
+    g.X = geom->X; g.Y = geom->Y; g.Z = geom->Z; g.T = geom->T;
+    g.Xh = geom->X / 2;
+    g.Vh4 = int(V / 2);
+    g.L5 = 0;
+    g.Vh = 0;
+    g.antiperiodic = geom->antiperiodic_t ? 1 : 0;
+    g.fXh = FastDiv(uint32_t(g.Xh));
+    g.fY = FastDiv(uint32_t(g.Y));
+    g.fZ = FastDiv(uint32_t(g.Z));
+    if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
+        (void)hipGetLastError();
+        mdwf_destroy(c);
+        return fail(nullptr, MDWF_ERR_OOM, "device allocation failed");
+    }
+    *out = c;
+    return MDWF_OK;
+}
+
+void mdwf_destroy(mdwf_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    if (c->gauge_mem) (void)hipFree(c->gauge_mem);
+    if (c->d_coef1) (void)hipFree(c->d_coef1);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* mdwf_last_error(const mdwf_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+void mdwf_default_opts(mdwf_solver_opts* o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->max_iter = 100000;
+    o->inner = MDWF_F64;
+    o->delta = 0.1;
+    o->check_every = 1;
+    o->use_graph = 0;
+}
+
+static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_device) {
+    if (!c) return fail(nullptr, MDWF_ERR_ARG, "null context");
+    if (!U) return fail(c, MDWF_ERR_ARG, "gauge pointer is null");
+    mdwf_status s = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+    if (s) return s;
+    Geo& g = c->geo;
+    size_t seg[3], tot = 0;
+    for (int p = 0; p < 3; ++p) {
+        seg[p] = link_segment_bytes(Prec(p), g.Vh4);
+        tot += 8 * seg[p];
+    }
+    if (!c->gauge_mem) {
+        s = hip_check(c, hipMalloc(&c->gauge_mem, tot), "gauge allocation");
+        if (s) return s;
+    }
+    char* base = static_cast<char*>(c->gauge_mem);
+    for (int p = 0; p < 3; ++p) {
+        c->gs.seg[p] = base;
+        c->gs.seg_bytes[p] = seg[p];
+        base += 8 * seg[p];
+    }
+    const size_t canon_bytes = size_t(2) * g.Vh4 * 4 * 18 * sizeof(double);
+    const double* src = U;
+    if (!on_device) {
+        void* stage = buf(c, "gauge_stage", canon_bytes, &s);
+        if (!stage) return s;
+        s = hip_check(c, hipMemcpyAsync(stage, U, canon_bytes, hipMemcpyHostToDevice, c->stream), "gauge H2D");
+        if (s) return s;
+        src = static_cast<const double*>(stage);
+    }
+    launch_gauge_layout(g, src, c->gs, c->stream);
+    s = hip_check(c, hipGetLastError(), "gauge layout kernel");
+    if (s) return s;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "gauge upload");
+    if (s) return s;
+    c->have_gauge = true;
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_load_gauge(mdwf_ctx* c, const double* U) { return load_gauge_common(c, U, false); }
+mdwf_status mdwf_load_gauge_dev(mdwf_ctx* c, const double* U) { return load_gauge_common(c, U, true); }
+
+mdwf_status mdwf_set_action(mdwf_ctx* c, const mdwf_action* a) {
+    if (!c) return fail(nullptr, MDWF_ERR_ARG, "null context");
+    if (!a) return fail(c, MDWF_ERR_ARG, "action is null");
+    if (a->L5 < 1 || a->L5 > kMaxL5) return fail(c, MDWF_ERR_ARG, "L5 must be in [1, 32]");
+    if (!(a->c5 >= 0.0) || !(a->b5 > a->c5)) return fail(c, MDWF_ERR_ARG, "need b5 > c5 >= 0");
+    if (!(a->mq >= 0.0 && a->mq <= 1.0)) return fail(c, MDWF_ERR_ARG, "need 0 <= mq <= 1");
+    if (!(a->M5 > 0.0 && a->M5 < 2.0)) return fail(c, MDWF_ERR_ARG, "need 0 < M5 < 2");
+    if (!std::isfinite(a->b5) || !std::isfinite(a->c5) || !std::isfinite(a->M5))
+        return fail(c, MDWF_ERR_ARG, "non-finite action parameter");
+    mdwf_status s = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+    if (s) return s;
+    c->act = *a;
+    c->geo.L5 = a->L5;
+    c->geo.Vh = c->geo.Vh4 * a->L5;
+    RhsCoef cf = make_coef(*a, a->mq);
+    s = hip_check(c, hipMemcpy(c->d_coef1, &cf, sizeof(cf), hipMemcpyHostToDevice), "coefficient upload");
+    if (s) return s;
+    c->have_action = true;
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_field_bytes(const mdwf_ctx* c, mdwf_prec prec, mdwf_field_kind kind, size_t* bytes) {
+    if (!c || !bytes) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "null argument");
+    if (!valid_prec(prec)) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "bad precision");
+    if (!c->have_action) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_STATE, "mdwf_set_action has not been called");
+    const size_t hb = half_field_bytes(Prec(prec), c->geo.Vh);
+    *bytes = (kind == MDWF_FULL) ? 2 * hb : hb;
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_pack_dev(mdwf_ctx* c, mdwf_prec prec, mdwf_field_kind kind, const double* canon, void* native,
+                          void* stream) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!valid_prec(prec) || kind < 0 || kind > 2 || !canon || !native) return fail(c, MDWF_ERR_ARG, "bad argument");
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    launch_pack(c->geo, Prec(prec), kind, canon, native, st);
+    return hip_check(c, hipGetLastError(), "pack kernel");
+}
+
+mdwf_status mdwf_unpack_dev(mdwf_ctx* c, mdwf_prec prec, mdwf_field_kind kind, const void* native, double* canon,
+                            void* stream) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!valid_prec(prec) || kind < 0 || kind > 2 || !canon || !native) return fail(c, MDWF_ERR_ARG, "bad argument");
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    launch_unpack(c->geo, Prec(prec), kind, native, canon, st);
+    return hip_check(c, hipGetLastError(), "unpack kernel");
+}
+
+mdwf_status mdwf_apply_dev(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, const void* in, void* out, void* stream) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!valid_prec(prec) || op < 0 || op >= MDWF_OP_COUNT) return fail(c, MDWF_ERR_ARG, "bad operator or precision");
+    if (!in || !out) return fail(c, MDWF_ERR_ARG, "null field pointer");
+    if (in == out) return fail(c, MDWF_ERR_ARG, "in and out must not overlap");
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    const size_t hb = half_field_bytes(Prec(prec), c->geo.Vh);
+    const size_t stride = op_full(op) ? 2 * hb : hb;
+    return apply_native(c, op, Prec(prec), in, out, stride, 1, c->d_coef1, nullptr, st);
+}
+
+mdwf_status mdwf_apply(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, const double* in, double* out) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!valid_prec(prec) || op < 0 || op >= MDWF_OP_COUNT) return fail(c, MDWF_ERR_ARG, "bad operator or precision");
+    if (!in || !out) return fail(c, MDWF_ERR_ARG, "null field pointer");
+    const Geo& g = c->geo;
+    const int ik = op_in_kind(op), ok = op_out_kind(op);
+    const size_t full_canon = size_t(2) * g.Vh * 24 * sizeof(double);
+    const size_t in_canon = ik == MDWF_FULL ? full_canon : full_canon / 2;
+    const size_t out_canon = ok == MDWF_FULL ? full_canon : full_canon / 2;
+    const size_t hb = half_field_bytes(Prec(prec), g.Vh);
+    void* cin = buf(c, "apply_canon_in", in_canon, &s);
+    if (!cin) return s;
+    void* cout = buf(c, "apply_canon_out", out_canon, &s);
+    if (!cout) return s;
+    void* nin = buf(c, "apply_native_in", 2 * hb, &s);
+    if (!nin) return s;
+    void* nout = buf(c, "apply_native_out", 2 * hb, &s);
+    if (!nout) return s;
+    hipStream_t st = c->stream;
+    if ((s = hip_check(c, hipMemcpyAsync(cin, in, in_canon, hipMemcpyHostToDevice, st), "H2D"))) return s;
+    launch_pack(g, Prec(prec), ik, static_cast<const double*>(cin), nin, st);
+    const size_t stride = op_full(op) ? 2 * hb : hb;
+    if ((s = apply_native(c, op, Prec(prec), nin, nout, stride, 1, c->d_coef1, nullptr, st))) return s;
+    launch_unpack(g, Prec(prec), ok, nout, static_cast<double*>(cout), st);
+    if ((s = hip_check(c, hipGetLastError(), "unpack kernel"))) return s;
+    if ((s = hip_check(c, hipMemcpyAsync(out, cout, out_canon, hipMemcpyDeviceToHost, st), "D2H"))) return s;
+    return hip_check(c, hipStreamSynchronize(st), "apply");
+}
+
+mdwf_status mdwf_op_model(const mdwf_ctx* c, mdwf_op op, mdwf_prec prec, double* flops, double* bytes) {
+    if (!c || !flops || !bytes) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "null argument");
+    if (!c->have_action) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_STATE, "mdwf_set_action has not been called");
+    if (!valid_prec(prec) || op < 0 || op >= MDWF_OP_COUNT) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "bad operator or precision");
+    op_model(c->geo, op, Prec(prec), flops, bytes);
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_solve_dev(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, const double* mq,
+                           const mdwf_solver_opts* o, mdwf_solve_info* info, void* stream) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    return mdwf_solve_dev_impl(c, nrhs, b, x, mq, o, info, st);
+}
+
+mdwf_status mdwf_solve(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, const double* mq,
+                       const mdwf_solver_opts* o, mdwf_solve_info* info) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (nrhs < 1 || !b || !x) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
+    for (int k = 0; k < nrhs; ++k)
+        if (!b[k] || !x[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+    const size_t fb = size_t(2) * c->geo.Vh * 24 * sizeof(double);
+    char* db = static_cast<char*>(buf(c, "solve_host_b", fb * nrhs, &s));
+    if (!db) return s;
+    char* dx = static_cast<char*>(buf(c, "solve_host_x", fb * nrhs, &s));
+    if (!dx) return s;
+    std::vector<const double*> bp(nrhs);
+    std::vector<double*> xp(nrhs);
+    for (int k = 0; k < nrhs; ++k) {
+        bp[k] = reinterpret_cast<const double*>(db + fb * k);
+        xp[k] = reinterpret_cast<double*>(dx + fb * k);
+        if ((s = hip_check(c, hipMemcpyAsync(db + fb * k, b[k], fb, hipMemcpyHostToDevice, c->stream), "H2D")))
+            return s;
+    }
+    mdwf_status rs = mdwf_solve_dev_impl(c, nrhs, bp.data(), xp.data(), mq, o, info, c->stream);
+    if (rs != MDWF_OK && rs != MDWF_ERR_NOCONV && rs != MDWF_ERR_NUMERIC) return rs;
+    for (int k = 0; k < nrhs; ++k)
+        if ((s = hip_check(c, hipMemcpyAsync(x[k], dx + fb * k, fb, hipMemcpyDeviceToHost, c->stream), "D2H")))
+            return s;
+    if ((s = hip_check(c, hipStreamSynchronize(c->stream), "solve D2H"))) return s;
+    return rs;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Context object behind the opaque mdwf_ctx handle.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mdwf.h"
+#include "mdwf_internal.h"
+
+struct mdwf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mdwf_geometry geom{};
+    mdwf::Geo geo{};
+    bool have_action = false;
+    mdwf_action act{};
+    bool have_gauge = false;
+    mdwf::GaugeSet gs;
+    void* gauge_mem = nullptr;
+    std::string err;
+
+    // grow-only named device buffers
+    struct Buf {
+        void* p = nullptr;
+        size_t n = 0;
+    };
+    std::map<std::string, Buf> bufs;
+
+    // per-RHS coefficient table of the context's own action (one entry)
+    mdwf::RhsCoef* d_coef1 = nullptr;
+    // pinned host staging for scalars
+    void* h_pin = nullptr;
+    size_t h_pin_n = 0;
+};
+
+namespace mdwf {
+
+// Error helpers: record a message on the context and return a status.
+mdwf_status fail(mdwf_ctx* c, mdwf_status st, const std::string& msg);
+mdwf_status hip_check(mdwf_ctx* c, hipError_t e, const char* what);
+
+// Device buffer of at least n bytes under `name` (contents undefined after growth).
+void* buf(mdwf_ctx* c, const std::string& name, size_t n, mdwf_status* st);
+void* pinned(mdwf_ctx* c, size_t n, mdwf_status* st);
+
+// Coefficients of the fifth-dimension polynomials for mass mq.
+RhsCoef make_coef(const mdwf_action& a, double mq);
+
+// Native-layout operator application on `nrhs` right-hand sides stored at
+// byte stride `stride` (half fields; a full field is two consecutive halves of
+// half_field_bytes each and `stride` then covers both).
+mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
+                         const RhsCoef* d_coef, const int* d_active, hipStream_t st);
+
+// Model counts (per application, all right-hand sides counted once).
+void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes);
+double spinor_site_bytes(Prec p);
+double link_site_bytes(Prec p, int L5);
+
+}  // namespace mdwf
+
+mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_dev, double* const* x_dev,
+                                const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st);

@@ -1,0 +1,445 @@
+// Wilson hop on every fifth-dimension slice, fused with the fifth-dimension
+// operators of the Moebius domain-wall operator (arXiv:1701.07559, Sec. II).
+//
+// Thread mapping: the L5 slices of one 4D site sit in L5 consecutive lanes of
+// one wavefront (64 / L5 sites per wave; the remaining lanes idle).  All lanes
+// of a site read the same eight links, so a link is fetched once per site and
+// reused across the fifth dimension, and the fifth-dimension couplings (B, C,
+// K5 and the dense B K5^-1) become exchanges inside that lane group:
+// ds_bpermute for the nearest-slice terms, an LDS tile for the dense L5 x L5
+// polynomials.  Spinors are read 16 bytes per lane from the structure-of-
+// arrays layout, so a wave's loads of one block are contiguous.
+#include "mdwf_internal.h"
+
+namespace mdwf {
+
+// ----------------------------------------------------------- lane exchange
+__device__ __forceinline__ float bperm(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bperm(int addr, double v) {
+    int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <typename R> __device__ __forceinline__ cx<R> bperm(int addr, cx<R> v) {
+    return {bperm(addr, v.re), bperm(addr, v.im)};
+}
+
+// Exchange partners of lane s inside its site group: s-1 and s+1 with
+// wrap-around; the wrapped term carries -m_q (quark-mass coupling of walls).
+template <typename R> struct Nbr5 {
+    int am1, ap1;   // bpermute byte addresses of lanes s-1, s+1
+    R fm1, fp1;     // 1, or -m_q on the wrap
+};
+
+// (C v) with C = P- shift(s+1) + P+ shift(s-1) (dag = 0) or C^+ (dag = 1);
+// spins 0,1 are P+ (components 0..5), spins 2,3 are P- (components 6..11).
+template <typename R, bool DAGC>
+__device__ __forceinline__ void apply_C_lanes(const Nbr5<R>& n, const cx<R> v[12], cx<R> out[12]) {
+    const int aU = DAGC ? n.ap1 : n.am1;
+    const R fU = DAGC ? n.fp1 : n.fm1;
+    const int aD = DAGC ? n.am1 : n.ap1;
+    const R fD = DAGC ? n.fm1 : n.fp1;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[c] = fU * bperm(aU, v[c]);
+#pragma unroll
+    for (int c = 6; c < 12; ++c) out[c] = fD * bperm(aD, v[c]);
+}
+
+// ------------------------------------------------------------ spin algebra
+// Chiral basis: g_mu = [[0, G],[G^+, 0]] with G_x = -i s1, G_y = -i s2,
+// G_z = -i s3, G_t = 1.  (1 - sg g_mu) psi = (h, -sg G^+ h) with the half
+// spinor h = u - sg G d (u, d = upper and lower spin pairs).
+template <int MU, typename R>
+__device__ __forceinline__ void project(R sg, const cx<R> in[12], cx<R> h[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<R> u0 = in[a], u1 = in[3 + a], d0 = in[6 + a], d1 = in[9 + a];
+        if (MU == 0) {        // G d = (-i d1, -i d0)
+            h[a] = u0 + sg * timesI(d1);
+            h[3 + a] = u1 + sg * timesI(d0);
+        } else if (MU == 1) { // G d = (-d1, d0)
+            h[a] = u0 + sg * d1;
+            h[3 + a] = u1 - sg * d0;
+        } else if (MU == 2) { // G d = (-i d0, i d1)
+            h[a] = u0 + sg * timesI(d0);
+            h[3 + a] = u1 - sg * timesI(d1);
+        } else {              // G d = d
+            h[a] = u0 - sg * d0;
+            h[3 + a] = u1 - sg * d1;
+        }
+    }
+}
+
+template <int MU, typename R>
+__device__ __forceinline__ void reconstruct_add(R sg, const cx<R> w[6], cx<R> acc[12]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<R> w0 = w[a], w1 = w[3 + a];
+        acc[a] = acc[a] + w0;
+        acc[3 + a] = acc[3 + a] + w1;
+        if (MU == 0) {        // -sg G^+ w = (-sg i w1, -sg i w0)
+            acc[6 + a] = acc[6 + a] - sg * timesI(w1);
+            acc[9 + a] = acc[9 + a] - sg * timesI(w0);
+        } else if (MU == 1) { // (-sg w1, +sg w0)
+            acc[6 + a] = acc[6 + a] - sg * w1;
+            acc[9 + a] = acc[9 + a] + sg * w0;
+        } else if (MU == 2) { // (-sg i w0, +sg i w1)
+            acc[6 + a] = acc[6 + a] - sg * timesI(w0);
+            acc[9 + a] = acc[9 + a] + sg * timesI(w1);
+        } else {              // (-sg w0, -sg w1)
+            acc[6 + a] = acc[6 + a] - sg * w0;
+            acc[9 + a] = acc[9 + a] - sg * w1;
+        }
+    }
+}
+
+// w = U h (FWD) or U^+ h, on the two colour vectors of a half spinor.
+template <bool FWD, typename R>
+__device__ __forceinline__ void su3_mul(const cx<R> U[9], const cx<R> h[6], cx<R> w[6]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<R> acc = {R(0), R(0)};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (FWD)
+                    acc = cmadd(acc, U[a * 3 + b], h[sp * 3 + b]);
+                else
+                    acc = cjmadd(acc, U[b * 3 + a], h[sp * 3 + b]);
+            }
+            w[sp * 3 + a] = acc;
+        }
+}
+
+// ----------------------------------------------------------- hop kernels
+struct HopDev {
+    void* out;
+    const void* in;
+    const void* centre;
+    const char* links_out;   // segments (mu = 0..3) of the output parity
+    const char* links_in;    // segments of the input parity
+    size_t lseg;
+    size_t stride;
+    int nrhs;
+    int nblk;
+    int out_parity;
+    const RhsCoef* coef;
+    const int* active;
+    double* partials;
+};
+
+template <int K> struct HopTraits {
+    static constexpr bool dag = (K == HOP_D5_DAG || K == HOP_SCHUR_A_DAG || K == HOP_SCHUR_B_DAG || K == HOP_BARE_DAG);
+    static constexpr bool preB = (K == HOP_D5 || K == HOP_SCHUR_A || K == HOP_PREP);
+    // epilogue on the hop result: 0 none, 1 B K5^-1, 2 (B K5^-1)^+, 3 B^+
+    static constexpr int epi = (K == HOP_SCHUR_A) ? 1 : (K == HOP_SCHUR_A_DAG) ? 2
+                             : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 3 : 0;
+    // centre term: 0 none, 1 K5, 2 K5^+, 3 identity
+    static constexpr int cen = (K == HOP_D5 || K == HOP_SCHUR_B) ? 1
+                             : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 2 : (K == HOP_PREP) ? 3 : 0;
+    static constexpr double coef = (K == HOP_D5 || K == HOP_D5_DAG) ? -0.5
+                                 : (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG) ? -0.25
+                                 : (K == HOP_PREP) ? 0.5 : 1.0;
+};
+
+template <Prec P, bool DAG, bool PREB, int MU, int DIR>
+__device__ __forceinline__ void hop_dir(cx<typename Real<P>::T> acc[12], const char* lseg, int li, int Vh4,
+                                        const void* in, int Vh, int jn, const Nbr5<typename Real<P>::T>& nb,
+                                        typename Real<P>::T b5, typename Real<P>::T c5) {
+    using R = typename Real<P>::T;
+    cx<R> U[9];
+    Link<P>::load(lseg, Vh4, li, U);
+    cx<R> psi[12];
+    Field<P>::load(in, Vh, jn, psi);
+    if (PREB) {
+        cx<R> cpsi[12];
+        apply_C_lanes<R, false>(nb, psi, cpsi);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) psi[c] = b5 * psi[c] + c5 * cpsi[c];
+    }
+    constexpr R sg = ((DIR > 0) != DAG) ? R(1) : R(-1);
+    cx<R> h[6], w[6];
+    project<MU>(sg, psi, h);
+    su3_mul<(DIR > 0)>(U, h, w);
+    reconstruct_add<MU>(sg, w, acc);
+}
+
+template <Prec P, int K>
+__global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
+    using R = typename Real<P>::T;
+    using TR = HopTraits<K>;
+    const int L5 = g.L5;
+    const int spw = 64 / L5;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int rhs = lb % a.nrhs;
+    const int tile = lb / a.nrhs;
+    if (a.active && !a.active[rhs]) return;   // uniform over the block
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int sw = lane / L5;
+    const int s = lane - sw * L5;
+    const int i = (tile * kWaves + wave) * spw + sw;
+    const bool valid = (sw < spw) && (i < g.Vh4);
+    const int gbase = lane - s;
+
+    const RhsCoef& cf = a.coef[rhs];
+    const R mq = R(cf.mq), b5 = R(cf.b5), c5 = R(cf.c5);
+    Nbr5<R> nb;
+    nb.am1 = (gbase + (s == 0 ? L5 - 1 : s - 1)) << 2;
+    nb.ap1 = (gbase + (s == L5 - 1 ? 0 : s + 1)) << 2;
+    nb.fm1 = (s == 0) ? -mq : R(1);
+    nb.fp1 = (s == L5 - 1) ? -mq : R(1);
+
+    const void* in = at_rhs(a.in, a.stride, rhs);
+    cx<R> res[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) res[c] = {R(0), R(0)};
+
+    if (valid) {
+        // 4D coordinates of the output site
+        uint32_t r = uint32_t(i);
+        uint32_t q = g.fXh.div(r);
+        const int xh = int(r - q * uint32_t(g.Xh));
+        r = q;
+        q = g.fY.div(r);
+        const int y = int(r - q * uint32_t(g.Y));
+        r = q;
+        q = g.fZ.div(r);
+        const int z = int(r - q * uint32_t(g.Z));
+        const int t = int(q);
+        const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+        const int row = i - xh;
+        const int sy = g.Xh, sz = g.Xh * g.Y, st = sz * g.Z;
+        const int n_xp = row + ((x + 1 == g.X ? 0 : x + 1) >> 1);
+        const int n_xm = row + ((x == 0 ? g.X - 1 : x - 1) >> 1);
+        const int n_yp = i + (y == g.Y - 1 ? -(g.Y - 1) * sy : sy);
+        const int n_ym = i + (y == 0 ? (g.Y - 1) * sy : -sy);
+        const int n_zp = i + (z == g.Z - 1 ? -(g.Z - 1) * sz : sz);
+        const int n_zm = i + (z == 0 ? (g.Z - 1) * sz : -sz);
+        const int n_tp = i + (t == g.T - 1 ? -(g.T - 1) * st : st);
+        const int n_tm = i + (t == 0 ? (g.T - 1) * st : -st);
+
+        const char* lo = a.links_out;
+        const char* li = a.links_in;
+        const size_t ls = a.lseg;
+        constexpr bool D = TR::dag, PB = TR::preB;
+        hop_dir<P, D, PB, 0, +1>(res, lo + 0 * ls, i, g.Vh4, in, g.Vh, n_xp * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 0, -1>(res, li + 0 * ls, n_xm, g.Vh4, in, g.Vh, n_xm * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 1, +1>(res, lo + 1 * ls, i, g.Vh4, in, g.Vh, n_yp * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 1, -1>(res, li + 1 * ls, n_ym, g.Vh4, in, g.Vh, n_ym * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 2, +1>(res, lo + 2 * ls, i, g.Vh4, in, g.Vh, n_zp * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 2, -1>(res, li + 2 * ls, n_zm, g.Vh4, in, g.Vh, n_zm * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 3, +1>(res, lo + 3 * ls, i, g.Vh4, in, g.Vh, n_tp * L5 + s, nb, b5, c5);
+        hop_dir<P, D, PB, 3, -1>(res, li + 3 * ls, n_tm, g.Vh4, in, g.Vh, n_tm * L5 + s, nb, b5, c5);
+    }
+
+    // ---- epilogue on the hop result
+    if constexpr (TR::epi == 1 || TR::epi == 2) {
+        // dense B K5^-1 = sum_k m_k C^k (or its adjoint) across the L5 lanes
+        __shared__ cx<R> sh[12 * kBlock];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = res[c];
+        __syncthreads();
+        if (valid) {
+            cx<R> o[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) o[c] = {R(0), R(0)};
+            const int tbase = tid - s;
+            for (int k = 0; k < L5; ++k) {
+                const R mk = R(cf.m[k]);
+                // C^k on P+ reads slice s-k, on P- slice s+k (adjoint: swapped)
+                int su = (TR::epi == 1) ? s - k : s + k;
+                int sd = (TR::epi == 1) ? s + k : s - k;
+                R fu = mk, fd = mk;
+                if (su < 0) { su += L5; fu = -mq * mk; }
+                if (su >= L5) { su -= L5; fu = -mq * mk; }
+                if (sd < 0) { sd += L5; fd = -mq * mk; }
+                if (sd >= L5) { sd -= L5; fd = -mq * mk; }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) o[c] = o[c] + fu * sh[c * kBlock + tbase + su];
+#pragma unroll
+                for (int c = 6; c < 12; ++c) o[c] = o[c] + fd * sh[c * kBlock + tbase + sd];
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) res[c] = o[c];
+        }
+    } else if constexpr (TR::epi == 3) {
+        if (valid) {   // B^+ = b5 + c5 C^+
+            cx<R> cr[12];
+            apply_C_lanes<R, true>(nb, res, cr);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) res[c] = b5 * res[c] + c5 * cr[c];
+        }
+    }
+
+    double n2 = 0.0;
+    if (valid) {
+        const int j = i * L5 + s;
+        const R hc = R(TR::coef);
+        if constexpr (TR::cen != 0) {
+            cx<R> cv[12];
+            Field<P>::load(at_rhs(a.centre, a.stride, rhs), g.Vh, j, cv);
+            if constexpr (TR::cen == 1 || TR::cen == 2) {
+                cx<R> cc[12];
+                apply_C_lanes<R, TR::cen == 2>(nb, cv, cc);
+                const R ka = R(cf.k5[0]), kb = R(cf.k5[1]);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) res[c] = ka * cv[c] + kb * cc[c] + hc * res[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) res[c] = cv[c] + hc * res[c];
+            }
+        } else if constexpr (TR::coef != 1.0) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) res[c] = hc * res[c];
+        }
+        Field<P>::store(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
+        if (a.partials) {
+            R acc = R(0);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc += res[c].re * res[c].re + res[c].im * res[c].im;
+            n2 = double(acc);
+        }
+    }
+    if (a.partials) {
+        // fixed-order reduction: wave (xor butterfly), then the 4 waves
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) n2 += __shfl_xor(n2, off, 64);
+        __shared__ double wsum[kWaves];
+        if (lane == 0) wsum[wave] = n2;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += wsum[w];
+            a.partials[size_t(rhs) * a.nblk + tile] = t;
+        }
+    }
+}
+
+int hop_blocks_per_rhs(const Geo& g) {
+    const int spw = 64 / g.L5;
+    const int sites_per_block = kWaves * spw;
+    return (g.Vh4 + sites_per_block - 1) / sites_per_block;
+}
+
+template <Prec P, int K>
+static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
+    HopDev a;
+    a.out = L.out;
+    a.in = L.in;
+    a.centre = L.centre;
+    const size_t seg = gs.seg_bytes[P];
+    a.lseg = seg;
+    a.links_out = gs.seg[P] + size_t(L.out_parity) * 4 * seg;
+    a.links_in = gs.seg[P] + size_t(1 - L.out_parity) * 4 * seg;
+    a.stride = L.stride;
+    a.nrhs = L.nrhs;
+    a.nblk = hop_blocks_per_rhs(g);
+    a.out_parity = L.out_parity;
+    a.coef = L.coef;
+    a.active = L.active;
+    a.partials = L.partials;
+    L.nblocks_per_rhs = a.nblk;
+    dim3 grid(a.nblk * L.nrhs);
+    hipLaunchKernelGGL((k_hop<P, K>), grid, dim3(kBlock), 0, st, g, a);
+}
+
+template <Prec P>
+static void launch_hop_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
+    switch (L.kind) {
+        case HOP_BARE: launch_hop_t<P, HOP_BARE>(g, gs, L, st); break;
+        case HOP_BARE_DAG: launch_hop_t<P, HOP_BARE_DAG>(g, gs, L, st); break;
+        case HOP_D5: launch_hop_t<P, HOP_D5>(g, gs, L, st); break;
+        case HOP_D5_DAG: launch_hop_t<P, HOP_D5_DAG>(g, gs, L, st); break;
+        case HOP_SCHUR_A: launch_hop_t<P, HOP_SCHUR_A>(g, gs, L, st); break;
+        case HOP_SCHUR_B: launch_hop_t<P, HOP_SCHUR_B>(g, gs, L, st); break;
+        case HOP_SCHUR_A_DAG: launch_hop_t<P, HOP_SCHUR_A_DAG>(g, gs, L, st); break;
+        case HOP_SCHUR_B_DAG: launch_hop_t<P, HOP_SCHUR_B_DAG>(g, gs, L, st); break;
+        case HOP_PREP: launch_hop_t<P, HOP_PREP>(g, gs, L, st); break;
+    }
+}
+
+void launch_hop(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
+    switch (L.prec) {
+        case P64: launch_hop_p<P64>(g, gs, L, st); break;
+        case P32: launch_hop_p<P32>(g, gs, L, st); break;
+        case P16: launch_hop_p<P16>(g, gs, L, st); break;
+    }
+}
+
+// ------------------------------------------------- site-local 5th dimension
+// out = sum_k c_k C^k in (or with C^+), for K5, K5^-1 and B.
+template <Prec P>
+__global__ void __launch_bounds__(kBlock) k_fifth(const Geo g, int kind, int dag, const void* in, void* out,
+                                                   size_t stride, int nrhs, int nblk, const RhsCoef* coef,
+                                                   const int* active) {
+    using R = typename Real<P>::T;
+    const int L5 = g.L5;
+    const int spw = 64 / L5;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int rhs = lb % nrhs;
+    const int tile = lb / nrhs;
+    if (active && !active[rhs]) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int sw = lane / L5;
+    const int s = lane - sw * L5;
+    const int i = (tile * kWaves + wave) * spw + sw;
+    const bool valid = (sw < spw) && (i < g.Vh4);
+    const int j = i * L5 + s;
+    const RhsCoef& cf = coef[rhs];
+    const R mq = R(cf.mq);
+
+    __shared__ cx<R> sh[12 * kBlock];
+    cx<R> v[12];
+    if (valid) Field<P>::load(at_rhs(in, stride, rhs), g.Vh, j, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = valid ? v[c] : cx<R>{R(0), R(0)};
+    __syncthreads();
+    if (!valid) return;
+
+    // K5 = k5[0] + k5[1] C, B = b5 + c5 C, K5^-1 = sum_k kinv[k] C^k
+    double two[2];
+    const double* ck;
+    if (kind == FIFTH_K5) { two[0] = cf.k5[0]; two[1] = cf.k5[1]; ck = two; }
+    else if (kind == FIFTH_B) { two[0] = cf.b5; two[1] = cf.c5; ck = two; }
+    else { ck = cf.kinv; }
+    cx<R> o[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = {R(0), R(0)};
+    const int tbase = tid - s;
+    const int nterms = (kind == FIFTH_K5INV) ? L5 : 2;
+    for (int k = 0; k < nterms; ++k) {
+        const R mk = R(ck[k]);
+        int su = dag ? s + k : s - k;
+        int sd = dag ? s - k : s + k;
+        R fu = mk, fd = mk;
+        // k may reach L5 only when L5 = 1 (then C^1 = -m_q on the single slice)
+        while (su < 0) { su += L5; fu = -mq * fu; }
+        while (su >= L5) { su -= L5; fu = -mq * fu; }
+        while (sd < 0) { sd += L5; fd = -mq * fd; }
+        while (sd >= L5) { sd -= L5; fd = -mq * fd; }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) o[c] = o[c] + fu * sh[c * kBlock + tbase + su];
+#pragma unroll
+        for (int c = 6; c < 12; ++c) o[c] = o[c] + fd * sh[c * kBlock + tbase + sd];
+    }
+    Field<P>::store(at_rhs(out, stride, rhs), g.Vh, j, o);
+}
+
+void launch_fifth(const Geo& g, Prec p, FifthKind kind, int dag, const void* in, void* out, size_t stride,
+                  int nrhs, const RhsCoef* coef, const int* active, hipStream_t st) {
+    const int nblk = hop_blocks_per_rhs(g);
+    dim3 grid(nblk * nrhs);
+    switch (p) {
+        case P64: hipLaunchKernelGGL(k_fifth<P64>, grid, dim3(kBlock), 0, st, g, int(kind), dag, in, out, stride, nrhs, nblk, coef, active); break;
+        case P32: hipLaunchKernelGGL(k_fifth<P32>, grid, dim3(kBlock), 0, st, g, int(kind), dag, in, out, stride, nrhs, nblk, coef, active); break;
+        case P16: hipLaunchKernelGGL(k_fifth<P16>, grid, dim3(kBlock), 0, st, g, int(kind), dag, in, out, stride, nrhs, nblk, coef, active); break;
+    }
+}
+
+}  // namespace mdwf

@@ -1,0 +1,381 @@
+// Internal declarations shared by the HIP translation units of libmdwf.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mdwf {
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+constexpr int kMaxL5 = 32;
+constexpr int kBlock = 256;   // threads per workgroup of the site kernels (4 waves)
+constexpr int kWaves = kBlock / 64;
+
+template <Prec P> struct Real { using T = float; };
+template <> struct Real<P64> { using T = double; };
+
+// ---------------------------------------------------------------- complex
+template <typename R> struct cx {
+    R re, im;
+};
+template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return {a, b}; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> timesI(cx<R> a) { return {-a.im, a.re}; }
+template <typename R> __device__ __forceinline__ cx<R> timesMinusI(cx<R> a) { return {a.im, -a.re}; }
+// a * b
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <typename R> __device__ __forceinline__ cx<R> cmadd(cx<R> acc, cx<R> a, cx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename R> __device__ __forceinline__ cx<R> cjmadd(cx<R> acc, cx<R> a, cx<R> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(-a.im, b.re, acc.im);
+    return acc;
+}
+
+// ------------------------------------------------------ integer division
+// Division by a runtime-invariant divisor with one multiply-high and a shift
+// (Granlund & Montgomery, PLDI 1994, round-up multiplier); exact for
+// dividends below 2^31.
+struct FastDiv {
+    uint32_t d = 1, m = 1, s = 0;
+    FastDiv() = default;
+    explicit FastDiv(uint32_t div) : d(div) {
+        s = 0;
+        while ((uint64_t(1) << s) < div) ++s;
+        m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - div)) / div + 1);
+    }
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+        uint32_t t = __umulhi(n, m);
+#else
+        uint32_t t = uint32_t((uint64_t(n) * m) >> 32);
+#endif
+        return (t + n) >> s;
+    }
+};
+
+// -------------------------------------------------------------- geometry
+struct Geo {
+    int X, Y, Z, T, Xh;
+    int Vh4;   // 4D sites of one parity
+    int L5;
+    int Vh;    // 5D sites of one parity = Vh4 * L5
+    int antiperiodic;
+    FastDiv fXh, fY, fZ;
+};
+
+// Coefficients of one right-hand side (its mass); all fifth-dimension
+// operators are polynomials in C: sum_k c_k C^k.
+struct RhsCoef {
+    double mq, b5, c5;
+    double k5[2];         // K5 = k5[0] + k5[1] C
+    double m[kMaxL5];     // B K5^-1   = sum_k m[k] C^k
+    double kinv[kMaxL5];  // K5^-1     = sum_k kinv[k] C^k
+};
+
+// Bytes of a native half field / link segment.
+__host__ __device__ inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+inline size_t half_field_bytes(Prec p, size_t Vh) {
+    switch (p) {
+        case P64: return align256(192 * Vh);
+        case P32: return align256(96 * Vh);
+        default: return align256(48 * Vh) + align256(4 * Vh);
+    }
+}
+inline size_t link_segment_bytes(Prec p, size_t Vh4) {
+    switch (p) {
+        case P64: return align256(144 * Vh4);
+        case P32: return align256(64 * Vh4) + align256(8 * Vh4);
+        default: return align256(32 * Vh4) + align256(4 * Vh4);
+    }
+}
+__host__ __device__ inline size_t norm_offset(size_t Vh) { return align256(48 * Vh); }  // P16 only
+
+// ------------------------------------------------------- native accesses
+template <Prec P> struct Field;
+
+template <> struct Field<P64> {
+    using R = double;
+    static __device__ __forceinline__ void load(const void* base, int Vh, int j, cx<R> v[12]) {
+        const double2* p = static_cast<const double2*>(base);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 w = p[size_t(k) * Vh + j];
+            v[k] = {w.x, w.y};
+        }
+    }
+    static __device__ __forceinline__ void store(void* base, int Vh, int j, const cx<R> v[12]) {
+        double2* p = static_cast<double2*>(base);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[size_t(k) * Vh + j] = make_double2(v[k].re, v[k].im);
+    }
+};
+
+template <> struct Field<P32> {
+    using R = float;
+    static __device__ __forceinline__ void load(const void* base, int Vh, int j, cx<R> v[12]) {
+        const float4* p = static_cast<const float4*>(base);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            float4 w = p[size_t(k) * Vh + j];
+            v[2 * k] = {w.x, w.y};
+            v[2 * k + 1] = {w.z, w.w};
+        }
+    }
+    static __device__ __forceinline__ void store(void* base, int Vh, int j, const cx<R> v[12]) {
+        float4* p = static_cast<float4*>(base);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            p[size_t(k) * Vh + j] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+};
+
+__device__ __forceinline__ float h2f(uint32_t bits16) {
+    return __half2float(__ushort_as_half(static_cast<unsigned short>(bits16)));
+}
+__device__ __forceinline__ uint32_t f2h(float f) {
+    return static_cast<uint32_t>(__half_as_ushort(__float2half_rn(f)));
+}
+__device__ __forceinline__ void unpack_h2(uint32_t w, float s, cx<float>& c) {
+    c.re = h2f(w & 0xffffu) * s;
+    c.im = h2f(w >> 16) * s;
+}
+__device__ __forceinline__ uint32_t pack_h2(cx<float> c, float inv) {
+    return f2h(c.re * inv) | (f2h(c.im * inv) << 16);
+}
+
+template <> struct Field<P16> {
+    using R = float;
+    static __device__ __forceinline__ void load(const void* base, int Vh, int j, cx<R> v[12]) {
+        const uint4* p = static_cast<const uint4*>(base);
+        const float* nrm = reinterpret_cast<const float*>(static_cast<const char*>(base) + norm_offset(Vh));
+        const float s = nrm[j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 w = p[size_t(k) * Vh + j];
+            unpack_h2(w.x, s, v[4 * k]);
+            unpack_h2(w.y, s, v[4 * k + 1]);
+            unpack_h2(w.z, s, v[4 * k + 2]);
+            unpack_h2(w.w, s, v[4 * k + 3]);
+        }
+    }
+    // Stores v / norm in binary16 (round to nearest even) with
+    // norm = max |re|, |im| over the site; v is replaced by what was stored.
+    static __device__ __forceinline__ void store(void* base, int Vh, int j, cx<R> v[12]) {
+        float n = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) n = fmaxf(n, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float inv = n > 0.f ? 1.0f / n : 0.f;
+        uint4* p = static_cast<uint4*>(base);
+        float* nrm = reinterpret_cast<float*>(static_cast<char*>(base) + norm_offset(Vh));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint4 w;
+            w.x = pack_h2(v[4 * k], inv);
+            w.y = pack_h2(v[4 * k + 1], inv);
+            w.z = pack_h2(v[4 * k + 2], inv);
+            w.w = pack_h2(v[4 * k + 3], inv);
+            p[size_t(k) * Vh + j] = w;
+            unpack_h2(w.x, n, v[4 * k]);
+            unpack_h2(w.y, n, v[4 * k + 1]);
+            unpack_h2(w.z, n, v[4 * k + 2]);
+            unpack_h2(w.w, n, v[4 * k + 3]);
+        }
+        nrm[j] = n;
+    }
+};
+
+// Links: one segment per (parity, mu) holding the links that live on the
+// sites of that parity; 3x3 complex, element a*3+b.
+template <Prec P> struct Link;
+template <> struct Link<P64> {
+    using R = double;
+    static __device__ __forceinline__ void load(const char* seg, int Vh4, int i, cx<R> u[9]) {
+        const double2* p = reinterpret_cast<const double2*>(seg);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 w = p[size_t(k) * Vh4 + i];
+            u[k] = {w.x, w.y};
+        }
+    }
+    static __device__ __forceinline__ void store(char* seg, int Vh4, int i, const cx<double> u[9]) {
+        double2* p = reinterpret_cast<double2*>(seg);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) p[size_t(k) * Vh4 + i] = make_double2(u[k].re, u[k].im);
+    }
+};
+template <> struct Link<P32> {
+    using R = float;
+    static __device__ __forceinline__ void load(const char* seg, int Vh4, int i, cx<R> u[9]) {
+        const float4* p = reinterpret_cast<const float4*>(seg);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float4 w = p[size_t(k) * Vh4 + i];
+            u[2 * k] = {w.x, w.y};
+            u[2 * k + 1] = {w.z, w.w};
+        }
+        const float2* q = reinterpret_cast<const float2*>(seg + align256(64 * size_t(Vh4)));
+        float2 w = q[i];
+        u[8] = {w.x, w.y};
+    }
+    static __device__ __forceinline__ void store(char* seg, int Vh4, int i, const cx<double> u[9]) {
+        float4* p = reinterpret_cast<float4*>(seg);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            p[size_t(k) * Vh4 + i] = make_float4(float(u[2 * k].re), float(u[2 * k].im),
+                                                 float(u[2 * k + 1].re), float(u[2 * k + 1].im));
+        float2* q = reinterpret_cast<float2*>(seg + align256(64 * size_t(Vh4)));
+        q[i] = make_float2(float(u[8].re), float(u[8].im));
+    }
+};
+template <> struct Link<P16> {
+    using R = float;
+    static __device__ __forceinline__ void load(const char* seg, int Vh4, int i, cx<R> u[9]) {
+        const uint4* p = reinterpret_cast<const uint4*>(seg);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            uint4 w = p[size_t(k) * Vh4 + i];
+            unpack_h2(w.x, 1.f, u[4 * k]);
+            unpack_h2(w.y, 1.f, u[4 * k + 1]);
+            unpack_h2(w.z, 1.f, u[4 * k + 2]);
+            unpack_h2(w.w, 1.f, u[4 * k + 3]);
+        }
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(seg + align256(32 * size_t(Vh4)));
+        unpack_h2(q[i], 1.f, u[8]);
+    }
+    static __device__ __forceinline__ void store(char* seg, int Vh4, int i, const cx<double> u[9]) {
+        uint4* p = reinterpret_cast<uint4*>(seg);
+        cx<float> f[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = {float(u[k].re), float(u[k].im)};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            uint4 w;
+            w.x = pack_h2(f[4 * k], 1.f);
+            w.y = pack_h2(f[4 * k + 1], 1.f);
+            w.z = pack_h2(f[4 * k + 2], 1.f);
+            w.w = pack_h2(f[4 * k + 3], 1.f);
+            p[size_t(k) * Vh4 + i] = w;
+        }
+        uint32_t* q = reinterpret_cast<uint32_t*>(seg + align256(32 * size_t(Vh4)));
+        q[i] = pack_h2(f[8], 1.f);
+    }
+};
+
+// ------------------------------------------------------------- workgroups
+// Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that each
+// XCD works on one contiguous range of logical tiles, keeping neighbouring
+// tiles (stencil halo) and the right-hand sides of one tile (shared links) in
+// the same L2.
+__device__ __forceinline__ int xcd_logical_block(int hw, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = hw & 7, slot = hw >> 3;
+    return x * q + (x < r ? x : r) + slot;
+}
+
+// Fields of several right-hand sides are stored one after another with a
+// fixed byte stride.
+__device__ __forceinline__ const void* at_rhs(const void* base, size_t stride, int r) {
+    return static_cast<const char*>(base) + stride * size_t(r);
+}
+__device__ __forceinline__ void* at_rhs(void* base, size_t stride, int r) {
+    return static_cast<char*>(base) + stride * size_t(r);
+}
+
+// ---------------------------------------------------- host-side launchers
+struct GaugeSet {
+    char* seg[3] = {nullptr, nullptr, nullptr};   // per precision: 8 segments (parity*4+mu)
+    size_t seg_bytes[3] = {0, 0, 0};
+};
+
+enum HopKind {
+    HOP_BARE = 0,    // out = Dslash in
+    HOP_D5,          // out = K5 c - 1/2 Dslash B in
+    HOP_D5_DAG,      // out = K5^+ c - 1/2 B^+ Dslash^+ in
+    HOP_SCHUR_A,     // out = B K5^-1 Dslash B in
+    HOP_SCHUR_B,     // out = K5 c - 1/4 Dslash in
+    HOP_SCHUR_A_DAG, // out = (B K5^-1)^+ Dslash^+ in
+    HOP_SCHUR_B_DAG, // out = K5^+ c - 1/4 B^+ Dslash^+ in
+    HOP_PREP,        // out = c + 1/2 Dslash B in
+    HOP_BARE_DAG     // out = Dslash^+ in
+};
+
+struct HopLaunch {
+    HopKind kind;
+    Prec prec;
+    int out_parity;
+    void* out;
+    const void* in;       // neighbour field (parity 1 - out_parity)
+    const void* centre;   // field at the output parity (K5 / identity term)
+    size_t stride;        // bytes between right-hand sides of in/out/centre
+    int nrhs;
+    const RhsCoef* coef;  // device, [nrhs]
+    const int* active;    // device, [nrhs] or nullptr
+    double* partials;     // device, [nrhs][nblocks] when a norm is wanted, else nullptr
+    int nblocks_per_rhs;  // filled by the launcher
+};
+
+enum FifthKind { FIFTH_K5 = 0, FIFTH_K5INV, FIFTH_B };
+
+void launch_hop(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st);
+void launch_fifth(const Geo& g, Prec p, FifthKind kind, int dag, const void* in, void* out, size_t stride,
+                  int nrhs, const RhsCoef* coef, const int* active, hipStream_t st);
+int hop_blocks_per_rhs(const Geo& g);
+
+// BLAS and conversions (blas.hip)
+void launch_gauge_layout(const Geo& g, const double* canon, GaugeSet& gs, hipStream_t st);
+void launch_pack(const Geo& g, Prec p, int kind, const double* canon, void* native, hipStream_t st);
+void launch_unpack(const Geo& g, Prec p, int kind, const void* native, double* canon, hipStream_t st);
+// one parity: full = 1 reads/writes the canonical full field, 0 the parity-compressed half
+void launch_pack_parity(const Geo& g, Prec p, int full, int par, const double* canon, void* dst, hipStream_t st);
+void launch_unpack_parity(const Geo& g, Prec p, int full, int par, const void* src, double* canon, hipStream_t st);
+void launch_convert(const Geo& g, Prec pin, Prec pout, const void* in, void* out, size_t sin, size_t sout,
+                    int nrhs, const int* active, hipStream_t st);
+// z = a*x + b*y per RHS, scalars from host; optional norm partials of z
+void launch_axpby(const Geo& g, Prec p, double a, const void* x, double b, const void* y, void* z, size_t stride,
+                  int nrhs, const int* active, double* partials, hipStream_t st);
+void launch_norm2(const Geo& g, Prec p, const void* x, size_t stride, int nrhs, const int* active,
+                  double* partials, hipStream_t st);
+// x(px) += alpha[r] * p(pi); r(pi) -= alpha[r] * q(pi); partials <- |r|^2
+struct CGScal;
+void launch_cg_xr(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* r, const void* p, const void* q,
+                  size_t si, int nrhs, const int* active, const CGScal* sc, double* partials, hipStream_t st);
+// p = s + beta[r] p
+void launch_cg_p(const Geo& g, Prec pi, void* p, const void* s, size_t si, int nrhs, const int* active,
+                 const CGScal* sc, hipStream_t st);
+// x_hi(P64) += x_lo(px); x_lo = 0
+void launch_flush(const Geo& g, Prec px, void* xhi, size_t shi, void* xlo, size_t slo, int nrhs,
+                  const int* active, hipStream_t st);
+int blas_blocks_per_rhs(const Geo& g);
+
+// Per-RHS scalar state of the CG recursion, in device memory.
+struct CGScal {
+    double gamma;   // ||s||^2
+    double delta;   // ||q||^2
+    double alpha, beta;
+    double rr;      // ||r||^2 (iterated)
+    int bad;        // NaN/Inf or breakdown seen
+    int pad;
+};
+enum ScalOp { SC_ALPHA = 0, SC_BETA, SC_SET_GAMMA, SC_RR, SC_SUM };
+// Reduce partials per RHS in a fixed order and update the scalars.
+void launch_scalars(ScalOp op, const double* partials, int nblk, int nrhs, const int* active, CGScal* sc,
+                    double* out_sum, hipStream_t st);
+
+}  // namespace mdwf

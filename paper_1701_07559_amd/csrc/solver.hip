@@ -1,0 +1,436 @@
+// Solve D5 x = b for several right-hand sides at once (arXiv:1701.07559,
+// Sec. VII: even-odd preconditioned Moebius solve, "double-half" mixed
+// precision).
+//
+//   b'_e = b_e + 1/2 D_eo B K5^-1 b_o
+//   CG on the normal equations of S x_e = b'_e in least-squares form:
+//     q = S p, alpha = |s|^2/|q|^2, x += alpha p, r -= alpha q,
+//     s = S^+ r, beta = |s_new|^2/|s|^2, p = s + beta p
+//   x_o = K5^-1 (b_o + 1/2 D_oe B x_e)
+// The recursion tracks r = b' - S x_e, whose norm equals the full residual
+// |b - D5 x| after reconstruction, so it stops on the quantity that matters;
+// every stop is confirmed by an FP64 true residual of the full system.
+//
+// Mixed precision: the inner vectors r, p, s, q and the hop temporary live in
+// FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32; the
+// FP64 solution x_hi, the prepared source and all reductions stay FP64.  When
+// the iterated |r| falls below delta times its value at the last update (or
+// reaches the target) the solver flushes x_lo into x_hi, recomputes
+// r = b' - S x_hi with the FP64 operator and continues from it, keeping the
+// search direction p.
+//
+// Right-hand sides (with their own masses) share every launch; a per-RHS
+// active flag in device memory lets finished ones drop out without
+// re-capturing the iteration graph.  The CG scalars live in device memory; the
+// host reads |r|^2 one iteration late so the GPU never waits for it.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace mdwf;
+
+namespace {
+
+struct Solver {
+    mdwf_ctx* c;
+    Geo g;
+    hipStream_t st;
+    int n;
+    Prec pi, px;
+    bool mixed;
+    size_t H64, Hi, Hx;
+    int nbh, nbb;
+    char *be, *bo, *bp, *xh, *rh, *t64, *ye, *xo;
+    char *r, *p, *s, *q, *t, *xl;
+    RhsCoef* coef;
+    CGScal* sc;
+    int* act;       // iterate on these
+    int* msk;       // scratch mask for updates / checks
+    double* part;
+    double* sums;
+    // pinned host mirrors
+    CGScal* hsc[2];
+    double* hsum;
+    int* hmask;
+    hipEvent_t ev[2];
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    mdwf_status err = MDWF_OK;
+
+    bool ok(mdwf_status s) {
+        if (s != MDWF_OK && err == MDWF_OK) err = s;
+        return err == MDWF_OK;
+    }
+    bool hipok(hipError_t e, const char* what) { return ok(hip_check(c, e, what)); }
+
+    void upload_mask(int* dst, const std::vector<int>& m) {
+        for (int k = 0; k < n; ++k) hmask[k] = m[k];
+        hipok(hipMemcpyAsync(dst, hmask, sizeof(int) * n, hipMemcpyHostToDevice, st), "mask upload");
+        // the pinned staging is reused: wait until the copy has read it
+        hipok(hipStreamSynchronize(st), "mask upload");
+    }
+
+    // q = S x (prec p) for masked RHS; tmp is an odd half-field array
+    void schur(Prec pr, const void* in, void* out, void* tmp, size_t stride, const int* mask, bool dag,
+               double* partials) {
+        HopLaunch L{};
+        L.prec = pr;
+        L.stride = stride;
+        L.nrhs = n;
+        L.coef = coef;
+        L.active = mask;
+        L.kind = dag ? HOP_SCHUR_A_DAG : HOP_SCHUR_A;
+        L.out_parity = 1;
+        L.out = tmp;
+        L.in = in;
+        L.partials = nullptr;
+        launch_hop(g, c->gs, L, st);
+        L.kind = dag ? HOP_SCHUR_B_DAG : HOP_SCHUR_B;
+        L.out_parity = 0;
+        L.out = out;
+        L.in = tmp;
+        L.centre = in;
+        L.partials = partials;
+        launch_hop(g, c->gs, L, st);
+    }
+
+    // per-RHS sum of partials (nblk per RHS) -> host vector
+    std::vector<double> fetch_sums(int nblk, const int* mask) {
+        launch_scalars(SC_SUM, part, nblk, n, mask, sc, sums, st);
+        hipok(hipMemcpyAsync(hsum, sums, sizeof(double) * n, hipMemcpyDeviceToHost, st), "sum D2H");
+        hipok(hipStreamSynchronize(st), "sum sync");
+        return std::vector<double>(hsum, hsum + n);
+    }
+
+    std::vector<double> norm2(Prec pr, const void* x, size_t stride, const int* mask) {
+        hipok(hipMemsetAsync(sums, 0, sizeof(double) * n, st), "memset");
+        launch_norm2(g, pr, x, stride, n, mask, part, st);
+        return fetch_sums(nbb, mask);
+    }
+
+    void one_iteration() {
+        void* xcur = mixed ? static_cast<void*>(xl) : static_cast<void*>(xh);
+        const size_t sxc = mixed ? Hx : H64;
+        schur(pi, p, q, t, Hi, act, false, part);
+        launch_scalars(SC_ALPHA, part, nbh, n, act, sc, nullptr, st);
+        launch_cg_xr(g, mixed ? px : P64, pi, xcur, sxc, r, p, q, Hi, n, act, sc, part, st);
+        launch_scalars(SC_RR, part, nbb, n, act, sc, nullptr, st);
+        schur(pi, r, s, t, Hi, act, true, part);
+        launch_scalars(SC_BETA, part, nbh, n, act, sc, nullptr, st);
+        launch_cg_p(g, pi, p, s, Hi, n, act, sc, st);
+    }
+};
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_dev, double* const* x_dev,
+                                const double* mq, const mdwf_solver_opts* o_in, mdwf_solve_info* info, hipStream_t st) {
+    const double t_start = now();
+    if (nrhs < 1 || !b_dev || !x_dev) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
+    for (int k = 0; k < nrhs; ++k)
+        if (!b_dev[k] || !x_dev[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+    mdwf_solver_opts o;
+    mdwf_default_opts(&o);
+    if (o_in) o = *o_in;
+    if (!(o.tol > 0.0) || o.max_iter < 1 || (o.inner != MDWF_F64 && o.inner != MDWF_F32 && o.inner != MDWF_F16) ||
+        !(o.delta > 0.0 && o.delta < 1.0))
+        return fail(c, MDWF_ERR_ARG, "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1)");
+    if (o.check_every < 1) o.check_every = 1;
+    std::vector<double> masses(nrhs, c->act.mq);
+    if (mq)
+        for (int k = 0; k < nrhs; ++k) {
+            if (!(mq[k] >= 0.0 && mq[k] <= 1.0)) return fail(c, MDWF_ERR_ARG, "need 0 <= mq <= 1");
+            masses[k] = mq[k];
+        }
+
+    Solver S;
+    S.c = c;
+    S.g = c->geo;
+    S.st = st;
+    S.n = nrhs;
+    S.pi = Prec(o.inner);
+    S.mixed = S.pi != P64;
+    S.px = S.mixed ? P32 : P64;
+    const Geo& g = S.g;
+    S.H64 = half_field_bytes(P64, g.Vh);
+    S.Hi = half_field_bytes(S.pi, g.Vh);
+    S.Hx = half_field_bytes(S.px, g.Vh);
+    S.nbh = hop_blocks_per_rhs(g);
+    S.nbb = blas_blocks_per_rhs(g);
+    const int n = nrhs;
+
+    mdwf_status s = MDWF_OK;
+#define ALLOC(var, name, bytes)                                       \
+    S.var = static_cast<decltype(S.var)>(buf(c, name, (bytes), &s)); \
+    if (!S.var) return s;
+    ALLOC(be, "sv_be", S.H64 * n);
+    ALLOC(bo, "sv_bo", S.H64 * n);
+    ALLOC(bp, "sv_bp", S.H64 * n);
+    ALLOC(xh, "sv_xh", S.H64 * n);
+    ALLOC(rh, "sv_rh", S.H64 * n);
+    ALLOC(t64, "sv_t64", S.H64 * n);
+    ALLOC(ye, "sv_ye", S.H64 * n);
+    ALLOC(xo, "sv_xo", S.H64 * n);
+    if (S.mixed) {
+        ALLOC(r, "sv_r", S.Hi * n);
+        ALLOC(p, "sv_p", S.Hi * n);
+        ALLOC(s, "sv_s", S.Hi * n);
+        ALLOC(q, "sv_q", S.Hi * n);
+        ALLOC(t, "sv_t", S.Hi * n);
+        ALLOC(xl, "sv_xl", S.Hx * n);
+    } else {
+        ALLOC(r, "sv_r64", S.H64 * n);
+        ALLOC(p, "sv_p64", S.H64 * n);
+        ALLOC(s, "sv_s64", S.H64 * n);
+        ALLOC(q, "sv_q64", S.H64 * n);
+        S.t = S.t64;
+        S.xl = nullptr;
+    }
+    ALLOC(coef, "sv_coef", sizeof(RhsCoef) * n);
+    ALLOC(sc, "sv_scal", sizeof(CGScal) * n);
+    ALLOC(act, "sv_act", sizeof(int) * n);
+    ALLOC(msk, "sv_msk", sizeof(int) * n);
+    ALLOC(part, "sv_part", sizeof(double) * n * (S.nbh > S.nbb ? S.nbh : S.nbb));
+    ALLOC(sums, "sv_sums", sizeof(double) * n);
+#undef ALLOC
+    const size_t pin_bytes = 2 * sizeof(CGScal) * n + sizeof(double) * n + sizeof(int) * n + sizeof(RhsCoef) * n + 64;
+    char* hp = static_cast<char*>(pinned(c, pin_bytes, &s));
+    if (!hp) return s;
+    S.hsc[0] = reinterpret_cast<CGScal*>(hp);
+    S.hsc[1] = S.hsc[0] + n;
+    S.hsum = reinterpret_cast<double*>(S.hsc[1] + n);
+    S.hmask = reinterpret_cast<int*>(S.hsum + n);
+    RhsCoef* hcoef = reinterpret_cast<RhsCoef*>(S.hmask + n);
+    for (int k = 0; k < n; ++k) hcoef[k] = make_coef(c->act, masses[k]);
+    if (!S.hipok(hipMemcpyAsync(S.coef, hcoef, sizeof(RhsCoef) * n, hipMemcpyHostToDevice, st), "coef upload"))
+        return S.err;
+    if (!S.hipok(hipMemsetAsync(S.sc, 0, sizeof(CGScal) * n, st), "memset")) return S.err;
+    for (int e = 0; e < 2; ++e)
+        if (!S.hipok(hipEventCreateWithFlags(&S.ev[e], hipEventDisableTiming), "event")) return S.err;
+
+    std::vector<int> active(n, 1), done(n, 0), iters(n, 0), updates(n, 0), restarts(n, 0), stopped(n, 0);
+    std::vector<double> true_res(n, -1.0), bnorm(n, 0.0), rmax(n, 0.0);
+    S.upload_mask(S.act, active);
+
+    // ---- pack b, source preparation
+    for (int k = 0; k < n; ++k) {
+        launch_pack_parity(g, P64, 1, 0, b_dev[k], S.be + S.H64 * k, st);
+        launch_pack_parity(g, P64, 1, 1, b_dev[k], S.bo + S.H64 * k, st);
+    }
+    {
+        auto ne = S.norm2(P64, S.be, S.H64, S.act);
+        auto no = S.norm2(P64, S.bo, S.H64, S.act);
+        for (int k = 0; k < n; ++k) bnorm[k] = std::sqrt(ne[k] + no[k]);
+    }
+    launch_fifth(g, P64, FIFTH_K5INV, 0, S.bo, S.t64, S.H64, n, S.coef, S.act, st);
+    {
+        HopLaunch L{};
+        L.kind = HOP_PREP; L.prec = P64; L.out_parity = 0; L.out = S.bp; L.in = S.t64; L.centre = S.be;
+        L.stride = S.H64; L.nrhs = n; L.coef = S.coef; L.active = S.act;
+        launch_hop(g, c->gs, L, st);
+    }
+    S.hipok(hipMemsetAsync(S.xh, 0, S.H64 * n, st), "memset");
+    if (S.mixed) S.hipok(hipMemsetAsync(S.xl, 0, S.Hx * n, st), "memset");
+    for (int k = 0; k < n; ++k) {
+        if (bnorm[k] == 0.0) {   // b = 0: x = 0 exactly
+            active[k] = 0;
+            done[k] = 1;
+            true_res[k] = 0.0;
+        }
+        if (!std::isfinite(bnorm[k])) {
+            active[k] = 0;
+            stopped[k] = 2;
+        }
+    }
+    S.upload_mask(S.act, active);
+
+    // Reliable update / restart for the RHS in `upd`: r_hi = b' - S x_hi (FP64),
+    // then (if still running) r = r_hi in the inner precision, s = S^+ r,
+    // gamma = |s|^2, and p = s when `restart_p`.
+    auto refresh = [&](const std::vector<int>& upd, const std::vector<int>& restart_p) {
+        S.upload_mask(S.msk, upd);
+        if (S.mixed) launch_flush(g, S.px, S.xh, S.H64, S.xl, S.Hx, n, S.msk, st);
+        S.schur(P64, S.xh, S.rh, S.t64, S.H64, S.msk, false, nullptr);
+        launch_axpby(g, P64, 1.0, S.bp, -1.0, S.rh, S.rh, S.H64, n, S.msk, S.part, st);
+        auto rr = S.fetch_sums(S.nbb, S.msk);
+        launch_convert(g, P64, S.pi, S.rh, S.r, S.H64, S.Hi, n, S.msk, st);
+        S.schur(S.pi, S.r, S.s, S.t, S.Hi, S.msk, true, S.part);
+        launch_scalars(SC_SET_GAMMA, S.part, S.nbh, n, S.msk, S.sc, nullptr, st);
+        std::vector<int> rp(n, 0);
+        bool any_rp = false;
+        for (int k = 0; k < n; ++k) {
+            if (!upd[k]) continue;
+            rmax[k] = std::sqrt(rr[k]);
+            if (restart_p[k]) { rp[k] = 1; any_rp = true; }
+        }
+        if (any_rp) {
+            S.upload_mask(S.msk, rp);
+            launch_convert(g, S.pi, S.pi, S.s, S.p, S.Hi, S.Hi, n, S.msk, st);
+        }
+        return rr;
+    };
+
+    // FP64 true residual |b - D5 x| / |b| of the RHS in `chk`; leaves x_o in xo.
+    auto true_residual = [&](const std::vector<int>& chk) {
+        S.upload_mask(S.msk, chk);
+        HopLaunch L{};
+        L.prec = P64; L.stride = S.H64; L.nrhs = n; L.coef = S.coef; L.active = S.msk;
+        L.kind = HOP_PREP; L.out_parity = 1; L.out = S.t64; L.in = S.xh; L.centre = S.bo;
+        launch_hop(g, c->gs, L, st);
+        launch_fifth(g, P64, FIFTH_K5INV, 0, S.t64, S.xo, S.H64, n, S.coef, S.msk, st);
+        L.kind = HOP_D5; L.out_parity = 0; L.out = S.ye; L.in = S.xo; L.centre = S.xh;
+        launch_hop(g, c->gs, L, st);
+        L.kind = HOP_D5; L.out_parity = 1; L.out = S.t64; L.in = S.xh; L.centre = S.xo;
+        launch_hop(g, c->gs, L, st);
+        launch_axpby(g, P64, 1.0, S.be, -1.0, S.ye, S.ye, S.H64, n, S.msk, S.part, st);
+        auto se = S.fetch_sums(S.nbb, S.msk);
+        launch_axpby(g, P64, 1.0, S.bo, -1.0, S.t64, S.t64, S.H64, n, S.msk, S.part, st);
+        auto so = S.fetch_sums(S.nbb, S.msk);
+        std::vector<double> tr(n, 0.0);
+        for (int k = 0; k < n; ++k)
+            if (chk[k]) tr[k] = bnorm[k] > 0.0 ? std::sqrt(se[k] + so[k]) / bnorm[k] : 0.0;
+        return tr;
+    };
+
+    // initial residual and direction (x = 0, so r = b')
+    {
+        std::vector<int> all(active), rp(active);
+        refresh(all, rp);
+    }
+    if (S.err) return S.err;
+
+    // optional graph of one iteration
+    bool use_graph = o.use_graph != 0;
+    if (use_graph) {
+        if (!S.hipok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "capture")) return S.err;
+        S.one_iteration();
+        hipError_t e = hipStreamEndCapture(st, &S.graph);
+        if (!S.hipok(e, "capture end")) return S.err;
+        if (!S.hipok(hipGraphInstantiate(&S.gexec, S.graph, nullptr, nullptr, 0), "graph instantiate")) return S.err;
+    }
+
+    const double tgt = 0.5 * o.tol;
+    int it = 0;
+    bool pending = false;
+    int pend_slot = 0;
+    auto any_active = [&]() {
+        for (int k = 0; k < n; ++k)
+            if (active[k]) return true;
+        return false;
+    };
+    while (any_active() && S.err == MDWF_OK) {
+        if (use_graph) S.hipok(hipGraphLaunch(S.gexec, st), "graph launch");
+        else S.one_iteration();
+        ++it;
+        for (int k = 0; k < n; ++k)
+            if (active[k]) ++iters[k];
+        const bool check = (it % o.check_every) == 0;
+        int slot = it & 1;
+        if (check) {
+            S.hipok(hipMemcpyAsync(S.hsc[slot], S.sc, sizeof(CGScal) * n, hipMemcpyDeviceToHost, st), "scal D2H");
+            S.hipok(hipEventRecord(S.ev[slot], st), "event");
+        }
+        // examine the previous check while this iteration runs
+        if (!pending) {
+            if (check) { pending = true; pend_slot = slot; }
+            continue;
+        }
+        S.hipok(hipEventSynchronize(S.ev[pend_slot]), "event sync");
+        const CGScal* h = S.hsc[pend_slot];
+        pending = check;
+        pend_slot = slot;
+        std::vector<int> upd(n, 0), rp(n, 0);
+        bool any = false;
+        for (int k = 0; k < n; ++k) {
+            if (!active[k]) continue;
+            if (h[k].bad || !std::isfinite(h[k].rr)) {
+                stopped[k] = 2;
+                upd[k] = 1;
+                any = true;
+                continue;
+            }
+            const double rn = std::sqrt(h[k].rr);
+            if (rn <= tgt * bnorm[k] || iters[k] >= o.max_iter) { upd[k] = 1; any = true; }
+            else if (S.mixed && rn < o.delta * rmax[k]) { upd[k] = 1; any = true; }
+        }
+        if (!any) continue;
+        // act on the current state (includes the iteration just enqueued)
+        pending = false;
+        S.hipok(hipStreamSynchronize(st), "sync");
+        auto rr = refresh(upd, rp);   // keeps p for now; restarts handled below
+        std::vector<int> chk(n, 0);
+        bool any_chk = false;
+        for (int k = 0; k < n; ++k) {
+            if (!upd[k]) continue;
+            if (S.mixed) ++updates[k];
+            if (std::sqrt(rr[k]) <= tgt * bnorm[k] || iters[k] >= o.max_iter || stopped[k] == 2) {
+                chk[k] = 1;
+                any_chk = true;
+            }
+        }
+        if (any_chk) {
+            auto tr = true_residual(chk);
+            std::vector<int> again(n, 0), again_rp(n, 0);
+            bool any_again = false;
+            for (int k = 0; k < n; ++k) {
+                if (!chk[k]) continue;
+                true_res[k] = tr[k];
+                if (tr[k] <= o.tol) { done[k] = 1; active[k] = 0; }
+                else if (iters[k] >= o.max_iter || stopped[k] == 2) { active[k] = 0; if (!stopped[k]) stopped[k] = 1; }
+                else { ++restarts[k]; again[k] = 1; again_rp[k] = 1; any_again = true; }
+            }
+            if (any_again) refresh(again, again_rp);   // restart p = s from the true residual
+            S.upload_mask(S.act, active);
+        }
+    }
+    if (S.err) return S.err;
+
+    // reconstruct every RHS and write x
+    {
+        std::vector<int> all(n, 1);
+        auto tr = true_residual(all);
+        for (int k = 0; k < n; ++k) {
+            true_res[k] = tr[k];
+            launch_unpack_parity(g, P64, 1, 0, S.xh + S.H64 * k, x_dev[k], st);
+            launch_unpack_parity(g, P64, 1, 1, S.xo + S.H64 * k, x_dev[k], st);
+        }
+        S.hipok(hipStreamSynchronize(st), "final sync");
+    }
+    if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
+    if (S.graph) (void)hipGraphDestroy(S.graph);
+    for (int e = 0; e < 2; ++e) (void)hipEventDestroy(S.ev[e]);
+    if (S.err) return S.err;
+
+    const double secs = now() - t_start;
+    mdwf_status result = MDWF_OK;
+    // model counts per RHS
+    const double bsI = spinor_site_bytes(S.pi), bsX = spinor_site_bytes(S.px), bs64 = spinor_site_bytes(P64);
+    const double blI = link_site_bytes(S.pi, g.L5), bl64 = link_site_bytes(P64, g.L5);
+    const double it_bytes = g.Vh * (17 * bsI + 2 * bsX + 4 * blI);
+    const double it_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 5 * 48.0);
+    const double up_bytes = g.Vh * (5 * bs64 + 2 * bl64 + 3 * bs64 + bs64 + bsI + 5 * bsI + 2 * blI + 2 * bs64 + 2 * bsX);
+    const double up_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 3 * 48.0);
+    for (int k = 0; k < n; ++k) {
+        if (stopped[k] == 2) result = MDWF_ERR_NUMERIC;
+        else if (!done[k] && result == MDWF_OK) result = MDWF_ERR_NOCONV;
+        if (info) {
+            info[k].iters = iters[k];
+            info[k].reliable_updates = updates[k];
+            info[k].restarts = restarts[k];
+            info[k].true_resid = true_res[k];
+            info[k].seconds = secs;
+            info[k].model_bytes = iters[k] * it_bytes + (updates[k] + restarts[k] + 1) * up_bytes;
+            info[k].model_flops = iters[k] * it_flops + (updates[k] + restarts[k] + 1) * up_flops;
+        }
+    }
+    if (result == MDWF_ERR_NOCONV) fail(c, result, "solver reached max_iter before the target residual");
+    if (result == MDWF_ERR_NUMERIC) fail(c, result, "non-finite value or breakdown in the CG recursion");
+    return result;
+}

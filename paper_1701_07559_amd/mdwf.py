@@ -1,0 +1,243 @@
+"""ctypes binding of libmdwf (include/mdwf.h), argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: all work runs in the HIP library.  Device pointers are
+plain integers (e.g. ``torch.Tensor.data_ptr()``), streams are HIP stream
+handles as integers (``torch.cuda.current_stream().cuda_stream``) or None.
+
+Importing this module loads ``libmdwf.so`` from the package directory and
+raises if it is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdwf.so")
+
+MDWF_OK, MDWF_ERR_ARG, MDWF_ERR_STATE, MDWF_ERR_OOM, MDWF_ERR_HIP, MDWF_ERR_NOCONV, MDWF_ERR_NUMERIC = range(7)
+STATUS_NAMES = ["OK", "ERR_ARG", "ERR_STATE", "ERR_OOM", "ERR_HIP", "ERR_NOCONV", "ERR_NUMERIC"]
+MDWF_F64, MDWF_F32, MDWF_F16 = 0, 1, 2
+MDWF_FULL, MDWF_HALF_EVEN, MDWF_HALF_ODD = 0, 1, 2
+(MDWF_OP_D5, MDWF_OP_D5_DAG, MDWF_OP_SCHUR, MDWF_OP_SCHUR_DAG, MDWF_OP_HOP_EO, MDWF_OP_HOP_OE,
+ MDWF_OP_K5, MDWF_OP_K5INV, MDWF_OP_HOP_EO_DAG, MDWF_OP_HOP_OE_DAG, MDWF_OP_K5_DAG, MDWF_OP_K5INV_DAG,
+ MDWF_OP_B, MDWF_OP_B_DAG) = range(14)
+
+# field kinds (in, out) of each operator
+OP_KINDS = {
+    MDWF_OP_D5: (MDWF_FULL, MDWF_FULL), MDWF_OP_D5_DAG: (MDWF_FULL, MDWF_FULL),
+    MDWF_OP_SCHUR: (MDWF_HALF_EVEN, MDWF_HALF_EVEN), MDWF_OP_SCHUR_DAG: (MDWF_HALF_EVEN, MDWF_HALF_EVEN),
+    MDWF_OP_HOP_EO: (MDWF_HALF_ODD, MDWF_HALF_EVEN), MDWF_OP_HOP_OE: (MDWF_HALF_EVEN, MDWF_HALF_ODD),
+    MDWF_OP_HOP_EO_DAG: (MDWF_HALF_ODD, MDWF_HALF_EVEN), MDWF_OP_HOP_OE_DAG: (MDWF_HALF_EVEN, MDWF_HALF_ODD),
+    MDWF_OP_K5: (MDWF_FULL, MDWF_FULL), MDWF_OP_K5INV: (MDWF_FULL, MDWF_FULL),
+    MDWF_OP_K5_DAG: (MDWF_FULL, MDWF_FULL), MDWF_OP_K5INV_DAG: (MDWF_FULL, MDWF_FULL),
+    MDWF_OP_B: (MDWF_FULL, MDWF_FULL), MDWF_OP_B_DAG: (MDWF_FULL, MDWF_FULL),
+}
+
+
+class mdwf_geometry(C.Structure):
+    _fields_ = [("X", C.c_int), ("Y", C.c_int), ("Z", C.c_int), ("T", C.c_int), ("antiperiodic_t", C.c_int)]
+
+
+class mdwf_action(C.Structure):
+    _fields_ = [("M5", C.c_double), ("b5", C.c_double), ("c5", C.c_double), ("mq", C.c_double), ("L5", C.c_int)]
+
+
+class mdwf_solver_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner", C.c_int), ("delta", C.c_double),
+                ("check_every", C.c_int), ("use_graph", C.c_int)]
+
+
+class mdwf_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("restarts", C.c_int),
+                ("true_resid", C.c_double), ("seconds", C.c_double), ("model_flops", C.c_double),
+                ("model_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MdwfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES[status] if 0 <= status < 7 else status, msg))
+        self.status = status
+
+
+def _share_hip_runtime_with_torch():
+    """Load torch's HIP runtime first, when torch is installed.
+
+    torch ships its own libamdhip64 (same SONAME as the system one, but
+    torch's extensions name it without the version suffix, so the loader would
+    otherwise map a second copy).  Two HIP runtimes in one process do not
+    share devices, streams or allocations; with torch loaded first, libmdwf's
+    dependency resolves to torch's already-loaded runtime.
+    """
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
+def _load():
+    _share_hip_runtime_with_torch()
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmdwf.so is not built (run __graft_entry__.build() or "
+                          "python paper_1701_07559_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, ip, dp = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "mdwf_create": ([C.POINTER(mdwf_geometry), ip, vp, C.POINTER(vp)], ip),
+        "mdwf_destroy": ([vp], None),
+        "mdwf_last_error": ([vp], C.c_char_p),
+        "mdwf_load_gauge": ([vp, vp], ip),
+        "mdwf_load_gauge_dev": ([vp, vp], ip),
+        "mdwf_set_action": ([vp, C.POINTER(mdwf_action)], ip),
+        "mdwf_field_bytes": ([vp, ip, ip, C.POINTER(C.c_size_t)], ip),
+        "mdwf_pack_dev": ([vp, ip, ip, vp, vp, vp], ip),
+        "mdwf_unpack_dev": ([vp, ip, ip, vp, vp, vp], ip),
+        "mdwf_apply": ([vp, ip, ip, vp, vp], ip),
+        "mdwf_apply_dev": ([vp, ip, ip, vp, vp, vp], ip),
+        "mdwf_solve": ([vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
+                        C.POINTER(mdwf_solve_info)], ip),
+        "mdwf_solve_dev": ([vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
+                            C.POINTER(mdwf_solve_info), vp], ip),
+        "mdwf_default_opts": ([C.POINTER(mdwf_solver_opts)], None),
+        "mdwf_op_model": ([vp, ip, ip, C.POINTER(dp), C.POINTER(dp)], ip),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def mdwf_last_error(ctx) -> str:
+    s = lib.mdwf_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def _check(ctx, st, allow=()):
+    if st != MDWF_OK and st not in allow:
+        raise MdwfError(st, mdwf_last_error(ctx))
+    return st
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def mdwf_create(dims, antiperiodic_t=True, hip_device=0, hip_stream=None):
+    g = mdwf_geometry(*[int(d) for d in dims], int(bool(antiperiodic_t)))
+    out = C.c_void_p()
+    _check(None, lib.mdwf_create(C.byref(g), int(hip_device), hip_stream, C.byref(out)))
+    return out
+
+
+def mdwf_destroy(ctx):
+    lib.mdwf_destroy(ctx)
+
+
+def mdwf_load_gauge(ctx, U):
+    U = _c128(U)
+    _check(ctx, lib.mdwf_load_gauge(ctx, U.ctypes.data))
+
+
+def mdwf_load_gauge_dev(ctx, U_ptr):
+    _check(ctx, lib.mdwf_load_gauge_dev(ctx, int(U_ptr)))
+
+
+def mdwf_set_action(ctx, M5, b5, c5, mq, L5):
+    a = mdwf_action(float(M5), float(b5), float(c5), float(mq), int(L5))
+    _check(ctx, lib.mdwf_set_action(ctx, C.byref(a)))
+
+
+def mdwf_field_bytes(ctx, prec, kind) -> int:
+    n = C.c_size_t()
+    _check(ctx, lib.mdwf_field_bytes(ctx, int(prec), int(kind), C.byref(n)))
+    return int(n.value)
+
+
+def mdwf_pack_dev(ctx, prec, kind, canon_ptr, native_ptr, stream=None):
+    _check(ctx, lib.mdwf_pack_dev(ctx, int(prec), int(kind), int(canon_ptr), int(native_ptr), stream))
+
+
+def mdwf_unpack_dev(ctx, prec, kind, native_ptr, canon_ptr, stream=None):
+    _check(ctx, lib.mdwf_unpack_dev(ctx, int(prec), int(kind), int(native_ptr), int(canon_ptr), stream))
+
+
+def mdwf_apply(ctx, op, prec, inp, out):
+    """Host canonical complex128 arrays; `out` is written in place."""
+    inp = _c128(inp)
+    if not (out.flags.c_contiguous and out.dtype == np.complex128):
+        raise ValueError("out must be a C-contiguous complex128 array")
+    _check(ctx, lib.mdwf_apply(ctx, int(op), int(prec), inp.ctypes.data, out.ctypes.data))
+    return out
+
+
+def mdwf_apply_dev(ctx, op, prec, in_ptr, out_ptr, stream=None):
+    _check(ctx, lib.mdwf_apply_dev(ctx, int(op), int(prec), int(in_ptr), int(out_ptr), stream))
+
+
+def mdwf_default_opts() -> mdwf_solver_opts:
+    o = mdwf_solver_opts()
+    lib.mdwf_default_opts(C.byref(o))
+    return o
+
+
+def _opts(opts):
+    o = mdwf_default_opts()
+    if isinstance(opts, mdwf_solver_opts):
+        return opts
+    for k, v in (opts or {}).items():
+        setattr(o, k, v)
+    return o
+
+
+def mdwf_solve(ctx, b_list, x_list, mq=None, opts=None):
+    """Host canonical complex128 fields; returns (status, [info dicts])."""
+    n = len(b_list)
+    bs = [_c128(b) for b in b_list]
+    for x in x_list:
+        if not (x.flags.c_contiguous and x.dtype == np.complex128):
+            raise ValueError("x must be C-contiguous complex128 arrays")
+    bp = (C.c_void_p * n)(*[b.ctypes.data for b in bs])
+    xp = (C.c_void_p * n)(*[x.ctypes.data for x in x_list])
+    m = (C.c_double * n)(*mq) if mq is not None else None
+    infos = (mdwf_solve_info * n)()
+    o = _opts(opts)
+    st = lib.mdwf_solve(ctx, n, bp, xp, m, C.byref(o), infos)
+    _check(ctx, st, allow=(MDWF_ERR_NOCONV, MDWF_ERR_NUMERIC))
+    return st, [i.as_dict() for i in infos]
+
+
+def mdwf_solve_dev(ctx, b_ptrs, x_ptrs, mq=None, opts=None, stream=None):
+    """Canonical FP64 device fields (integer pointers); returns (status, [info dicts])."""
+    n = len(b_ptrs)
+    bp = (C.c_void_p * n)(*[int(p) for p in b_ptrs])
+    xp = (C.c_void_p * n)(*[int(p) for p in x_ptrs])
+    m = (C.c_double * n)(*mq) if mq is not None else None
+    infos = (mdwf_solve_info * n)()
+    o = _opts(opts)
+    st = lib.mdwf_solve_dev(ctx, n, bp, xp, m, C.byref(o), infos, stream)
+    _check(ctx, st, allow=(MDWF_ERR_NOCONV, MDWF_ERR_NUMERIC))
+    return st, [i.as_dict() for i in infos]
+
+
+def mdwf_op_model(ctx, op, prec):
+    f, b = C.c_double(), C.c_double()
+    _check(ctx, lib.mdwf_op_model(ctx, int(op), int(prec), C.byref(f), C.byref(b)))
+    return f.value, b.value
+
+
+def exported_symbols():
+    """Names of the C entry points declared in include/mdwf.h."""
+    return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
+            "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
+            "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model"]

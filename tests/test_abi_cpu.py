@@ -1,0 +1,64 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+entry point, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdwf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdwf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["mdwf_create", "mdwf_destroy", "mdwf_load_gauge", "mdwf_set_action", "mdwf_apply",
+                 "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1701_07559_amd import mdwf
+    lib = C.CDLL(mdwf.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(mdwf.exported_symbols()) == declared_functions()
+
+
+def test_create_rejects_odd_extents_without_device():
+    from paper_1701_07559_amd import mdwf
+    g = mdwf.mdwf_geometry(3, 4, 4, 4, 1)
+    out = C.c_void_p()
+    st = mdwf.lib.mdwf_create(C.byref(g), 0, None, C.byref(out))
+    assert st == mdwf.MDWF_ERR_ARG
+    assert "even" in mdwf.mdwf_last_error(None)
+    g = mdwf.mdwf_geometry(4, 4, 0, 4, 1)
+    assert mdwf.lib.mdwf_create(C.byref(g), 0, None, C.byref(out)) == mdwf.MDWF_ERR_ARG
+    assert mdwf.lib.mdwf_create(None, 0, None, C.byref(out)) == mdwf.MDWF_ERR_ARG
+
+
+def test_null_context_calls_return_arg_errors():
+    from paper_1701_07559_amd import mdwf
+    a = mdwf.mdwf_action(1.3, 1.5, 0.5, 0.05, 8)
+    assert mdwf.lib.mdwf_set_action(None, C.byref(a)) == mdwf.MDWF_ERR_ARG
+    assert mdwf.lib.mdwf_load_gauge(None, None) == mdwf.MDWF_ERR_ARG
+    assert mdwf.lib.mdwf_apply(None, 0, 0, None, None) == mdwf.MDWF_ERR_ARG
+    o = mdwf.mdwf_default_opts()
+    assert o.tol == 1e-10 and o.inner == mdwf.MDWF_F64 and abs(o.delta - 0.1) < 1e-15
+    mdwf.lib.mdwf_destroy(None)   # ignored
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    import importlib.util
+    src = os.path.join(ROOT, "paper_1701_07559_amd", "mdwf.py")
+    spec = importlib.util.spec_from_file_location("mdwf_copy", str(tmp_path / "mdwf.py"))
+    (tmp_path / "mdwf.py").write_text(open(src).read())
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)

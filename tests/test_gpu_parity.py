@@ -1,0 +1,295 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Operator parity: relative 2-norm error of every operator against the oracle,
+at most 1e-13 in FP64, 1e-6 in FP32 and 5e-3 in FP16 (the dslash tolerances of
+the solver's specification), on lattices that span several workgroup tiles
+with a ragged tail, on the degenerate 2^4 lattice (forward and backward
+neighbours coincide), with L5 = 1 and with periodic time.
+
+Solver parity: every solve's true FP64 residual ||b - D5 x|| / ||b||, computed
+by the oracle's operator on the returned x, is at most 1e-10; where the oracle
+solves the same system its solution is compared as well.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_07559_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-13, 1: 1e-6, 2: 5e-3}
+PREC_NAME = {0: "f64", 1: "f32", 2: "f16"}
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1701_07559_amd import mdwf
+    try:
+        ctx = mdwf.mdwf_create((2, 2, 2, 2))
+    except mdwf.MdwfError as e:
+        pytest.skip("no HIP device: %s" % e)
+    mdwf.mdwf_destroy(ctx)
+    return mdwf
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def half(psi, dims, parity):
+    """Parity-compressed canonical half field of a full canonical field."""
+    X, Y, Z, T = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    mask = ((x + y + z + t) % 2) == parity
+    return np.ascontiguousarray(psi[:, mask])
+
+
+def expand(h, dims, parity):
+    X, Y, Z, T = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    mask = ((x + y + z + t) % 2) == parity
+    out = np.zeros((h.shape[0], T, Z, Y, X, 4, 3), complex)
+    out[:, mask] = h
+    return out
+
+
+def make_ctx(M, act, U):
+    ctx = M.mdwf_create(act.dims, antiperiodic_t=act.antiperiodic_t)
+    M.mdwf_set_action(ctx, act.M5, act.b5, act.c5, act.mq, act.L5)
+    M.mdwf_load_gauge(ctx, U)
+    return ctx
+
+
+def oracle_op(M, op, act, U, psi):
+    """Oracle result of `op` on the full canonical field psi, as the kind the op returns."""
+    d = act.dims
+    if op == M.MDWF_OP_D5:
+        return oracle.D5(act, U, psi)
+    if op == M.MDWF_OP_D5_DAG:
+        return oracle.D5(act, U, psi, dag=True)
+    if op in (M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG):
+        return half(oracle.schur(act, U, psi, dag=(op == M.MDWF_OP_SCHUR_DAG)), d, 0)
+    if op in (M.MDWF_OP_HOP_EO, M.MDWF_OP_HOP_EO_DAG):
+        return half(oracle.hop(act, U, psi, 0, dag=(op == M.MDWF_OP_HOP_EO_DAG)), d, 0)
+    if op in (M.MDWF_OP_HOP_OE, M.MDWF_OP_HOP_OE_DAG):
+        return half(oracle.hop(act, U, psi, 1, dag=(op == M.MDWF_OP_HOP_OE_DAG)), d, 1)
+    f = {M.MDWF_OP_K5: oracle.apply_K5, M.MDWF_OP_K5_DAG: oracle.apply_K5,
+         M.MDWF_OP_K5INV: oracle.apply_K5inv, M.MDWF_OP_K5INV_DAG: oracle.apply_K5inv,
+         M.MDWF_OP_B: oracle.apply_B, M.MDWF_OP_B_DAG: oracle.apply_B}[op]
+    dag = op in (M.MDWF_OP_K5_DAG, M.MDWF_OP_K5INV_DAG, M.MDWF_OP_B_DAG)
+    return f(act, psi, dag=dag)
+
+
+def gpu_op(M, ctx, op, prec, act, psi):
+    kin, kout = M.OP_KINDS[op]
+    d = act.dims
+    if kin == M.MDWF_FULL:
+        inp = psi
+    else:
+        inp = half(psi, d, 0 if kin == M.MDWF_HALF_EVEN else 1)
+    if kout == M.MDWF_FULL:
+        out = np.zeros(act.shape5, complex)
+    else:
+        X, Y, Z, T = d
+        out = np.zeros((act.L5, X * Y * Z * T // 2, 4, 3), complex)
+    M.mdwf_apply(ctx, op, prec, inp, out)
+    return out
+
+
+GEOMS = [
+    # dims, L5, antiperiodic -- tiles of 32 (L5=8), 20 (L5=12), 64 (L5=1) sites with ragged tails
+    ((6, 4, 2, 6), 8, True),
+    ((4, 6, 6, 4), 12, True),
+    ((2, 2, 2, 2), 4, True),
+    ((4, 2, 4, 6), 1, False),
+    ((2, 4, 2, 4), 5, True),
+]
+ALL_OPS = list(range(14))
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "x".join(map(str, g[0])) + "_L%d" % g[1])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=lambda p: PREC_NAME[p])
+def test_operator_parity(M, geom, prec):
+    dims, L5, ap = geom
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05, antiperiodic_t=ap)
+    U = I.random_links(dims, 0.3, 41)
+    psi = I.gaussian_source(dims, L5, 42)
+    ctx = make_ctx(M, act, U)
+    try:
+        for op in ALL_OPS:
+            ref = oracle_op(M, op, act, U, psi)
+            out = gpu_op(M, ctx, op, prec, act, psi)
+            err = rel(out, ref)
+            assert err <= TOL[prec], "op %d prec %s: rel err %.3e" % (op, PREC_NAME[prec], err)
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_operator_parity_other_action(M):
+    """Shamir-like and heavy-mass corner: b5 = 1, c5 = 0, m_q = 1, M5 = 1.8."""
+    dims, L5 = (4, 4, 2, 2), 6
+    act = oracle.Action(dims, L5, M5=1.8, b5=1.0, c5=0.0, mq=1.0)
+    U = I.random_links(dims, 0.5, 43)
+    psi = I.gaussian_source(dims, L5, 44)
+    ctx = make_ctx(M, act, U)
+    try:
+        for op in ALL_OPS:
+            assert rel(gpu_op(M, ctx, op, 0, act, psi), oracle_op(M, op, act, U, psi)) <= 1e-13
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_dev_entry_points_roundtrip(M):
+    """pack -> apply_dev -> unpack on device buffers equals the host path."""
+    import torch
+    dims, L5 = (6, 4, 2, 6), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 45)
+    psi = I.gaussian_source(dims, L5, 46)
+    ctx = make_ctx(M, act, U)
+    try:
+        dev = torch.device("cuda:0")
+        for prec in (0, 1, 2):
+            nb = M.mdwf_field_bytes(ctx, prec, M.MDWF_FULL)
+            a = torch.empty(nb, dtype=torch.uint8, device=dev)
+            b = torch.empty(nb, dtype=torch.uint8, device=dev)
+            canon = torch.from_numpy(psi.view(np.float64).copy()).to(dev)
+            outc = torch.empty_like(canon)
+            stream = torch.cuda.current_stream().cuda_stream
+            M.mdwf_pack_dev(ctx, prec, M.MDWF_FULL, canon.data_ptr(), a.data_ptr(), stream)
+            M.mdwf_apply_dev(ctx, M.MDWF_OP_D5, prec, a.data_ptr(), b.data_ptr(), stream)
+            M.mdwf_unpack_dev(ctx, prec, M.MDWF_FULL, b.data_ptr(), outc.data_ptr(), stream)
+            torch.cuda.synchronize()
+            got = outc.cpu().numpy().view(np.complex128).reshape(psi.shape)
+            assert rel(got, oracle.D5(act, U, psi)) <= TOL[prec]
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+# ---------------------------------------------------------------- solver
+
+CFG1 = dict(dims=(4, 4, 4, 8), L5=8, M5=1.3, b5=1.5, c5=0.5, mq=0.05, eps=0.3, gseed=101, sseed=301)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    c = CFG1
+    act = oracle.Action(c["dims"], c["L5"], M5=c["M5"], b5=c["b5"], c5=c["c5"], mq=c["mq"])
+    U = I.random_links(c["dims"], c["eps"], c["gseed"])
+    b = I.gaussian_source(c["dims"], c["L5"], c["sseed"])
+    x_ref, info = oracle.solve(act, U, b, tol=1e-12)
+    assert info["status"] == 0
+    return act, U, b, x_ref
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2], ids=["f64", "f32_inner", "f16_inner"])
+def test_solve_matches_oracle(M, cfg1, inner):
+    act, U, b, x_ref = cfg1
+    ctx = make_ctx(M, act, U)
+    try:
+        x = np.zeros_like(b)
+        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(tol=1e-10, inner=inner, max_iter=20000))
+        assert st == M.MDWF_OK, info
+        tr = oracle.true_residual(act, U, b, x)
+        assert tr <= 1e-10, (tr, info)
+        assert abs(tr - info[0]["true_resid"]) <= 1e-11
+        assert rel(x, x_ref) <= 1e-7
+        if inner:
+            assert info[0]["reliable_updates"] >= 1
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_solve_graph_replay_matches_eager(M, cfg1):
+    act, U, b, _ = cfg1
+    ctx = make_ctx(M, act, U)
+    try:
+        xs = []
+        for g in (0, 1, 1):
+            x = np.zeros_like(b)
+            st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(inner=1, use_graph=g))
+            assert st == M.MDWF_OK
+            xs.append((x, info[0]["iters"]))
+        for x, it in xs[1:]:
+            assert it == xs[0][1]
+            assert np.array_equal(x, xs[0][0])
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_multi_rhs_multi_mass_equals_single(M):
+    """Point-source columns at three masses in one launch; each equals its solo solve."""
+    dims, L5 = (4, 4, 4, 8), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 47)
+    site = I.random_point_site(dims, 404)
+    cols = I.point_source_columns(dims, L5, site)
+    bs = [cols[0], cols[7], cols[11], cols[4]]
+    masses = [0.05, 0.02, 0.1, 0.04]
+    ctx = make_ctx(M, act, U)
+    try:
+        for inner in (0, 2):
+            xs = [np.zeros_like(b) for b in bs]
+            st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=inner))
+            assert st == M.MDWF_OK
+            for k, b in enumerate(bs):
+                a_k = act.with_mass(masses[k])
+                assert oracle.true_residual(a_k, U, b, xs[k]) <= 1e-10
+                x1 = np.zeros_like(b)
+                st1, info1 = M.mdwf_solve(ctx, [b], [x1], mq=[masses[k]], opts=dict(inner=inner))
+                assert st1 == M.MDWF_OK
+                assert info1[0]["iters"] == info[k]["iters"]
+                assert np.array_equal(x1, xs[k]), "RHS %d differs alone vs batched" % k
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_solve_dev_with_torch_buffers(M, cfg1):
+    import torch
+    act, U, b, x_ref = cfg1
+    ctx = make_ctx(M, act, U)
+    try:
+        dev = torch.device("cuda:0")
+        bt = torch.from_numpy(b.view(np.float64).copy()).to(dev)
+        xt = torch.zeros_like(bt)
+        st, info = M.mdwf_solve_dev(ctx, [bt.data_ptr()], [xt.data_ptr()], opts=dict(inner=2),
+                                    stream=torch.cuda.current_stream().cuda_stream)
+        assert st == M.MDWF_OK
+        x = xt.cpu().numpy().view(np.complex128).reshape(b.shape)
+        assert oracle.true_residual(act, U, b, x) <= 1e-10
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_solver_failure_paths(M, cfg1):
+    act, U, b, _ = cfg1
+    ctx = M.mdwf_create(act.dims)
+    try:
+        x = np.zeros_like(b)
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_solve(ctx, [b], [x])
+        assert e.value.status == M.MDWF_ERR_STATE
+        M.mdwf_set_action(ctx, act.M5, act.b5, act.c5, act.mq, act.L5)
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_apply(ctx, M.MDWF_OP_D5, 0, b, x)
+        assert e.value.status == M.MDWF_ERR_STATE
+        M.mdwf_load_gauge(ctx, U)
+        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(max_iter=3))
+        assert st == M.MDWF_ERR_NOCONV and info[0]["iters"] >= 3
+        assert info[0]["true_resid"] > 1e-10
+        bad = b.copy()
+        bad[0, 0, 0, 0, 0, 0, 0] = np.nan
+        st, info = M.mdwf_solve(ctx, [bad], [x])
+        assert st == M.MDWF_ERR_NUMERIC
+        zero = np.zeros_like(b)
+        st, info = M.mdwf_solve(ctx, [zero], [x])
+        assert st == M.MDWF_OK and np.all(x == 0)
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_solve(ctx, [b], [x], opts=dict(tol=-1.0))
+        assert e.value.status == M.MDWF_ERR_ARG
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_set_action(ctx, 1.3, 0.5, 0.5, 0.05, 8)
+        assert e.value.status == M.MDWF_ERR_ARG
+    finally:
+        M.mdwf_destroy(ctx)
