@@ -109,6 +109,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--micro-only", action="store_true", help="time the operator kernels and stop")
+    ap.add_argument("--micro-reps", type=int, default=50)
+    ap.add_argument("--micro-precs", default="f64,f32,f16")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -122,6 +127,10 @@ def main():
     from paper_1701_07559_amd import mdwf as M
 
     dev = torch.device("cuda:0")
+    # One explicit stream for torch and the library: torch's default stream
+    # is the null handle, which the C ABI reads as "the context's stream".
+    work = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(work)
     X, Y, Z, T = DIMS
     V = X * Y * Z * T
     log("generating links", DIMS)
@@ -130,20 +139,32 @@ def main():
     log("plaquette %.4f" % plaq)
     site = I.random_point_site(DIMS, SITE_SEED)
 
-    ctx = M.mdwf_create(DIMS, antiperiodic_t=True, hip_device=0,
-                        hip_stream=torch.cuda.current_stream().cuda_stream)
+    ctx = M.mdwf_create(DIMS, antiperiodic_t=True, hip_device=0, hip_stream=work.cuda_stream)
     M.mdwf_set_action(ctx, ACTION["M5"], ACTION["b5"], ACTION["c5"], ACTION["mq"], L5)
     M.mdwf_load_gauge(ctx, U)
-    stream = torch.cuda.current_stream().cuda_stream
+    stream = work.cuda_stream
+    assert stream and torch.cuda.current_stream().cuda_stream == stream
+
+    if args.copy_calib:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     micro = {}
     if not args.no_micro:
-        for pname, prec in (("f64", 0), ("f32", 1), ("f16", 2)):
+        precs = [p for p in (("f64", 0), ("f32", 1), ("f16", 2)) if p[0] in args.micro_precs.split(",")]
+        for pname, prec in precs:
             for oname, op in (("hop", M.MDWF_OP_HOP_EO), ("schur", M.MDWF_OP_SCHUR),
                               ("schur_dag", M.MDWF_OP_SCHUR_DAG)):
-                r = time_apply(M, torch, ctx, op, prec, reps=50)
+                r = time_apply(M, torch, ctx, op, prec, reps=args.micro_reps)
                 micro["%s_%s" % (oname, pname)] = r
                 log("%s %s: %.3f ms  %.0f GB/s  %.0f GFLOP/s" % (oname, pname, r["ms"], r["GBps"], r["GFLOPs"]))
+    if args.micro_only:
+        print(json.dumps({k: dict(ms=v["ms"], GBps=v["GBps"]) for k, v in micro.items()}), flush=True)
+        M.mdwf_destroy(ctx)
+        return
 
     # right-hand sides: the 12 spin-colour columns of a point source, FP64
     # canonical, built on the device

@@ -80,6 +80,8 @@ def _load():
             ("oracle_true_residual", [P, d, d, d], C.c_double),
             ("oracle_solve", [P, d, d, d, C.c_double, C.c_int, C.POINTER(SolveInfo)], C.c_int),
             ("oracle_cgls_step", [P, d, d, d, d, d, d, C.POINTER(C.c_double)], C.c_double),
+            ("oracle_D5_sites", [P, d, d, d, C.c_int, d], None),
+            ("oracle_schur_sites", [P, d, d, d, C.c_int, C.c_int, d], None),
         ]:
             f = getattr(lib, name)
             f.argtypes = args
@@ -227,6 +229,26 @@ def cgls_step(act: Action, U, x, r, p, s, q, gam):
     rr = _load().oracle_cgls_step(C.byref(act.params()), pu, x.ctypes.data, r.ctypes.data,
                                   p.ctypes.data, s.ctypes.data, q.ctypes.data, C.byref(g))
     return float(rr), float(g.value)
+
+
+def D5_sites(act: Action, U, psi, sites):
+    """(D5 psi) at the listed 4D lexicographic sites, all slices: [n, L5, 4, 3]."""
+    U, pu = _c(U)
+    psi, pi = _c(psi)
+    s = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(s), act.L5, 4, 3), np.complex128)
+    _load().oracle_D5_sites(C.byref(act.params()), pu, pi, s.ctypes.data, len(s), out.ctypes.data)
+    return out
+
+
+def schur_sites(act: Action, U, psi, sites, dag=False):
+    """(S psi) or (S^+ psi) at the listed even 4D sites, all slices: [n, L5, 4, 3]."""
+    U, pu = _c(U)
+    psi, pi = _c(psi)
+    s = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(s), act.L5, 4, 3), np.complex128)
+    _load().oracle_schur_sites(C.byref(act.params()), pu, pi, s.ctypes.data, len(s), int(dag), out.ctypes.data)
+    return out
 
 
 def even_mask(dims) -> np.ndarray:

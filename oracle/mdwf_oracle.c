@@ -143,48 +143,55 @@ static long neighbour(const oracle_params *p, long site, int mu, int dir, double
 
 /* ------------------------------------------------------------ 4D Wilson */
 
-/* out(x) = sum_mu (1 - sg g_mu) U_mu(x) in(x+mu) + (1 + sg g_mu) U_mu(x-mu)^+ in(x-mu)
- * with sg = +1 for Dslash and sg = -1 for its adjoint.  Only sites whose parity
- * equals `out_parity` are written (all sites when out_parity < 0); the others
- * are set to zero. */
+/* acc = (Dslash in)(x) for one site x of a 4D field:
+ *   sum_mu (1 - sg g_mu) U_mu(x) in(x+mu) + (1 + sg g_mu) U_mu(x-mu)^+ in(x-mu)
+ * with sg = +1 for Dslash and sg = -1 for its adjoint. */
+static void hop_site(const oracle_params *p, const cplx *U, const cplx *in, long x, int dag,
+                     cplx acc[4][3])
+{
+    init_gamma();
+    const double sg = dag ? -1.0 : 1.0;
+    memset(acc, 0, 12 * sizeof(cplx));
+    for (int mu = 0; mu < 4; ++mu) {
+        for (int dir = +1; dir >= -1; dir -= 2) {
+            double bc;
+            long y = neighbour(p, x, mu, dir, &bc);
+            const cplx *psi = in + 12 * y;
+            /* colour: forward uses U_mu(x), backward U_mu(x-mu)^+ */
+            cplx tmp[4][3];
+            for (int sp = 0; sp < 4; ++sp)
+                for (int a = 0; a < 3; ++a) {
+                    cplx v = 0;
+                    for (int b = 0; b < 3; ++b) {
+                        cplx u = (dir > 0) ? U[(x * 4 + mu) * 9 + a * 3 + b]
+                                           : conj(U[(y * 4 + mu) * 9 + b * 3 + a]);
+                        v += u * psi[sp * 3 + b];
+                    }
+                    tmp[sp][a] = v;
+                }
+            /* spin: (1 - dir*sg g_mu) */
+            const double gs = -dir * sg;
+            for (int sp = 0; sp < 4; ++sp)
+                for (int a = 0; a < 3; ++a) {
+                    cplx v = tmp[sp][a];
+                    for (int sq = 0; sq < 4; ++sq) v += gs * G[mu][sp][sq] * tmp[sq][a];
+                    acc[sp][a] += bc * v;
+                }
+        }
+    }
+}
+
+/* Dslash (or its adjoint) on a 4D field.  Only sites whose parity equals
+ * `out_parity` are written (all sites when out_parity < 0); the others are
+ * set to zero. */
 static void dslash4(const oracle_params *p, const cplx *U, const cplx *in, cplx *out,
                     int dag, int out_parity)
 {
-    init_gamma();
     const long V = volume(p);
-    const double sg = dag ? -1.0 : 1.0;
     for (long x = 0; x < V; ++x) {
         cplx acc[4][3];
         memset(acc, 0, sizeof(acc));
-        if (out_parity < 0 || parity_of(p, x) == out_parity) {
-            for (int mu = 0; mu < 4; ++mu) {
-                for (int dir = +1; dir >= -1; dir -= 2) {
-                    double bc;
-                    long y = neighbour(p, x, mu, dir, &bc);
-                    const cplx *psi = in + 12 * y;
-                    /* colour: forward uses U_mu(x), backward U_mu(x-mu)^+ */
-                    cplx tmp[4][3];
-                    for (int sp = 0; sp < 4; ++sp)
-                        for (int a = 0; a < 3; ++a) {
-                            cplx v = 0;
-                            for (int b = 0; b < 3; ++b) {
-                                cplx u = (dir > 0) ? U[(x * 4 + mu) * 9 + a * 3 + b]
-                                                   : conj(U[(y * 4 + mu) * 9 + b * 3 + a]);
-                                v += u * psi[sp * 3 + b];
-                            }
-                            tmp[sp][a] = v;
-                        }
-                    /* spin: (1 - dir*sg g_mu) */
-                    const double gs = -dir * sg;
-                    for (int sp = 0; sp < 4; ++sp)
-                        for (int a = 0; a < 3; ++a) {
-                            cplx v = tmp[sp][a];
-                            for (int sq = 0; sq < 4; ++sq) v += gs * G[mu][sp][sq] * tmp[sq][a];
-                            acc[sp][a] += bc * v;
-                        }
-                }
-            }
-        }
+        if (out_parity < 0 || parity_of(p, x) == out_parity) hop_site(p, U, in, x, dag, acc);
         memcpy(out + 12 * x, acc, sizeof(acc));
     }
 }
@@ -543,6 +550,139 @@ int oracle_solve(const oracle_params *p, const double *Ud, const double *bd, dou
     }
     free(bp); free(r); free(s); free(pv); free(q); free(xe);
     return status;
+}
+
+/* ------------------------------------------------------ sampled sites */
+
+/* (D5 in)(x, s) for the 4D sites listed in `sites` and every slice s;
+ * out[n][L5][12].  Evaluated site by site from the definition
+ * D5 = D_W B + 1 - C (the full-lattice B and C passes are O(volume)). */
+void oracle_D5_sites(const oracle_params *p, const double *Ud, const double *ind,
+                     const long *sites, int nsites, double *outd)
+{
+    const cplx *U = (const cplx *)Ud, *in = (const cplx *)ind;
+    cplx *out = (cplx *)outd;
+    const long V = volume(p), n = n5(p);
+    const int L5 = p->L5;
+    cplx *b = malloc(n * sizeof(cplx)), *c = malloc(n * sizeof(cplx));
+    apply_B(p, in, b, 0);
+    apply_C(p, in, c, 0);
+    for (int k = 0; k < nsites; ++k) {
+        const long x = sites[k];
+        for (int s = 0; s < L5; ++s) {
+            cplx acc[4][3];
+            hop_site(p, U, b + (long)s * V * 12, x, 0, acc);
+            const long o = ((long)s * V + x) * 12;
+            for (int i = 0; i < 12; ++i)
+                out[((long)k * L5 + s) * 12 + i] =
+                    (4.0 - p->M5) * b[o + i] - 0.5 * (&acc[0][0])[i] + in[o + i] - c[o + i];
+        }
+    }
+    free(b); free(c);
+}
+
+/* (S in)(x, s) or (S^+ in)(x, s) for even 4D sites `sites` and every slice;
+ * out[n][L5][12].  The odd-site intermediate is evaluated only on the eight
+ * neighbours of each sampled site:
+ *   S   = K5   - 1/4 D_eo (B K5^-1) D_oe B
+ *   S^+ = K5^+ - 1/4 B^+ D_oe^+ K5^-+ B^+ D_eo^+ */
+void oracle_schur_sites(const oracle_params *p, const double *Ud, const double *ind,
+                        const long *sites, int nsites, int dag, double *outd)
+{
+    const cplx *U = (const cplx *)Ud;
+    cplx *out = (cplx *)outd;
+    const long V = volume(p), n = n5(p), n4 = 12 * V;
+    const int L5 = p->L5;
+    cplx *x = malloc(n * sizeof(cplx)), *src = malloc(n * sizeof(cplx)),
+         *kx = malloc(n * sizeof(cplx)), *nb = calloc(n, sizeof(cplx));
+    memcpy(x, ind, n * sizeof(cplx));
+    mask_parity(p, x, 0);
+    apply_K5(p, x, kx, dag);
+    if (!dag) apply_B(p, x, src, 0);       /* B x, input of D_oe      */
+    else memcpy(src, x, n * sizeof(cplx)); /* x,  input of D_eo^+     */
+    double *K[2], *A = malloc(sizeof(double) * L5 * L5);
+    cplx *col = malloc(sizeof(cplx) * L5), *v = malloc(sizeof(cplx) * L5 * 12),
+         *w = malloc(sizeof(cplx) * L5 * 12);
+    for (int u = 0; u < 2; ++u) {
+        K[u] = malloc(sizeof(double) * L5 * L5);
+        k5_matrix(p, u, dag, K[u]);
+    }
+    for (int k = 0; k < nsites; ++k) {
+        const long xs = sites[k];
+        long ys[8];
+        int m = 0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int dir = +1; dir >= -1; dir -= 2) {
+                double bc;
+                ys[m++] = neighbour(p, xs, mu, dir, &bc);
+            }
+        /* odd neighbours: v = (B K5^-1)(D_oe B x) or K5^-+ B^+ (D_eo^+ x) */
+        for (int m2 = 0; m2 < 8; ++m2) {
+            const long y = ys[m2];
+            for (int s = 0; s < L5; ++s) {
+                cplx acc[4][3];
+                hop_site(p, U, src + (long)s * n4, y, dag, acc);
+                memcpy(v + s * 12, acc, sizeof(acc));
+            }
+            if (dag) {   /* B^+ on the slices of y */
+                for (int s = 0; s < L5; ++s)
+                    for (int sp = 0; sp < 4; ++sp) {
+                        long from = (sp < 2) ? s + 1 : s - 1;
+                        double f = 1.0;
+                        if (from < 0) { from += L5; f = -p->mq; }
+                        if (from >= L5) { from -= L5; f = -p->mq; }
+                        for (int a = 0; a < 3; ++a)
+                            w[s * 12 + sp * 3 + a] = p->b5 * v[s * 12 + sp * 3 + a] + p->c5 * f * v[from * 12 + sp * 3 + a];
+                    }
+                memcpy(v, w, sizeof(cplx) * L5 * 12);
+            }
+            for (int sp = 0; sp < 4; ++sp)   /* K5^-1 or K5^-+ */
+                for (int a = 0; a < 3; ++a) {
+                    for (int s = 0; s < L5; ++s) col[s] = v[s * 12 + sp * 3 + a];
+                    memcpy(A, K[sp < 2], sizeof(double) * L5 * L5);
+                    gauss_solve(L5, A, col);
+                    for (int s = 0; s < L5; ++s) v[s * 12 + sp * 3 + a] = col[s];
+                }
+            if (!dag) {  /* B on the slices of y */
+                for (int s = 0; s < L5; ++s)
+                    for (int sp = 0; sp < 4; ++sp) {
+                        long from = (sp < 2) ? s - 1 : s + 1;
+                        double f = 1.0;
+                        if (from < 0) { from += L5; f = -p->mq; }
+                        if (from >= L5) { from -= L5; f = -p->mq; }
+                        for (int a = 0; a < 3; ++a)
+                            w[s * 12 + sp * 3 + a] = p->b5 * v[s * 12 + sp * 3 + a] + p->c5 * f * v[from * 12 + sp * 3 + a];
+                    }
+                memcpy(v, w, sizeof(cplx) * L5 * 12);
+            }
+            for (int s = 0; s < L5; ++s) memcpy(nb + (long)s * n4 + 12 * y, v + s * 12, 12 * sizeof(cplx));
+        }
+        /* back to x: D_eo (or D_oe^+) of the neighbour values */
+        for (int s = 0; s < L5; ++s) {
+            cplx acc[4][3];
+            hop_site(p, U, nb + (long)s * n4, xs, dag, acc);
+            memcpy(w + s * 12, acc, sizeof(acc));
+        }
+        if (dag) {   /* B^+ on the slices of x */
+            for (int s = 0; s < L5; ++s)
+                for (int sp = 0; sp < 4; ++sp) {
+                    long from = (sp < 2) ? s + 1 : s - 1;
+                    double f = 1.0;
+                    if (from < 0) { from += L5; f = -p->mq; }
+                    if (from >= L5) { from -= L5; f = -p->mq; }
+                    for (int a = 0; a < 3; ++a)
+                        v[s * 12 + sp * 3 + a] = p->b5 * w[s * 12 + sp * 3 + a] + p->c5 * f * w[from * 12 + sp * 3 + a];
+                }
+            memcpy(w, v, sizeof(cplx) * L5 * 12);
+        }
+        for (int s = 0; s < L5; ++s)
+            for (int i = 0; i < 12; ++i)
+                out[((long)k * L5 + s) * 12 + i] = kx[((long)s * V + xs) * 12 + i] - 0.25 * w[s * 12 + i];
+        for (int m2 = 0; m2 < 8; ++m2)   /* clear the scratch entries */
+            for (int s = 0; s < L5; ++s) memset(nb + (long)s * n4 + 12 * ys[m2], 0, 12 * sizeof(cplx));
+    }
+    free(K[0]); free(K[1]); free(A); free(col); free(v); free(w);
+    free(x); free(src); free(kx); free(nb);
 }
 
 /* One CGLS iteration's operator work (S, S^+, and the vector updates) on

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 
 #include "ctx.h"
@@ -254,6 +255,20 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     g.fXh = FastDiv(uint32_t(g.Xh));
     g.fY = FastDiv(uint32_t(g.Y));
     g.fZ = FastDiv(uint32_t(g.Z));
+    g.plane = g.Xh * g.Y;
+    g.zb = (g.Z % 4 == 0) ? 4 : 2;
+    g.xcd_remap = 1;
+    g.nt_store = 0;
+    // launch-shape tuning knobs, read once per context
+    if (const char* e = std::getenv("MDWF_ZBLOCK")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && g.Z % v == 0) g.zb = v;
+    }
+    if (const char* e = std::getenv("MDWF_XCD_REMAP")) g.xcd_remap = std::atoi(e) != 0;
+    if (const char* e = std::getenv("MDWF_NT_STORE")) g.nt_store = std::atoi(e) != 0;
+    g.fPlane = FastDiv(uint32_t(g.plane));
+    g.fZb = FastDiv(uint32_t(g.zb));
+    g.fT = FastDiv(uint32_t(g.T));
     if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
         mdwf_destroy(c);

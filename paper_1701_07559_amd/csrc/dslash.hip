@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     using TR = HopTraits<K>;
     const int L5 = g.L5;
     const int spw = 64 / L5;
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int lb = g.xcd_remap ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
     const int rhs = lb % a.nrhs;
     const int tile = lb / a.nrhs;
     if (a.active && !a.active[rhs]) return;   // uniform over the block
@@ -181,9 +181,24 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     const int lane = tid & 63, wave = tid >> 6;
     const int sw = lane / L5;
     const int s = lane - sw * L5;
-    const int i = (tile * kWaves + wave) * spw + sw;
-    const bool valid = (sw < spw) && (i < g.Vh4);
+    const int pos = (tile * kWaves + wave) * spw + sw;   // traversal position
+    const bool valid = (sw < spw) && (pos < g.Vh4);
     const int gbase = lane - s;
+    // position -> (z-block, t, z in block, plane index) -> coordinates and the
+    // parity-compressed index i of the output site
+    int xh, y, z, t, i;
+    {
+        const uint32_t q = g.fPlane.div(uint32_t(pos));
+        const int yx = pos - int(q) * g.plane;
+        const uint32_t q2 = g.fZb.div(q);
+        const int zz = int(q) - int(q2) * g.zb;
+        const uint32_t q3 = g.fT.div(q2);
+        t = int(q2) - int(q3) * g.T;
+        z = int(q3) * g.zb + zz;
+        y = int(g.fXh.div(uint32_t(yx)));
+        xh = yx - y * g.Xh;
+        i = yx + g.plane * (z + g.Z * t);
+    }
 
     const RhsCoef& cf = a.coef[rhs];
     const R mq = R(cf.mq), b5 = R(cf.b5), c5 = R(cf.c5);
@@ -199,17 +214,6 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     for (int c = 0; c < 12; ++c) res[c] = {R(0), R(0)};
 
     if (valid) {
-        // 4D coordinates of the output site
-        uint32_t r = uint32_t(i);
-        uint32_t q = g.fXh.div(r);
-        const int xh = int(r - q * uint32_t(g.Xh));
-        r = q;
-        q = g.fY.div(r);
-        const int y = int(r - q * uint32_t(g.Y));
-        r = q;
-        q = g.fZ.div(r);
-        const int z = int(r - q * uint32_t(g.Z));
-        const int t = int(q);
         const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
         const int row = i - xh;
         const int sy = g.Xh, sz = g.Xh * g.Y, st = sz * g.Z;
@@ -296,7 +300,8 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) res[c] = hc * res[c];
         }
-        Field<P>::store(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
+        if (g.nt_store) Field<P>::template store<true>(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
+        else Field<P>::store(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
         if (a.partials) {
             R acc = R(0);
 #pragma unroll

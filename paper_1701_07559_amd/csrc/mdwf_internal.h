@@ -78,6 +78,14 @@ struct Geo {
     int Vh;    // 5D sites of one parity = Vh4 * L5
     int antiperiodic;
     FastDiv fXh, fY, fZ;
+    // Traversal order of the hop kernels: z-blocks of zb slices, inside a
+    // block t, then z, then the (x, y) plane of Xh * Y sites.  Neighbours
+    // across t are then zb planes apart instead of a whole time slice.
+    int plane;   // Xh * Y
+    int zb;      // z-block depth, divides Z
+    FastDiv fPlane, fZb, fT;
+    int xcd_remap;   // renumber workgroups per XCD (1) or keep hardware order (0)
+    int nt_store;    // write hop outputs with non-temporal stores
 };
 
 // Coefficients of one right-hand side (its mass); all fifth-dimension
@@ -108,6 +116,16 @@ inline size_t link_segment_bytes(Prec p, size_t Vh4) {
 __host__ __device__ inline size_t norm_offset(size_t Vh) { return align256(48 * Vh); }  // P16 only
 
 // ------------------------------------------------------- native accesses
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
+
+// 16-byte store, optionally non-temporal (streamed past the caches)
+template <bool NT, typename V> __device__ __forceinline__ void st16(V* p, V v) {
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <Prec P> struct Field;
 
 template <> struct Field<P64> {
@@ -120,10 +138,11 @@ template <> struct Field<P64> {
             v[k] = {w.x, w.y};
         }
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(void* base, int Vh, int j, const cx<R> v[12]) {
-        double2* p = static_cast<double2*>(base);
+        nd2* p = static_cast<nd2*>(base);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) p[size_t(k) * Vh + j] = make_double2(v[k].re, v[k].im);
+        for (int k = 0; k < 12; ++k) st16<NT>(p + size_t(k) * Vh + j, nd2{v[k].re, v[k].im});
     }
 };
 
@@ -138,11 +157,12 @@ template <> struct Field<P32> {
             v[2 * k + 1] = {w.z, w.w};
         }
     }
+    template <bool NT = false>
     static __device__ __forceinline__ void store(void* base, int Vh, int j, const cx<R> v[12]) {
-        float4* p = static_cast<float4*>(base);
+        nf4* p = static_cast<nf4*>(base);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            p[size_t(k) * Vh + j] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+            st16<NT>(p + size_t(k) * Vh + j, nf4{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im});
     }
 };
 
@@ -177,27 +197,35 @@ template <> struct Field<P16> {
     }
     // Stores v / norm in binary16 (round to nearest even) with
     // norm = max |re|, |im| over the site; v is replaced by what was stored.
+    // A site whose largest component is below the smallest normal float is
+    // stored as zero (its reciprocal would overflow); NaN propagates.
+    template <bool NT = false>
     static __device__ __forceinline__ void store(void* base, int Vh, int j, cx<R> v[12]) {
         float n = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) n = fmaxf(n, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
-        const float inv = n > 0.f ? 1.0f / n : 0.f;
-        uint4* p = static_cast<uint4*>(base);
+        float inv = 1.0f / n;
+        if (n < 1.17549435e-38f) {
+            n = 0.f;
+            inv = 0.f;
+        }
+        nu4* p = static_cast<nu4*>(base);
         float* nrm = reinterpret_cast<float*>(static_cast<char*>(base) + norm_offset(Vh));
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            uint4 w;
+            nu4 w;
             w.x = pack_h2(v[4 * k], inv);
             w.y = pack_h2(v[4 * k + 1], inv);
             w.z = pack_h2(v[4 * k + 2], inv);
             w.w = pack_h2(v[4 * k + 3], inv);
-            p[size_t(k) * Vh + j] = w;
+            st16<NT>(p + size_t(k) * Vh + j, w);
             unpack_h2(w.x, n, v[4 * k]);
             unpack_h2(w.y, n, v[4 * k + 1]);
             unpack_h2(w.z, n, v[4 * k + 2]);
             unpack_h2(w.w, n, v[4 * k + 3]);
         }
-        nrm[j] = n;
+        if (NT) __builtin_nontemporal_store(n, nrm + j);
+        else nrm[j] = n;
     }
 };
 

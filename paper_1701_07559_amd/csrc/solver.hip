@@ -320,6 +320,10 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
     int it = 0;
     bool pending = false;
     int pend_slot = 0;
+    // Each RHS's update schedule must depend on its own residuals only, so a
+    // refresh of one RHS never shifts the checks of the others: after a
+    // refresh, only the refreshed RHS skip the (pre-refresh) pending copy.
+    std::vector<int> skip(n, 0);
     auto any_active = [&]() {
         for (int k = 0; k < n; ++k)
             if (active[k]) return true;
@@ -349,7 +353,10 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
         std::vector<int> upd(n, 0), rp(n, 0);
         bool any = false;
         for (int k = 0; k < n; ++k) {
-            if (!active[k]) continue;
+            if (!active[k] || skip[k]) {
+                skip[k] = 0;
+                continue;
+            }
             if (h[k].bad || !std::isfinite(h[k].rr)) {
                 stopped[k] = 2;
                 upd[k] = 1;
@@ -362,9 +369,10 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
         }
         if (!any) continue;
         // act on the current state (includes the iteration just enqueued)
-        pending = false;
         S.hipok(hipStreamSynchronize(st), "sync");
         auto rr = refresh(upd, rp);   // keeps p for now; restarts handled below
+        for (int k = 0; k < n; ++k)
+            if (upd[k]) skip[k] = pending ? 1 : 0;
         std::vector<int> chk(n, 0);
         bool any_chk = false;
         for (int k = 0; k < n; ++k) {

@@ -150,6 +150,8 @@ def test_dev_entry_points_roundtrip(M):
     ctx = make_ctx(M, act, U)
     try:
         dev = torch.device("cuda:0")
+        side = torch.cuda.Stream(device=dev)
+        torch.cuda.set_stream(side)
         for prec in (0, 1, 2):
             nb = M.mdwf_field_bytes(ctx, prec, M.MDWF_FULL)
             a = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -163,6 +165,40 @@ def test_dev_entry_points_roundtrip(M):
             torch.cuda.synchronize()
             got = outc.cpu().numpy().view(np.complex128).reshape(psi.shape)
             assert rel(got, oracle.D5(act, U, psi)) <= TOL[prec]
+    finally:
+        torch.cuda.set_stream(torch.cuda.default_stream())
+        M.mdwf_destroy(ctx)
+
+
+def test_fp16_store_of_sites_below_float_range(M):
+    """A 5D site whose largest component is below the smallest normal float
+    is stored as zero in FP16 (its norm's reciprocal would overflow and turn
+    zero components into NaN); ordinary sites keep their per-site precision."""
+    import torch
+    dims, L5 = (4, 2, 2, 2), 4
+    act = oracle.Action(dims, L5)
+    ctx = make_ctx(M, act, I.unit_links(dims))
+    try:
+        psi = I.gaussian_source(dims, L5, 48)
+        psi[1, 0, 0, 0, 0] *= 1e-40      # denormal in FP32
+        psi[2, 1, 1, 1, 3] = 0.0          # an all-zero site
+        psi[2, 1, 1, 1, 3, 0, 0] = 3e-39  # one denormal component
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            canon = torch.from_numpy(psi.view(np.float64).copy()).cuda()
+            nat = torch.empty(M.mdwf_field_bytes(ctx, 2, M.MDWF_FULL), dtype=torch.uint8, device="cuda")
+            back = torch.empty_like(canon)
+            M.mdwf_pack_dev(ctx, 2, M.MDWF_FULL, canon.data_ptr(), nat.data_ptr(), side.cuda_stream)
+            M.mdwf_unpack_dev(ctx, 2, M.MDWF_FULL, nat.data_ptr(), back.data_ptr(), side.cuda_stream)
+        torch.cuda.synchronize()
+        got = back.cpu().numpy().view(np.complex128).reshape(psi.shape)
+        assert np.all(np.isfinite(got))
+        assert np.all(got[1, 0, 0, 0, 0] == 0) and np.all(got[2, 1, 1, 1, 3] == 0)
+        mask = np.ones(psi.shape[:5], bool)
+        mask[1, 0, 0, 0, 0] = mask[2, 1, 1, 1, 3] = False
+        site_max = np.abs(np.stack([psi.real, psi.imag])).max(axis=(0, 6, 7))
+        err = np.abs(got - psi).max(axis=(5, 6))
+        assert np.all(err[mask] <= 2 ** -11 * site_max[mask] * 1.0001)
     finally:
         M.mdwf_destroy(ctx)
 
@@ -251,10 +287,13 @@ def test_solve_dev_with_torch_buffers(M, cfg1):
     ctx = make_ctx(M, act, U)
     try:
         dev = torch.device("cuda:0")
-        bt = torch.from_numpy(b.view(np.float64).copy()).to(dev)
-        xt = torch.zeros_like(bt)
-        st, info = M.mdwf_solve_dev(ctx, [bt.data_ptr()], [xt.data_ptr()], opts=dict(inner=2),
-                                    stream=torch.cuda.current_stream().cuda_stream)
+        side = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(side):
+            bt = torch.from_numpy(b.view(np.float64).copy()).to(dev)
+            xt = torch.zeros_like(bt)
+            st, info = M.mdwf_solve_dev(ctx, [bt.data_ptr()], [xt.data_ptr()], opts=dict(inner=2),
+                                        stream=side.cuda_stream)
+        torch.cuda.synchronize()
         assert st == M.MDWF_OK
         x = xt.cpu().numpy().view(np.complex128).reshape(b.shape)
         assert oracle.true_residual(act, U, b, x) <= 1e-10
