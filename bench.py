@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--micro-only", action="store_true", help="time the operator kernels and stop")
     ap.add_argument("--micro-reps", type=int, default=50)
     ap.add_argument("--micro-precs", default="f64,f32,f16")
@@ -144,6 +145,12 @@ def main():
     M.mdwf_load_gauge(ctx, U)
     stream = work.cuda_stream
     assert stream and torch.cuda.current_stream().cuda_stream == stream
+    tune = None
+    if not args.no_tune:
+        tune = M.mdwf_autotune(ctx)
+        for pn, t in zip(("f64", "f32", "f16"), tune):
+            log("autotune %s: zblock %d xcd_remap %d nt_store %d  schur %.1f us" %
+                (pn, t["zblock"], t["xcd_remap"], t["nt_store"], t["us"]))
 
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -260,6 +267,7 @@ def main():
                         "%d point-source columns, one multi-RHS %s-inner solve to true residual 1e-10" %
                         (plaq, nrhs, args.inner),
             "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "inner": args.inner,
+            "launch_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), tune)} if tune else None),
         },
         "solve": {
             "seconds": round(ms_per_step / 1e3, 4),

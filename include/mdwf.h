@@ -188,6 +188,24 @@ mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, 
  * check_every 1, use_graph 0. */
 void mdwf_default_opts(mdwf_solver_opts *opts);
 
+/* Launch shape of the hop kernels for one storage precision. */
+typedef struct {
+    int zblock;      /* traversal: z-blocks of this many z-planes, t inside (divides Z) */
+    int xcd_remap;   /* 1: workgroups renumbered so each XCD walks one contiguous range */
+    int nt_store;    /* 1: hop outputs written with non-temporal stores               */
+    double us;       /* measured time of one Schur application with this shape (us)   */
+} mdwf_launch_tune;
+
+/* Autotuner: for each precision (index mdwf_prec), time one Schur operator
+ * application (the two fused hop kernels) for every candidate launch shape on
+ * scratch fields and keep the fastest in the context.  out[3] (may be NULL)
+ * receives the chosen shapes.  Needs the action and gauge field; allocates
+ * scratch device memory (three half fields of each precision). */
+mdwf_status mdwf_autotune(mdwf_ctx *ctx, mdwf_launch_tune *out);
+
+/* Current launch shape of precision `prec` (defaults before autotuning). */
+mdwf_status mdwf_get_tune(const mdwf_ctx *ctx, mdwf_prec prec, mdwf_launch_tune *out);
+
 /* Model flop and byte counts for one application of an operator (per call). */
 mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, double *flops, double *bytes);
 

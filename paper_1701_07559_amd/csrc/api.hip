@@ -112,6 +112,13 @@ void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes) {
     *bytes = b * Vh;
 }
 
+void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
+    g.zb[p] = t.zblock;
+    g.fZb[p] = FastDiv(uint32_t(t.zblock));
+    g.xcd_remap[p] = t.xcd_remap ? 1 : 0;
+    g.nt_store[p] = t.nt_store ? 1 : 0;
+}
+
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
                          const RhsCoef* d_coef, const int* d_active, hipStream_t st) {
     const Geo& g = c->geo;
@@ -256,19 +263,18 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     g.fY = FastDiv(uint32_t(g.Y));
     g.fZ = FastDiv(uint32_t(g.Z));
     g.plane = g.Xh * g.Y;
-    g.zb = (g.Z % 4 == 0) ? 4 : 2;
-    g.xcd_remap = 1;
-    g.nt_store = 0;
-    // launch-shape tuning knobs, read once per context
+    g.fPlane = FastDiv(uint32_t(g.plane));
+    g.fT = FastDiv(uint32_t(g.T));
+    // default launch shape (mdwf_autotune refines it per precision); the
+    // MDWF_ZBLOCK / MDWF_XCD_REMAP / MDWF_NT_STORE variables override it
+    mdwf_launch_tune t0{(g.Z % 4 == 0) ? 4 : 2, 1, 0, 0.0};
     if (const char* e = std::getenv("MDWF_ZBLOCK")) {
         const int v = std::atoi(e);
-        if (v >= 1 && g.Z % v == 0) g.zb = v;
+        if (v >= 1 && g.Z % v == 0) t0.zblock = v;
     }
-    if (const char* e = std::getenv("MDWF_XCD_REMAP")) g.xcd_remap = std::atoi(e) != 0;
-    if (const char* e = std::getenv("MDWF_NT_STORE")) g.nt_store = std::atoi(e) != 0;
-    g.fPlane = FastDiv(uint32_t(g.plane));
-    g.fZb = FastDiv(uint32_t(g.zb));
-    g.fT = FastDiv(uint32_t(g.T));
+    if (const char* e = std::getenv("MDWF_XCD_REMAP")) t0.xcd_remap = std::atoi(e) != 0;
+    if (const char* e = std::getenv("MDWF_NT_STORE")) t0.nt_store = std::atoi(e) != 0;
+    for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
     if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
         mdwf_destroy(c);
@@ -443,6 +449,70 @@ mdwf_status mdwf_op_model(const mdwf_ctx* c, mdwf_op op, mdwf_prec prec, double*
     if (!valid_prec(prec) || op < 0 || op >= MDWF_OP_COUNT) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "bad operator or precision");
     op_model(c->geo, op, Prec(prec), flops, bytes);
     return MDWF_OK;
+}
+
+mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* out) {
+    if (!c || !out) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "null argument");
+    if (!valid_prec(prec)) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "bad precision");
+    out->zblock = c->geo.zb[prec];
+    out->xcd_remap = c->geo.xcd_remap[prec];
+    out->nt_store = c->geo.nt_store[prec];
+    out->us = c->tuned_us[prec];
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    Geo& g = c->geo;
+    hipStream_t st = c->stream;
+    // candidate z-block depths: small powers of two dividing Z, and Z itself
+    std::vector<int> zbs;
+    for (int v : {1, 2, 4, 8, 16})
+        if (g.Z % v == 0) zbs.push_back(v);
+    if (g.Z > 16) zbs.push_back(g.Z);
+    const size_t canon = size_t(g.Vh) * 24 * sizeof(double);
+    void* cin = buf(c, "tune_canon", canon, &s);
+    if (!cin) return s;
+    // any finite, normal pattern: timing does not depend on the values
+    if ((s = hip_check(c, hipMemsetAsync(cin, 0x3f, canon, st), "memset"))) return s;
+    hipEvent_t e0, e1;
+    if ((s = hip_check(c, hipEventCreate(&e0), "event"))) return s;
+    if ((s = hip_check(c, hipEventCreate(&e1), "event"))) return s;
+    for (int pi = 0; pi < 3; ++pi) {
+        const Prec p = Prec(pi);
+        const size_t hb = half_field_bytes(p, g.Vh);
+        void* a = buf(c, "tune_a", 2 * half_field_bytes(P64, g.Vh), &s);
+        void* b = a ? buf(c, "tune_b", 2 * half_field_bytes(P64, g.Vh), &s) : nullptr;
+        if (!a || !b) break;
+        launch_pack_parity(g, p, 0, 0, static_cast<const double*>(cin), a, st);
+        mdwf_launch_tune best{g.zb[p], g.xcd_remap[p], g.nt_store[p], 1e30};
+        for (int zb : zbs)
+            for (int rm = 1; rm >= 0; --rm)
+                for (int nt = 0; nt <= 1; ++nt) {
+                    mdwf_launch_tune cand{zb, rm, nt, 0.0};
+                    set_tune(g, p, cand);
+                    const int warm = 2, reps = 5;
+                    for (int r = 0; r < warm; ++r)
+                        if ((s = apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st))) break;
+                    if (s) break;
+                    (void)hipEventRecord(e0, st);
+                    for (int r = 0; r < reps; ++r) apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st);
+                    (void)hipEventRecord(e1, st);
+                    if ((s = hip_check(c, hipEventSynchronize(e1), "autotune"))) break;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    cand.us = 1e3 * ms / reps;
+                    if (cand.us < best.us) best = cand;
+                }
+        if (s) break;
+        set_tune(g, p, best);
+        c->tuned_us[pi] = best.us;
+        if (out) out[pi] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
 }
 
 mdwf_status mdwf_solve_dev(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, const double* mq,

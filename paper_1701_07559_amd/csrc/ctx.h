@@ -33,6 +33,8 @@ struct mdwf_ctx {
     // pinned host staging for scalars
     void* h_pin = nullptr;
     size_t h_pin_n = 0;
+    // autotuned time of one Schur application per precision (0 = not tuned)
+    double tuned_us[3] = {0.0, 0.0, 0.0};
 };
 
 namespace mdwf {
@@ -47,6 +49,9 @@ void* pinned(mdwf_ctx* c, size_t n, mdwf_status* st);
 
 // Coefficients of the fifth-dimension polynomials for mass mq.
 RhsCoef make_coef(const mdwf_action& a, double mq);
+
+// Install a launch shape for one precision in the geometry.
+void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t);
 
 // Native-layout operator application on `nrhs` right-hand sides stored at
 // byte stride `stride` (half fields; a full field is two consecutive halves of

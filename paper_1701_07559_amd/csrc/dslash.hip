@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     using TR = HopTraits<K>;
     const int L5 = g.L5;
     const int spw = 64 / L5;
-    const int lb = g.xcd_remap ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
+    const int lb = g.xcd_remap[P] ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
     const int rhs = lb % a.nrhs;
     const int tile = lb / a.nrhs;
     if (a.active && !a.active[rhs]) return;   // uniform over the block
@@ -188,13 +188,14 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     // parity-compressed index i of the output site
     int xh, y, z, t, i;
     {
+        const int zb = g.zb[P];
         const uint32_t q = g.fPlane.div(uint32_t(pos));
         const int yx = pos - int(q) * g.plane;
-        const uint32_t q2 = g.fZb.div(q);
-        const int zz = int(q) - int(q2) * g.zb;
+        const uint32_t q2 = g.fZb[P].div(q);
+        const int zz = int(q) - int(q2) * zb;
         const uint32_t q3 = g.fT.div(q2);
         t = int(q2) - int(q3) * g.T;
-        z = int(q3) * g.zb + zz;
+        z = int(q3) * zb + zz;
         y = int(g.fXh.div(uint32_t(yx)));
         xh = yx - y * g.Xh;
         i = yx + g.plane * (z + g.Z * t);
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) res[c] = hc * res[c];
         }
-        if (g.nt_store) Field<P>::template store<true>(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
+        if (g.nt_store[P]) Field<P>::template store<true>(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
         else Field<P>::store(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
         if (a.partials) {
             R acc = R(0);

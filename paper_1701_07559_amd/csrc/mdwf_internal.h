@@ -82,10 +82,12 @@ struct Geo {
     // block t, then z, then the (x, y) plane of Xh * Y sites.  Neighbours
     // across t are then zb planes apart instead of a whole time slice.
     int plane;   // Xh * Y
-    int zb;      // z-block depth, divides Z
-    FastDiv fPlane, fZb, fT;
-    int xcd_remap;   // renumber workgroups per XCD (1) or keep hardware order (0)
-    int nt_store;    // write hop outputs with non-temporal stores
+    FastDiv fPlane, fT;
+    // launch shape per storage precision (index Prec), set by the autotuner
+    int zb[3];          // z-block depth, divides Z
+    FastDiv fZb[3];
+    int xcd_remap[3];   // renumber workgroups per XCD (1) or keep hardware order (0)
+    int nt_store[3];    // write hop outputs with non-temporal stores
 };
 
 // Coefficients of one right-hand side (its mass); all fifth-dimension

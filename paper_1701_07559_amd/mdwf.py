@@ -60,6 +60,13 @@ class mdwf_solve_info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mdwf_launch_tune(C.Structure):
+    _fields_ = [("zblock", C.c_int), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("us", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class MdwfError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS_NAMES[status] if 0 <= status < 7 else status, msg))
@@ -106,6 +113,8 @@ def _load():
                             C.POINTER(mdwf_solve_info), vp], ip),
         "mdwf_default_opts": ([C.POINTER(mdwf_solver_opts)], None),
         "mdwf_op_model": ([vp, ip, ip, C.POINTER(dp), C.POINTER(dp)], ip),
+        "mdwf_autotune": ([vp, C.POINTER(mdwf_launch_tune)], ip),
+        "mdwf_get_tune": ([vp, ip, C.POINTER(mdwf_launch_tune)], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -236,8 +245,22 @@ def mdwf_op_model(ctx, op, prec):
     return f.value, b.value
 
 
+def mdwf_autotune(ctx):
+    """Autotune the hop kernels' launch shape per precision; returns 3 dicts."""
+    out = (mdwf_launch_tune * 3)()
+    _check(ctx, lib.mdwf_autotune(ctx, out))
+    return [o.as_dict() for o in out]
+
+
+def mdwf_get_tune(ctx, prec):
+    t = mdwf_launch_tune()
+    _check(ctx, lib.mdwf_get_tune(ctx, int(prec), C.byref(t)))
+    return t.as_dict()
+
+
 def exported_symbols():
     """Names of the C entry points declared in include/mdwf.h."""
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
-            "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model"]
+            "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
+            "mdwf_autotune", "mdwf_get_tune"]
