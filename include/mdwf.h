@@ -193,6 +193,7 @@ typedef struct {
     int zblock;      /* traversal: z-blocks of this many z-planes, t inside (divides Z) */
     int xcd_remap;   /* 1: workgroups renumbered so each XCD walks one contiguous range */
     int nt_store;    /* 1: hop outputs written with non-temporal stores               */
+    int link_lds;    /* 1: links staged in LDS, one fetch per site (needs L5 >= 8)    */
     double us;       /* measured time of one Schur application with this shape (us)   */
 } mdwf_launch_tune;
 

@@ -117,6 +117,7 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
     g.fZb[p] = FastDiv(uint32_t(t.zblock));
     g.xcd_remap[p] = t.xcd_remap ? 1 : 0;
     g.nt_store[p] = t.nt_store ? 1 : 0;
+    g.link_lds[p] = t.link_lds ? 1 : 0;
 }
 
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
@@ -267,13 +268,14 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     g.fT = FastDiv(uint32_t(g.T));
     // default launch shape (mdwf_autotune refines it per precision); the
     // MDWF_ZBLOCK / MDWF_XCD_REMAP / MDWF_NT_STORE variables override it
-    mdwf_launch_tune t0{(g.Z % 4 == 0) ? 4 : 2, 1, 0, 0.0};
+    mdwf_launch_tune t0{(g.Z % 4 == 0) ? 4 : 2, 1, 0, 0, 0.0};
     if (const char* e = std::getenv("MDWF_ZBLOCK")) {
         const int v = std::atoi(e);
         if (v >= 1 && g.Z % v == 0) t0.zblock = v;
     }
     if (const char* e = std::getenv("MDWF_XCD_REMAP")) t0.xcd_remap = std::atoi(e) != 0;
     if (const char* e = std::getenv("MDWF_NT_STORE")) t0.nt_store = std::atoi(e) != 0;
+    if (const char* e = std::getenv("MDWF_LINK_LDS")) t0.link_lds = std::atoi(e) != 0;
     for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
     if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
@@ -457,6 +459,7 @@ mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* o
     out->zblock = c->geo.zb[prec];
     out->xcd_remap = c->geo.xcd_remap[prec];
     out->nt_store = c->geo.nt_store[prec];
+    out->link_lds = c->geo.link_lds[prec];
     out->us = c->tuned_us[prec];
     return MDWF_OK;
 }
@@ -486,11 +489,13 @@ mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
         void* b = a ? buf(c, "tune_b", 2 * half_field_bytes(P64, g.Vh), &s) : nullptr;
         if (!a || !b) break;
         launch_pack_parity(g, p, 0, 0, static_cast<const double*>(cin), a, st);
-        mdwf_launch_tune best{g.zb[p], g.xcd_remap[p], g.nt_store[p], 1e30};
+        mdwf_launch_tune best{g.zb[p], g.xcd_remap[p], g.nt_store[p], g.link_lds[p], 1e30};
+        const int max_lds = (64 / g.L5 <= 8) ? 1 : 0;
         for (int zb : zbs)
             for (int rm = 1; rm >= 0; --rm)
-                for (int nt = 0; nt <= 1; ++nt) {
-                    mdwf_launch_tune cand{zb, rm, nt, 0.0};
+                for (int nt = 0; nt <= 1; ++nt)
+                for (int ll = 0; ll <= max_lds; ++ll) {
+                    mdwf_launch_tune cand{zb, rm, nt, ll, 0.0};
                     set_tune(g, p, cand);
                     const int warm = 2, reps = 5;
                     for (int r = 0; r < warm; ++r)

@@ -145,20 +145,208 @@ template <int K> struct HopTraits {
                                  : (K == HOP_PREP) ? 0.5 : 1.0;
 };
 
-template <Prec P, bool DAG, bool PREB, int MU, int DIR>
-__device__ __forceinline__ void hop_dir(cx<typename Real<P>::T> acc[12], const char* lseg, int li, int Vh4,
-                                        const void* in, int Vh, int jn, const Nbr5<typename Real<P>::T>& nb,
-                                        typename Real<P>::T b5, typename Real<P>::T c5) {
-    using R = typename Real<P>::T;
-    cx<R> U[9];
-    Link<P>::load(lseg, Vh4, li, U);
-    cx<R> psi[12];
-    Field<P>::load(in, Vh, jn, psi);
-    if (PREB) {
-        cx<R> cpsi[12];
-        apply_C_lanes<R, false>(nb, psi, cpsi);
+// ------------------------------------------------------ neighbour loads
+// Raw registers of one direction: the link and the neighbour spinor exactly
+// as stored.  Addresses are a wave-uniform block base plus a 32-bit lane
+// offset (the offset of a 16-byte element inside one block stays below 4 GB
+// for every lattice this library accepts), so the loads use scalar-base
+// addressing and cost one VGPR of address per direction.
+template <typename V> __device__ __forceinline__ V ldu(const char* base, uint32_t byte_off) {
+    return *reinterpret_cast<const V*>(base + byte_off);
+}
+typedef float nf2 __attribute__((ext_vector_type(2)));
+
+template <Prec P> struct Raw;
+
+template <> struct Raw<P64> {
+    nd2 s[12], u[9];
+    __device__ __forceinline__ void load(const char* lseg, uint32_t li, size_t lblk, const char* in, uint32_t jn,
+                                         size_t sblk, bool with_link) {
+        const uint32_t lo = li * 16u, so = jn * 16u;
+        if (with_link)
 #pragma unroll
-        for (int c = 0; c < 12; ++c) psi[c] = b5 * psi[c] + c5 * cpsi[c];
+            for (int k = 0; k < 9; ++k) u[k] = ldu<nd2>(lseg + k * lblk, lo);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s[k] = ldu<nd2>(in + k * sblk, so);
+    }
+    __device__ __forceinline__ void link(cx<double> U[9]) const {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) U[k] = {u[k].x, u[k].y};
+    }
+    __device__ __forceinline__ void spinor(cx<double> v[12]) const {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = {s[k].x, s[k].y};
+    }
+};
+
+template <> struct Raw<P32> {
+    nf4 s[6], u[4];
+    nf2 u8;
+    __device__ __forceinline__ void load(const char* lseg, uint32_t li, size_t lblk, const char* in, uint32_t jn,
+                                         size_t sblk, bool with_link) {
+        const uint32_t lo = li * 16u, so = jn * 16u;
+        if (with_link) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k] = ldu<nf4>(lseg + k * lblk, lo);
+            u8 = ldu<nf2>(lseg + 4 * lblk, li * 8u);   // 9th element: float2 block after the four float4 blocks
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] = ldu<nf4>(in + k * sblk, so);
+    }
+    __device__ __forceinline__ void link(cx<float> U[9]) const {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            U[2 * k] = {u[k].x, u[k].y};
+            U[2 * k + 1] = {u[k].z, u[k].w};
+        }
+        U[8] = {u8.x, u8.y};
+    }
+    __device__ __forceinline__ void spinor(cx<float> v[12]) const {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            v[2 * k] = {s[k].x, s[k].y};
+            v[2 * k + 1] = {s[k].z, s[k].w};
+        }
+    }
+};
+
+template <> struct Raw<P16> {
+    nu4 s[3], u[2];
+    uint32_t u8;
+    float n;
+    __device__ __forceinline__ void load(const char* lseg, uint32_t li, size_t lblk, const char* in, uint32_t jn,
+                                         size_t sblk, bool with_link) {
+        const uint32_t lo = li * 16u, so = jn * 16u;
+        if (with_link) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) u[k] = ldu<nu4>(lseg + k * lblk, lo);
+            u8 = ldu<uint32_t>(lseg + 2 * lblk, li * 4u);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = ldu<nu4>(in + k * sblk, so);
+        n = ldu<float>(in + align256(3 * sblk), jn * 4u);   // norm block (see norm_offset)
+    }
+    __device__ __forceinline__ void link(cx<float> U[9]) const {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            unpack_h2(u[k].x, 1.f, U[4 * k]);
+            unpack_h2(u[k].y, 1.f, U[4 * k + 1]);
+            unpack_h2(u[k].z, 1.f, U[4 * k + 2]);
+            unpack_h2(u[k].w, 1.f, U[4 * k + 3]);
+        }
+        unpack_h2(u8, 1.f, U[8]);
+    }
+    __device__ __forceinline__ void spinor(cx<float> v[12]) const {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            unpack_h2(s[k].x, n, v[4 * k]);
+            unpack_h2(s[k].y, n, v[4 * k + 1]);
+            unpack_h2(s[k].z, n, v[4 * k + 2]);
+            unpack_h2(s[k].w, n, v[4 * k + 3]);
+        }
+    }
+    // B psi with the slice neighbours' packed words and norms exchanged
+    // (6 + 6 + 2 lane swaps instead of 24 on unpacked floats)
+    __device__ __forceinline__ void spinor_B(const Nbr5<float>& nb, float b5, float c5, cx<float> v[12]) const {
+        const uint32_t up[6] = {s[0].x, s[0].y, s[0].z, s[0].w, s[1].x, s[1].y};
+        const uint32_t dn[6] = {s[1].z, s[1].w, s[2].x, s[2].y, s[2].z, s[2].w};
+        const float nu = bperm(nb.am1, n) * nb.fm1 * c5;   // (C psi) upper comes from slice s-1
+        const float nd = bperm(nb.ap1, n) * nb.fp1 * c5;   // lower from slice s+1
+        const float nb5 = n * b5;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const uint32_t o = uint32_t(__builtin_amdgcn_ds_bpermute(nb.am1, int(up[k])));
+            cx<float> mine, other;
+            unpack_h2(up[k], nb5, mine);
+            unpack_h2(o, nu, other);
+            v[k] = mine + other;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const uint32_t o = uint32_t(__builtin_amdgcn_ds_bpermute(nb.ap1, int(dn[k])));
+            cx<float> mine, other;
+            unpack_h2(dn[k], nb5, mine);
+            unpack_h2(o, nd, other);
+            v[6 + k] = mine + other;
+        }
+    }
+};
+
+// Links staged in LDS: 16-byte parts of the 18-real link.  Lane s of a site
+// group copies parts s, s + L5, ... of each of its site's eight links; every
+// lane then reads its site's links back (a broadcast inside the group), so a
+// link crosses the vector-memory path once per site instead of once per lane.
+template <Prec P> struct LinkStage;
+template <> struct LinkStage<P64> {
+    static constexpr int NP = 9;
+    static __device__ __forceinline__ void copy_part(const char* seg, size_t lblk, uint32_t idx, int b,
+                                                     unsigned char* dst) {
+        *reinterpret_cast<nd2*>(dst) = ldu<nd2>(seg + b * lblk, idx * 16u);
+    }
+    static __device__ __forceinline__ void read(const unsigned char* slot, cx<double> U[9]) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const nd2 w = reinterpret_cast<const nd2*>(slot)[k];
+            U[k] = {w.x, w.y};
+        }
+    }
+};
+template <> struct LinkStage<P32> {
+    static constexpr int NP = 5;
+    static __device__ __forceinline__ void copy_part(const char* seg, size_t lblk, uint32_t idx, int b,
+                                                     unsigned char* dst) {
+        if (b < 4) *reinterpret_cast<nf4*>(dst) = ldu<nf4>(seg + b * lblk, idx * 16u);
+        else *reinterpret_cast<nf2*>(dst) = ldu<nf2>(seg + 4 * lblk, idx * 8u);
+    }
+    static __device__ __forceinline__ void read(const unsigned char* slot, cx<float> U[9]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const nf4 w = reinterpret_cast<const nf4*>(slot)[k];
+            U[2 * k] = {w.x, w.y};
+            U[2 * k + 1] = {w.z, w.w};
+        }
+        const nf2 w = *reinterpret_cast<const nf2*>(slot + 64);
+        U[8] = {w.x, w.y};
+    }
+};
+template <> struct LinkStage<P16> {
+    static constexpr int NP = 3;
+    static __device__ __forceinline__ void copy_part(const char* seg, size_t lblk, uint32_t idx, int b,
+                                                     unsigned char* dst) {
+        if (b < 2) *reinterpret_cast<nu4*>(dst) = ldu<nu4>(seg + b * lblk, idx * 16u);
+        else *reinterpret_cast<uint32_t*>(dst) = ldu<uint32_t>(seg + 2 * lblk, idx * 4u);
+    }
+    static __device__ __forceinline__ void read(const unsigned char* slot, cx<float> U[9]) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const nu4 w = reinterpret_cast<const nu4*>(slot)[k];
+            unpack_h2(w.x, 1.f, U[4 * k]);
+            unpack_h2(w.y, 1.f, U[4 * k + 1]);
+            unpack_h2(w.z, 1.f, U[4 * k + 2]);
+            unpack_h2(w.w, 1.f, U[4 * k + 3]);
+        }
+        unpack_h2(*reinterpret_cast<const uint32_t*>(slot + 32), 1.f, U[8]);
+    }
+};
+
+// Accumulate one direction's term from its spinor registers and link.
+template <Prec P, bool DAG, bool PREB, int MU, int DIR>
+__device__ __forceinline__ void hop_term(cx<typename Real<P>::T> acc[12], const Raw<P>& r,
+                                         const cx<typename Real<P>::T> U[9],
+                                         const Nbr5<typename Real<P>::T>& nb, typename Real<P>::T b5,
+                                         typename Real<P>::T c5) {
+    using R = typename Real<P>::T;
+    cx<R> psi[12];
+    if constexpr (P == P16 && PREB) {
+        r.spinor_B(nb, b5, c5, psi);
+    } else {
+        r.spinor(psi);
+        if (PREB) {
+            cx<R> cpsi[12];
+            apply_C_lanes<R, false>(nb, psi, cpsi);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) psi[c] = b5 * psi[c] + c5 * cpsi[c];
+        }
     }
     constexpr R sg = ((DIR > 0) != DAG) ? R(1) : R(-1);
     cx<R> h[6], w[6];
@@ -167,7 +355,23 @@ __device__ __forceinline__ void hop_dir(cx<typename Real<P>::T> acc[12], const c
     reconstruct_add<MU>(sg, w, acc);
 }
 
-template <Prec P, int K>
+// Direction d of the fixed order x+, x-, y+, y-, z+, z-, t+, t-: the link
+// comes from the LDS stage or from the raw registers.
+template <Prec P, bool DAG, bool PREB, int D, bool STAGED>
+__device__ __forceinline__ void dir_term(cx<typename Real<P>::T> acc[12], const Raw<P>& r,
+                                         const unsigned char* slot, const Nbr5<typename Real<P>::T>& nb,
+                                         typename Real<P>::T b5, typename Real<P>::T c5) {
+    cx<typename Real<P>::T> U[9];
+    if constexpr (STAGED) LinkStage<P>::read(slot, U);
+    else r.link(U);
+    hop_term<P, DAG, PREB, D / 2, (D % 2 == 0) ? +1 : -1>(acc, r, U, nb, b5, c5);
+}
+
+// STAGE: links staged in LDS (requires at most kStageSites sites per wave,
+// i.e. L5 >= 8); otherwise every lane loads its links itself.
+constexpr int kStageSites = 8;
+
+template <Prec P, int K, bool STAGE>
 __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     using R = typename Real<P>::T;
     using TR = HopTraits<K>;
@@ -214,37 +418,84 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) res[c] = {R(0), R(0)};
 
-    if (valid) {
-        const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
-        const int row = i - xh;
-        const int sy = g.Xh, sz = g.Xh * g.Y, st = sz * g.Z;
-        const int n_xp = row + ((x + 1 == g.X ? 0 : x + 1) >> 1);
-        const int n_xm = row + ((x == 0 ? g.X - 1 : x - 1) >> 1);
-        const int n_yp = i + (y == g.Y - 1 ? -(g.Y - 1) * sy : sy);
-        const int n_ym = i + (y == 0 ? (g.Y - 1) * sy : -sy);
-        const int n_zp = i + (z == g.Z - 1 ? -(g.Z - 1) * sz : sz);
-        const int n_zm = i + (z == 0 ? (g.Z - 1) * sz : -sz);
-        const int n_tp = i + (t == g.T - 1 ? -(g.T - 1) * st : st);
-        const int n_tm = i + (t == 0 ? (g.T - 1) * st : -st);
+    // neighbours of the output site (used only by valid lanes)
+    const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+    const int row = i - xh;
+    const int sy = g.Xh, sz = g.Xh * g.Y, st = sz * g.Z;
+    const int n_xp = row + ((x + 1 == g.X ? 0 : x + 1) >> 1);
+    const int n_xm = row + ((x == 0 ? g.X - 1 : x - 1) >> 1);
+    const int n_yp = i + (y == g.Y - 1 ? -(g.Y - 1) * sy : sy);
+    const int n_ym = i + (y == 0 ? (g.Y - 1) * sy : -sy);
+    const int n_zp = i + (z == g.Z - 1 ? -(g.Z - 1) * sz : sz);
+    const int n_zm = i + (z == 0 ? (g.Z - 1) * sz : -sz);
+    const int n_tp = i + (t == g.T - 1 ? -(g.T - 1) * st : st);
+    const int n_tm = i + (t == 0 ? (g.T - 1) * st : -st);
 
-        const char* lo = a.links_out;
-        const char* li = a.links_in;
-        const size_t ls = a.lseg;
-        constexpr bool D = TR::dag, PB = TR::preB;
-        hop_dir<P, D, PB, 0, +1>(res, lo + 0 * ls, i, g.Vh4, in, g.Vh, n_xp * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 0, -1>(res, li + 0 * ls, n_xm, g.Vh4, in, g.Vh, n_xm * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 1, +1>(res, lo + 1 * ls, i, g.Vh4, in, g.Vh, n_yp * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 1, -1>(res, li + 1 * ls, n_ym, g.Vh4, in, g.Vh, n_ym * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 2, +1>(res, lo + 2 * ls, i, g.Vh4, in, g.Vh, n_zp * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 2, -1>(res, li + 2 * ls, n_zm, g.Vh4, in, g.Vh, n_zm * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 3, +1>(res, lo + 3 * ls, i, g.Vh4, in, g.Vh, n_tp * L5 + s, nb, b5, c5);
-        hop_dir<P, D, PB, 3, -1>(res, li + 3 * ls, n_tm, g.Vh4, in, g.Vh, n_tm * L5 + s, nb, b5, c5);
+    // links: segment mu of the output parity at i (forward) and of the input
+    // parity at the backward neighbour
+    const size_t ls = a.lseg;
+    const size_t lblk = size_t(g.Vh4) * 16;
+    const size_t sblk = size_t(g.Vh) * 16;
+    const char* lo = a.links_out;
+    const char* lk = a.links_in;
+    const char* src = static_cast<const char*>(in);
+    constexpr bool D = TR::dag, PB = TR::preB;
+    const uint32_t ui = uint32_t(i);
+    const char* seg[8] = {lo, lk, lo + ls, lk + ls, lo + 2 * ls, lk + 2 * ls, lo + 3 * ls, lk + 3 * ls};
+    const uint32_t lidx[8] = {ui, uint32_t(n_xm), ui, uint32_t(n_ym), ui, uint32_t(n_zm), ui, uint32_t(n_tm)};
+    const uint32_t jn[8] = {uint32_t(n_xp * L5 + s), uint32_t(n_xm * L5 + s), uint32_t(n_yp * L5 + s),
+                            uint32_t(n_ym * L5 + s), uint32_t(n_zp * L5 + s), uint32_t(n_zm * L5 + s),
+                            uint32_t(n_tp * L5 + s), uint32_t(n_tm * L5 + s)};
+
+    // LDS: link stage (when a wave holds at most kStageSites sites) and, for
+    // kernels A / A^+, the epilogue tile, which reuses the same bytes
+    constexpr int NP = LinkStage<P>::NP;
+    constexpr int kDirBytes = kStageSites * NP * 16;
+    constexpr int kLinkBytes = STAGE ? kWaves * 8 * kDirBytes : 0;
+    constexpr int kEpiBytes = (TR::epi == 1 || TR::epi == 2) ? 12 * kBlock * int(sizeof(cx<R>)) : 0;
+    constexpr int kSmem = kLinkBytes > kEpiBytes ? kLinkBytes : kEpiBytes;
+    __shared__ __align__(16) unsigned char smem[kSmem > 0 ? kSmem : 16];
+    constexpr bool staged = STAGE;
+    unsigned char* lslot = smem + size_t(wave) * 8 * kDirBytes + size_t(sw) * NP * 16;
+    if constexpr (STAGE) {
+        if (valid) {
+            for (int b = s; b < NP; b += L5)
+#pragma unroll
+                for (int d = 0; d < 8; ++d)
+                    LinkStage<P>::copy_part(seg[d], lblk, lidx[d], b, lslot + d * kDirBytes + b * 16);
+        }
+        __syncthreads();
+    }
+
+    if (valid) {
+        if constexpr (P == P64) {
+            // FP64: one direction in flight (two would exceed the register file)
+            Raw<P> r;
+#define MDWF_DIR(d)                                                                 \
+    r.load(seg[d], lidx[d], lblk, src, jn[d], sblk, !staged);                      \
+    dir_term<P, D, PB, d, STAGE>(res, r, lslot + (d) * kDirBytes, nb, b5, c5);
+            MDWF_DIR(0) MDWF_DIR(1) MDWF_DIR(2) MDWF_DIR(3) MDWF_DIR(4) MDWF_DIR(5) MDWF_DIR(6) MDWF_DIR(7)
+#undef MDWF_DIR
+        } else {
+            // two directions in flight: load d + 1 before computing d
+            Raw<P> r0, r1;
+            r0.load(seg[0], lidx[0], lblk, src, jn[0], sblk, !staged);
+#define MDWF_STEP(d, rc, rn)                                                          \
+    rn.load(seg[(d) + 1], lidx[(d) + 1], lblk, src, jn[(d) + 1], sblk, !staged);     \
+    dir_term<P, D, PB, d, STAGE>(res, rc, lslot + (d) * kDirBytes, nb, b5, c5);
+            MDWF_STEP(0, r0, r1) MDWF_STEP(1, r1, r0) MDWF_STEP(2, r0, r1) MDWF_STEP(3, r1, r0)
+            MDWF_STEP(4, r0, r1) MDWF_STEP(5, r1, r0) MDWF_STEP(6, r0, r1)
+#undef MDWF_STEP
+            dir_term<P, D, PB, 7, STAGE>(res, r1, lslot + 7 * kDirBytes, nb, b5, c5);
+        }
     }
 
     // ---- epilogue on the hop result
     if constexpr (TR::epi == 1 || TR::epi == 2) {
-        // dense B K5^-1 = sum_k m_k C^k (or its adjoint) across the L5 lanes
-        __shared__ cx<R> sh[12 * kBlock];
+        // dense B K5^-1 = sum_k m_k C^k (or its adjoint) across the L5 lanes;
+        // the tile reuses the link stage once every wave is past its hop
+        cx<R>* sh = reinterpret_cast<cx<R>*>(smem);
+        if constexpr (STAGE) __syncthreads();
 #pragma unroll
         for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = res[c];
         __syncthreads();
@@ -334,6 +585,7 @@ int hop_blocks_per_rhs(const Geo& g) {
 
 template <Prec P, int K>
 static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
+    const bool stage = g.link_lds[P] && 64 / g.L5 <= kStageSites;
     HopDev a;
     a.out = L.out;
     a.in = L.in;
@@ -351,7 +603,8 @@ static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
     a.partials = L.partials;
     L.nblocks_per_rhs = a.nblk;
     dim3 grid(a.nblk * L.nrhs);
-    hipLaunchKernelGGL((k_hop<P, K>), grid, dim3(kBlock), 0, st, g, a);
+    if (stage) hipLaunchKernelGGL((k_hop<P, K, true>), grid, dim3(kBlock), 0, st, g, a);
+    else hipLaunchKernelGGL((k_hop<P, K, false>), grid, dim3(kBlock), 0, st, g, a);
 }
 
 template <Prec P>

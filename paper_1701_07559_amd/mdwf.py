@@ -61,7 +61,8 @@ class mdwf_solve_info(C.Structure):
 
 
 class mdwf_launch_tune(C.Structure):
-    _fields_ = [("zblock", C.c_int), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("us", C.c_double)]
+    _fields_ = [("zblock", C.c_int), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_lds", C.c_int),
+                ("us", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -126,6 +126,55 @@ def test_operator_parity(M, geom, prec):
         M.mdwf_destroy(ctx)
 
 
+LAUNCH_VARIANTS = [
+    {"MDWF_LINK_LDS": "1"},
+    {"MDWF_LINK_LDS": "1", "MDWF_NT_STORE": "1", "MDWF_XCD_REMAP": "0"},
+    {"MDWF_ZBLOCK": "1", "MDWF_NT_STORE": "1"},
+    {"MDWF_ZBLOCK": "2", "MDWF_XCD_REMAP": "0"},
+]
+
+
+@pytest.mark.parametrize("env", LAUNCH_VARIANTS, ids=lambda e: "-".join("%s%s" % (k[5:], v) for k, v in e.items()))
+def test_operator_parity_launch_shapes(M, env, monkeypatch):
+    """Every launch shape the autotuner can pick computes the same operators
+    (traversal order, XCD numbering, non-temporal stores, LDS link stage)."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    for dims, L5 in (((6, 4, 2, 6), 8), ((4, 6, 6, 4), 12)):
+        act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+        U = I.random_links(dims, 0.3, 49)
+        psi = I.gaussian_source(dims, L5, 50)
+        ctx = make_ctx(M, act, U)
+        try:
+            for prec in (0, 1, 2):
+                t = M.mdwf_get_tune(ctx, prec)
+                if "MDWF_LINK_LDS" in env:
+                    assert t["link_lds"] == 1
+                for op in (M.MDWF_OP_D5, M.MDWF_OP_D5_DAG, M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG,
+                           M.MDWF_OP_HOP_EO, M.MDWF_OP_HOP_OE_DAG):
+                    err = rel(gpu_op(M, ctx, op, prec, act, psi), oracle_op(M, op, act, U, psi))
+                    assert err <= TOL[prec], (env, dims, L5, prec, op, err)
+        finally:
+            M.mdwf_destroy(ctx)
+
+
+def test_autotune_keeps_parity(M):
+    dims, L5 = (6, 4, 2, 6), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 51)
+    psi = I.gaussian_source(dims, L5, 52)
+    ctx = make_ctx(M, act, U)
+    try:
+        tunes = M.mdwf_autotune(ctx)
+        assert len(tunes) == 3 and all(t["us"] > 0 for t in tunes)
+        for prec in (0, 1, 2):
+            assert M.mdwf_get_tune(ctx, prec)["zblock"] == tunes[prec]["zblock"]
+            for op in (M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG, M.MDWF_OP_D5):
+                assert rel(gpu_op(M, ctx, op, prec, act, psi), oracle_op(M, op, act, U, psi)) <= TOL[prec]
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 def test_operator_parity_other_action(M):
     """Shamir-like and heavy-mass corner: b5 = 1, c5 = 0, m_q = 1, M5 = 1.8."""
     dims, L5 = (4, 4, 2, 2), 6
