@@ -525,36 +525,14 @@ mdwf_status mdwf_solve_dev(mdwf_ctx* c, int nrhs, const double* const* b, double
     mdwf_status s = ready(c);
     if (s) return s;
     hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
-    return mdwf_solve_dev_impl(c, nrhs, b, x, mq, o, info, st);
+    return mdwf_solve_impl(c, nrhs, b, x, false, mq, o, info, st);
 }
 
 mdwf_status mdwf_solve(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, const double* mq,
                        const mdwf_solver_opts* o, mdwf_solve_info* info) {
     mdwf_status s = ready(c);
     if (s) return s;
-    if (nrhs < 1 || !b || !x) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
-    for (int k = 0; k < nrhs; ++k)
-        if (!b[k] || !x[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
-    const size_t fb = size_t(2) * c->geo.Vh * 24 * sizeof(double);
-    char* db = static_cast<char*>(buf(c, "solve_host_b", fb * nrhs, &s));
-    if (!db) return s;
-    char* dx = static_cast<char*>(buf(c, "solve_host_x", fb * nrhs, &s));
-    if (!dx) return s;
-    std::vector<const double*> bp(nrhs);
-    std::vector<double*> xp(nrhs);
-    for (int k = 0; k < nrhs; ++k) {
-        bp[k] = reinterpret_cast<const double*>(db + fb * k);
-        xp[k] = reinterpret_cast<double*>(dx + fb * k);
-        if ((s = hip_check(c, hipMemcpyAsync(db + fb * k, b[k], fb, hipMemcpyHostToDevice, c->stream), "H2D")))
-            return s;
-    }
-    mdwf_status rs = mdwf_solve_dev_impl(c, nrhs, bp.data(), xp.data(), mq, o, info, c->stream);
-    if (rs != MDWF_OK && rs != MDWF_ERR_NOCONV && rs != MDWF_ERR_NUMERIC) return rs;
-    for (int k = 0; k < nrhs; ++k)
-        if ((s = hip_check(c, hipMemcpyAsync(x[k], dx + fb * k, fb, hipMemcpyDeviceToHost, c->stream), "D2H")))
-            return s;
-    if ((s = hip_check(c, hipStreamSynchronize(c->stream), "solve D2H"))) return s;
-    return rs;
+    return mdwf_solve_impl(c, nrhs, b, x, true, mq, o, info, c->stream);
 }
 
 }  // extern "C"

@@ -66,5 +66,6 @@ double link_site_bytes(Prec p, int L5);
 
 }  // namespace mdwf
 
-mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_dev, double* const* x_dev,
-                                const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st);
+// host_io: b and x are host pointers, streamed through one device staging field
+mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, bool host_io,
+                            const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st);

@@ -12,19 +12,28 @@
 // every stop is confirmed by an FP64 true residual of the full system.
 //
 // Mixed precision: the inner vectors r, p, s, q and the hop temporary live in
-// FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32; the
-// FP64 solution x_hi, the prepared source and all reductions stay FP64.  When
-// the iterated |r| falls below delta times its value at the last update (or
-// reaches the target) the solver flushes x_lo into x_hi, recomputes
+// FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32 or FP16;
+// the FP64 solution x_hi, the prepared source and all reductions stay FP64.
+// When the iterated |r| falls below delta times its value at the last update
+// (or reaches the target) the solver flushes x_lo into x_hi, recomputes
 // r = b' - S x_hi with the FP64 operator and continues from it, keeping the
 // search direction p.
 //
-// Right-hand sides (with their own masses) share every launch; a per-RHS
-// active flag in device memory lets finished ones drop out without
-// re-capturing the iteration graph.  The CG scalars live in device memory; the
-// host reads |r|^2 one iteration late so the GPU never waits for it.
+// Right-hand sides (with their own masses) share every launch of the
+// iteration; a per-RHS active flag in device memory lets finished ones drop
+// out without re-capturing the iteration graph.  The CG scalars live in
+// device memory; the host reads |r|^2 one iteration late so the GPU never
+// waits for it.
+//
+// Memory: per RHS only x_hi and b' (FP64) and r, p, s, q, x_lo (inner) stay
+// resident.  The hop temporary is shared by a chunk of RHS, and the FP64
+// scratch of reliable updates, source preparation and verification is shared
+// and used one RHS at a time; the caller's canonical b and x (device, or host
+// through one staging field) are touched only at the start and at the end.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -43,15 +52,20 @@ struct Solver {
     bool mixed;
     size_t H64, Hi, Hx;
     int nbh, nbb;
-    char *be, *bo, *bp, *xh, *rh, *t64, *ye, *xo;
-    char *r, *p, *s, *q, *t, *xl;
+    int chunk;   // RHS per Schur launch pair (they share the hop temporary)
+    // per RHS
+    char *xh, *bp;                 // FP64, stride H64
+    char *r, *p, *s, *q, *xl;      // inner precision (x_lo: px), strides Hi / Hx
+    // shared
+    char* t;                       // inner hop temporary, `chunk` RHS at stride Hi
+    char *be, *bo, *rh, *t64, *ye, *xo;   // FP64 scratch, one RHS each
+    double* canon = nullptr;       // canonical staging of one field (host I/O)
     RhsCoef* coef;
     CGScal* sc;
-    int* act;       // iterate on these
-    int* msk;       // scratch mask for updates / checks
+    int* act;
+    int* msk;
     double* part;
     double* sums;
-    // pinned host mirrors
     CGScal* hsc[2];
     double* hsum;
     int* hmask;
@@ -59,9 +73,13 @@ struct Solver {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     mdwf_status err = MDWF_OK;
+    const double* const* b;
+    double* const* x;
+    bool host_io;
+    size_t canon_bytes;
 
-    bool ok(mdwf_status s) {
-        if (s != MDWF_OK && err == MDWF_OK) err = s;
+    bool ok(mdwf_status s_) {
+        if (s_ != MDWF_OK && err == MDWF_OK) err = s_;
         return err == MDWF_OK;
     }
     bool hipok(hipError_t e, const char* what) { return ok(hip_check(c, e, what)); }
@@ -73,14 +91,15 @@ struct Solver {
         hipok(hipStreamSynchronize(st), "mask upload");
     }
 
-    // q = S x (prec p) for masked RHS; tmp is an odd half-field array
-    void schur(Prec pr, const void* in, void* out, void* tmp, size_t stride, const int* mask, bool dag,
-               double* partials) {
+    // S or S^+ on nk consecutive RHS (stride apart) starting at the given
+    // pointers; tmp holds nk odd half fields at the same stride.
+    void schur(Prec pr, const char* in, char* out, char* tmp, size_t stride, int nk, const RhsCoef* cf,
+               const int* mask, bool dag, double* partials) {
         HopLaunch L{};
         L.prec = pr;
         L.stride = stride;
-        L.nrhs = n;
-        L.coef = coef;
+        L.nrhs = nk;
+        L.coef = cf;
         L.active = mask;
         L.kind = dag ? HOP_SCHUR_A_DAG : HOP_SCHUR_A;
         L.out_parity = 1;
@@ -97,28 +116,46 @@ struct Solver {
         launch_hop(g, c->gs, L, st);
     }
 
-    // per-RHS sum of partials (nblk per RHS) -> host vector
-    std::vector<double> fetch_sums(int nblk, const int* mask) {
-        launch_scalars(SC_SUM, part, nblk, n, mask, sc, sums, st);
-        hipok(hipMemcpyAsync(hsum, sums, sizeof(double) * n, hipMemcpyDeviceToHost, st), "sum D2H");
-        hipok(hipStreamSynchronize(st), "sum sync");
-        return std::vector<double>(hsum, hsum + n);
+    // inner-precision S or S^+ on all RHS, chunk by chunk; partials [n][nbh]
+    void schur_inner(const char* in, char* out, const int* mask, bool dag, double* partials) {
+        for (int k0 = 0; k0 < n; k0 += chunk) {
+            const int nk = std::min(chunk, n - k0);
+            schur(pi, in + Hi * k0, out + Hi * k0, t, Hi, nk, coef + k0, mask ? mask + k0 : nullptr, dag,
+                  partials ? partials + size_t(k0) * nbh : nullptr);
+        }
     }
 
-    std::vector<double> norm2(Prec pr, const void* x, size_t stride, const int* mask) {
-        hipok(hipMemsetAsync(sums, 0, sizeof(double) * n, st), "memset");
-        launch_norm2(g, pr, x, stride, n, mask, part, st);
-        return fetch_sums(nbb, mask);
+    // per-RHS sums of partials (nblk per RHS) -> host vector
+    std::vector<double> fetch_sums(int nblk, int nr, const int* mask) {
+        launch_scalars(SC_SUM, part, nblk, nr, mask, sc, sums, st);
+        hipok(hipMemcpyAsync(hsum, sums, sizeof(double) * nr, hipMemcpyDeviceToHost, st), "sum D2H");
+        hipok(hipStreamSynchronize(st), "sum sync");
+        return std::vector<double>(hsum, hsum + nr);
+    }
+    double norm2_one(Prec pr, const void* v) {
+        launch_norm2(g, pr, v, 0, 1, nullptr, part, st);
+        return fetch_sums(nbb, 1, nullptr)[0];
+    }
+
+    // source k, packed into the shared scratch be / bo
+    void load_b(int k) {
+        const double* src = b[k];
+        if (host_io) {
+            hipok(hipMemcpyAsync(canon, b[k], canon_bytes, hipMemcpyHostToDevice, st), "b H2D");
+            src = canon;
+        }
+        launch_pack_parity(g, P64, 1, 0, src, be, st);
+        launch_pack_parity(g, P64, 1, 1, src, bo, st);
     }
 
     void one_iteration() {
         void* xcur = mixed ? static_cast<void*>(xl) : static_cast<void*>(xh);
         const size_t sxc = mixed ? Hx : H64;
-        schur(pi, p, q, t, Hi, act, false, part);
+        schur_inner(p, q, act, false, part);
         launch_scalars(SC_ALPHA, part, nbh, n, act, sc, nullptr, st);
         launch_cg_xr(g, mixed ? px : P64, pi, xcur, sxc, r, p, q, Hi, n, act, sc, part, st);
         launch_scalars(SC_RR, part, nbb, n, act, sc, nullptr, st);
-        schur(pi, r, s, t, Hi, act, true, part);
+        schur_inner(r, s, act, true, part);
         launch_scalars(SC_BETA, part, nbh, n, act, sc, nullptr, st);
         launch_cg_p(g, pi, p, s, Hi, n, act, sc, st);
     }
@@ -130,12 +167,12 @@ double now() {
 
 }  // namespace
 
-mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_dev, double* const* x_dev,
-                                const double* mq, const mdwf_solver_opts* o_in, mdwf_solve_info* info, hipStream_t st) {
+mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, double* const* x_out, bool host_io,
+                            const double* mq, const mdwf_solver_opts* o_in, mdwf_solve_info* info, hipStream_t st) {
     const double t_start = now();
-    if (nrhs < 1 || !b_dev || !x_dev) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
+    if (nrhs < 1 || !b_in || !x_out) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
     for (int k = 0; k < nrhs; ++k)
-        if (!b_dev[k] || !x_dev[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+        if (!b_in[k] || !x_out[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
     mdwf_solver_opts o;
     mdwf_default_opts(&o);
     if (o_in) o = *o_in;
@@ -155,43 +192,72 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
     S.g = c->geo;
     S.st = st;
     S.n = nrhs;
+    S.b = b_in;
+    S.x = x_out;
+    S.host_io = host_io;
     S.pi = Prec(o.inner);
     S.mixed = S.pi != P64;
-    S.px = S.mixed ? P32 : P64;
+    S.px = S.mixed ? P32 : P64;   // inner solution accumulator
     const Geo& g = S.g;
     S.H64 = half_field_bytes(P64, g.Vh);
     S.Hi = half_field_bytes(S.pi, g.Vh);
     S.Hx = half_field_bytes(S.px, g.Vh);
     S.nbh = hop_blocks_per_rhs(g);
     S.nbb = blas_blocks_per_rhs(g);
+    S.canon_bytes = size_t(2) * g.Vh * 24 * sizeof(double);
     const int n = nrhs;
+
+    // memory plan: the hop temporary is shared by `chunk` RHS; shrink the
+    // chunk when the whole batch would not fit next to the resident state
+    const size_t per_rhs = 2 * S.H64 + (S.mixed ? 4 * S.Hi + S.Hx : 4 * S.H64);
+    const size_t shared = 6 * S.H64 + (host_io ? S.canon_bytes : 0);
+    size_t held = 0;
+    for (auto& kv : c->bufs)
+        if (kv.first.rfind("sv_", 0) == 0) held += kv.second.n;
+    size_t freeb = 0, totalb = 0;
+    if (!S.hipok(hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo")) return S.err;
+    const size_t avail = freeb + held;
+    const size_t need_fixed = per_rhs * n + shared + (size_t(64) << 20);
+    S.chunk = n;
+    if (need_fixed + size_t(n) * S.Hi > avail) {
+        const size_t room = avail > need_fixed ? avail - need_fixed : 0;
+        S.chunk = int(std::max<size_t>(1, room / S.Hi));
+        if (S.chunk > n) S.chunk = n;
+    }
+    if (const char* e = std::getenv("MDWF_SOLVE_CHUNK")) {   // explicit chunk (memory / tests)
+        const int v = std::atoi(e);
+        if (v >= 1) S.chunk = std::min(v, n);
+    }
 
     mdwf_status s = MDWF_OK;
 #define ALLOC(var, name, bytes)                                       \
     S.var = static_cast<decltype(S.var)>(buf(c, name, (bytes), &s)); \
     if (!S.var) return s;
-    ALLOC(be, "sv_be", S.H64 * n);
-    ALLOC(bo, "sv_bo", S.H64 * n);
-    ALLOC(bp, "sv_bp", S.H64 * n);
     ALLOC(xh, "sv_xh", S.H64 * n);
-    ALLOC(rh, "sv_rh", S.H64 * n);
-    ALLOC(t64, "sv_t64", S.H64 * n);
-    ALLOC(ye, "sv_ye", S.H64 * n);
-    ALLOC(xo, "sv_xo", S.H64 * n);
+    ALLOC(bp, "sv_bp", S.H64 * n);
     if (S.mixed) {
         ALLOC(r, "sv_r", S.Hi * n);
         ALLOC(p, "sv_p", S.Hi * n);
         ALLOC(s, "sv_s", S.Hi * n);
         ALLOC(q, "sv_q", S.Hi * n);
-        ALLOC(t, "sv_t", S.Hi * n);
         ALLOC(xl, "sv_xl", S.Hx * n);
+        ALLOC(t, "sv_t", S.Hi * S.chunk);
     } else {
         ALLOC(r, "sv_r64", S.H64 * n);
         ALLOC(p, "sv_p64", S.H64 * n);
         ALLOC(s, "sv_s64", S.H64 * n);
         ALLOC(q, "sv_q64", S.H64 * n);
-        S.t = S.t64;
+        ALLOC(t, "sv_t64c", S.H64 * S.chunk);
         S.xl = nullptr;
+    }
+    ALLOC(be, "sv_be", S.H64);
+    ALLOC(bo, "sv_bo", S.H64);
+    ALLOC(rh, "sv_rh", S.H64);
+    ALLOC(t64, "sv_t64", S.H64);
+    ALLOC(ye, "sv_ye", S.H64);
+    ALLOC(xo, "sv_xo", S.H64);
+    if (host_io) {
+        ALLOC(canon, "sv_canon", S.canon_bytes);
     }
     ALLOC(coef, "sv_coef", sizeof(RhsCoef) * n);
     ALLOC(sc, "sv_scal", sizeof(CGScal) * n);
@@ -217,28 +283,16 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
 
     std::vector<int> active(n, 1), done(n, 0), iters(n, 0), updates(n, 0), restarts(n, 0), stopped(n, 0);
     std::vector<double> true_res(n, -1.0), bnorm(n, 0.0), rmax(n, 0.0);
-    S.upload_mask(S.act, active);
 
-    // ---- pack b, source preparation
-    for (int k = 0; k < n; ++k) {
-        launch_pack_parity(g, P64, 1, 0, b_dev[k], S.be + S.H64 * k, st);
-        launch_pack_parity(g, P64, 1, 1, b_dev[k], S.bo + S.H64 * k, st);
-    }
-    {
-        auto ne = S.norm2(P64, S.be, S.H64, S.act);
-        auto no = S.norm2(P64, S.bo, S.H64, S.act);
-        for (int k = 0; k < n; ++k) bnorm[k] = std::sqrt(ne[k] + no[k]);
-    }
-    launch_fifth(g, P64, FIFTH_K5INV, 0, S.bo, S.t64, S.H64, n, S.coef, S.act, st);
-    {
+    // ---- source preparation, one RHS at a time: b'_e = b_e + 1/2 D_eo B K5^-1 b_o
+    for (int k = 0; k < n && !S.err; ++k) {
+        S.load_b(k);
+        bnorm[k] = std::sqrt(S.norm2_one(P64, S.be) + S.norm2_one(P64, S.bo));
+        launch_fifth(g, P64, FIFTH_K5INV, 0, S.bo, S.t64, S.H64, 1, S.coef + k, nullptr, st);
         HopLaunch L{};
-        L.kind = HOP_PREP; L.prec = P64; L.out_parity = 0; L.out = S.bp; L.in = S.t64; L.centre = S.be;
-        L.stride = S.H64; L.nrhs = n; L.coef = S.coef; L.active = S.act;
+        L.kind = HOP_PREP; L.prec = P64; L.out_parity = 0; L.out = S.bp + S.H64 * k; L.in = S.t64; L.centre = S.be;
+        L.stride = S.H64; L.nrhs = 1; L.coef = S.coef + k; L.active = nullptr;
         launch_hop(g, c->gs, L, st);
-    }
-    S.hipok(hipMemsetAsync(S.xh, 0, S.H64 * n, st), "memset");
-    if (S.mixed) S.hipok(hipMemsetAsync(S.xl, 0, S.Hx * n, st), "memset");
-    for (int k = 0; k < n; ++k) {
         if (bnorm[k] == 0.0) {   // b = 0: x = 0 exactly
             active[k] = 0;
             done[k] = 1;
@@ -249,19 +303,26 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
             stopped[k] = 2;
         }
     }
+    S.hipok(hipMemsetAsync(S.xh, 0, S.H64 * n, st), "memset");
+    if (S.mixed) S.hipok(hipMemsetAsync(S.xl, 0, S.Hx * n, st), "memset");
     S.upload_mask(S.act, active);
+    if (S.err) return S.err;
 
-    // Reliable update / restart for the RHS in `upd`: r_hi = b' - S x_hi (FP64),
-    // then (if still running) r = r_hi in the inner precision, s = S^+ r,
-    // gamma = |s|^2, and p = s when `restart_p`.
+    // Reliable update / restart for the RHS in `upd`: r_hi = b' - S x_hi in FP64
+    // (one RHS at a time in the shared scratch), then r = r_hi in the inner
+    // precision, s = S^+ r, gamma = |s|^2, and p = s where `restart_p`.
     auto refresh = [&](const std::vector<int>& upd, const std::vector<int>& restart_p) {
         S.upload_mask(S.msk, upd);
         if (S.mixed) launch_flush(g, S.px, S.xh, S.H64, S.xl, S.Hx, n, S.msk, st);
-        S.schur(P64, S.xh, S.rh, S.t64, S.H64, S.msk, false, nullptr);
-        launch_axpby(g, P64, 1.0, S.bp, -1.0, S.rh, S.rh, S.H64, n, S.msk, S.part, st);
-        auto rr = S.fetch_sums(S.nbb, S.msk);
-        launch_convert(g, P64, S.pi, S.rh, S.r, S.H64, S.Hi, n, S.msk, st);
-        S.schur(S.pi, S.r, S.s, S.t, S.Hi, S.msk, true, S.part);
+        std::vector<double> rr(n, 0.0);
+        for (int k = 0; k < n; ++k) {
+            if (!upd[k]) continue;
+            S.schur(P64, S.xh + S.H64 * k, S.rh, S.t64, S.H64, 1, S.coef + k, nullptr, false, nullptr);
+            launch_axpby(g, P64, 1.0, S.bp + S.H64 * k, -1.0, S.rh, S.rh, S.H64, 1, nullptr, S.part, st);
+            rr[k] = S.fetch_sums(S.nbb, 1, nullptr)[0];
+            launch_convert(g, P64, S.pi, S.rh, S.r + S.Hi * k, S.H64, S.Hi, 1, nullptr, st);
+        }
+        S.schur_inner(S.r, S.s, S.msk, true, S.part);
         launch_scalars(SC_SET_GAMMA, S.part, S.nbh, n, S.msk, S.sc, nullptr, st);
         std::vector<int> rp(n, 0);
         bool any_rp = false;
@@ -277,26 +338,33 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
         return rr;
     };
 
-    // FP64 true residual |b - D5 x| / |b| of the RHS in `chk`; leaves x_o in xo.
-    auto true_residual = [&](const std::vector<int>& chk) {
-        S.upload_mask(S.msk, chk);
+    // FP64 true residual |b - D5 x| / |b| of RHS k (x_o reconstructed into
+    // the scratch xo); with `write_x` the full solution goes to the caller.
+    auto verify = [&](int k, bool write_x) {
+        S.load_b(k);
+        const char* xk = S.xh + S.H64 * k;
         HopLaunch L{};
-        L.prec = P64; L.stride = S.H64; L.nrhs = n; L.coef = S.coef; L.active = S.msk;
-        L.kind = HOP_PREP; L.out_parity = 1; L.out = S.t64; L.in = S.xh; L.centre = S.bo;
+        L.prec = P64; L.stride = S.H64; L.nrhs = 1; L.coef = S.coef + k; L.active = nullptr;
+        L.kind = HOP_PREP; L.out_parity = 1; L.out = S.t64; L.in = xk; L.centre = S.bo;
         launch_hop(g, c->gs, L, st);
-        launch_fifth(g, P64, FIFTH_K5INV, 0, S.t64, S.xo, S.H64, n, S.coef, S.msk, st);
-        L.kind = HOP_D5; L.out_parity = 0; L.out = S.ye; L.in = S.xo; L.centre = S.xh;
+        launch_fifth(g, P64, FIFTH_K5INV, 0, S.t64, S.xo, S.H64, 1, S.coef + k, nullptr, st);
+        L.kind = HOP_D5; L.out_parity = 0; L.out = S.ye; L.in = S.xo; L.centre = xk;
         launch_hop(g, c->gs, L, st);
-        L.kind = HOP_D5; L.out_parity = 1; L.out = S.t64; L.in = S.xh; L.centre = S.xo;
+        L.kind = HOP_D5; L.out_parity = 1; L.out = S.t64; L.in = xk; L.centre = S.xo;
         launch_hop(g, c->gs, L, st);
-        launch_axpby(g, P64, 1.0, S.be, -1.0, S.ye, S.ye, S.H64, n, S.msk, S.part, st);
-        auto se = S.fetch_sums(S.nbb, S.msk);
-        launch_axpby(g, P64, 1.0, S.bo, -1.0, S.t64, S.t64, S.H64, n, S.msk, S.part, st);
-        auto so = S.fetch_sums(S.nbb, S.msk);
-        std::vector<double> tr(n, 0.0);
-        for (int k = 0; k < n; ++k)
-            if (chk[k]) tr[k] = bnorm[k] > 0.0 ? std::sqrt(se[k] + so[k]) / bnorm[k] : 0.0;
-        return tr;
+        launch_axpby(g, P64, 1.0, S.be, -1.0, S.ye, S.ye, S.H64, 1, nullptr, S.part, st);
+        const double se = S.fetch_sums(S.nbb, 1, nullptr)[0];
+        launch_axpby(g, P64, 1.0, S.bo, -1.0, S.t64, S.t64, S.H64, 1, nullptr, S.part, st);
+        const double so = S.fetch_sums(S.nbb, 1, nullptr)[0];
+        if (write_x) {
+            double* dst = host_io ? S.canon : x_out[k];
+            launch_unpack_parity(g, P64, 1, 0, xk, dst, st);
+            launch_unpack_parity(g, P64, 1, 1, S.xo, dst, st);
+            if (host_io)
+                S.hipok(hipMemcpyAsync(x_out[k], S.canon, S.canon_bytes, hipMemcpyDeviceToHost, st), "x D2H");
+            S.hipok(hipStreamSynchronize(st), "x write");
+        }
+        return bnorm[k] > 0.0 ? std::sqrt(se + so) / bnorm[k] : 0.0;
     };
 
     // initial residual and direction (x = 0, so r = b')
@@ -370,47 +438,32 @@ mdwf_status mdwf_solve_dev_impl(mdwf_ctx* c, int nrhs, const double* const* b_de
         if (!any) continue;
         // act on the current state (includes the iteration just enqueued)
         S.hipok(hipStreamSynchronize(st), "sync");
-        auto rr = refresh(upd, rp);   // keeps p for now; restarts handled below
+        auto rr = refresh(upd, rp);   // keeps p; restarts handled below
         for (int k = 0; k < n; ++k)
             if (upd[k]) skip[k] = pending ? 1 : 0;
-        std::vector<int> chk(n, 0);
-        bool any_chk = false;
+        std::vector<int> again(n, 0), again_rp(n, 0);
+        bool any_again = false, any_stop = false;
         for (int k = 0; k < n; ++k) {
             if (!upd[k]) continue;
             if (S.mixed) ++updates[k];
             if (std::sqrt(rr[k]) <= tgt * bnorm[k] || iters[k] >= o.max_iter || stopped[k] == 2) {
-                chk[k] = 1;
-                any_chk = true;
+                const double tr = verify(k, false);
+                true_res[k] = tr;
+                if (tr <= o.tol) { done[k] = 1; active[k] = 0; any_stop = true; }
+                else if (iters[k] >= o.max_iter || stopped[k] == 2) {
+                    active[k] = 0;
+                    any_stop = true;
+                    if (!stopped[k]) stopped[k] = 1;
+                } else { ++restarts[k]; again[k] = 1; again_rp[k] = 1; any_again = true; }
             }
         }
-        if (any_chk) {
-            auto tr = true_residual(chk);
-            std::vector<int> again(n, 0), again_rp(n, 0);
-            bool any_again = false;
-            for (int k = 0; k < n; ++k) {
-                if (!chk[k]) continue;
-                true_res[k] = tr[k];
-                if (tr[k] <= o.tol) { done[k] = 1; active[k] = 0; }
-                else if (iters[k] >= o.max_iter || stopped[k] == 2) { active[k] = 0; if (!stopped[k]) stopped[k] = 1; }
-                else { ++restarts[k]; again[k] = 1; again_rp[k] = 1; any_again = true; }
-            }
-            if (any_again) refresh(again, again_rp);   // restart p = s from the true residual
-            S.upload_mask(S.act, active);
-        }
+        if (any_again) refresh(again, again_rp);   // restart p = s from the true residual
+        if (any_stop) S.upload_mask(S.act, active);
     }
     if (S.err) return S.err;
 
-    // reconstruct every RHS and write x
-    {
-        std::vector<int> all(n, 1);
-        auto tr = true_residual(all);
-        for (int k = 0; k < n; ++k) {
-            true_res[k] = tr[k];
-            launch_unpack_parity(g, P64, 1, 0, S.xh + S.H64 * k, x_dev[k], st);
-            launch_unpack_parity(g, P64, 1, 1, S.xo + S.H64 * k, x_dev[k], st);
-        }
-        S.hipok(hipStreamSynchronize(st), "final sync");
-    }
+    // reconstruct every RHS, verify and write x
+    for (int k = 0; k < n && !S.err; ++k) true_res[k] = verify(k, true);
     if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
     if (S.graph) (void)hipGraphDestroy(S.graph);
     for (int e = 0; e < 2; ++e) (void)hipEventDestroy(S.ev[e]);

@@ -330,6 +330,33 @@ def test_multi_rhs_multi_mass_equals_single(M):
         M.mdwf_destroy(ctx)
 
 
+def test_multi_rhs_chunked_schur_is_bitwise_identical(M, monkeypatch):
+    """Splitting the RHS into chunks that share the hop temporary changes no bit."""
+    dims, L5 = (4, 4, 4, 8), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 53)
+    bs = [I.gaussian_source(dims, L5, 60 + k) for k in range(5)]
+    masses = [0.05, 0.03, 0.08, 0.05, 0.2]
+    ctx = make_ctx(M, act, U)
+    try:
+        res = []
+        for chunk in (None, "2", "1"):
+            if chunk:
+                monkeypatch.setenv("MDWF_SOLVE_CHUNK", chunk)
+            xs = [np.zeros_like(b) for b in bs]
+            st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=2))
+            assert st == M.MDWF_OK
+            res.append((xs, [i["iters"] for i in info]))
+        for xs, its in res[1:]:
+            assert its == res[0][1]
+            for a, b in zip(xs, res[0][0]):
+                assert np.array_equal(a, b)
+        for k, b in enumerate(bs):
+            assert oracle.true_residual(act.with_mass(masses[k]), U, b, res[0][0][k]) <= 1e-10
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 def test_solve_dev_with_torch_buffers(M, cfg1):
     import torch
     act, U, b, x_ref = cfg1
