@@ -116,6 +116,10 @@ typedef struct {
     double delta;        /* reliable update when ||r|| < delta * ||r_last||    */
     int check_every;     /* host convergence check period in iterations (>=1)  */
     int use_graph;       /* 1: replay CG iterations from a captured hipGraph   */
+    int profile_iters;   /* time the inner operator launches of this many CG
+                            iterations (from the third on) with HIP events on
+                            the solve stream; 0 = off, at most 64, ignored
+                            with use_graph                                   */
 } mdwf_solver_opts;
 
 typedef struct {
@@ -126,6 +130,11 @@ typedef struct {
     double seconds;       /* wall time of the solve call                          */
     double model_flops;   /* flops of the model counted for this right-hand side  */
     double model_bytes;   /* algorithmic HBM bytes of the model for this RHS       */
+    double hop_us[4];     /* profile_iters > 0: mean duration (us) of one launch of
+                             kernel A, B, A^+, B^+ (inner precision, first chunk
+                             of right-hand sides, all its RHS together); else 0 */
+    int hop_rhs;          /* right-hand sides in those launches                   */
+    int hop_samples;      /* iterations sampled                                   */
 } mdwf_solve_info;
 
 /* Create a context for one lattice geometry on HIP device `hip_device`.
@@ -185,7 +194,7 @@ mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, 
                            void *stream);
 
 /* Fill opts with defaults: tol 1e-10, max_iter 100000, inner F64, delta 0.1,
- * check_every 1, use_graph 0. */
+ * check_every 1, use_graph 0, profile_iters 0. */
 void mdwf_default_opts(mdwf_solver_opts *opts);
 
 /* Launch shape of the hop kernels for one storage precision. */
@@ -193,7 +202,9 @@ typedef struct {
     int zblock;      /* traversal: z-blocks of this many z-planes, t inside (divides Z) */
     int xcd_remap;   /* 1: workgroups renumbered so each XCD walks one contiguous range */
     int nt_store;    /* 1: hop outputs written with non-temporal stores               */
-    int link_lds;    /* 1: links staged in LDS, one fetch per site (needs L5 >= 8)    */
+    int link_mode;   /* links: 0 loaded by every lane, 1 staged in LDS (L5 >= 8),
+                        2 one 16-byte part per lane, gathered by lane exchange
+                        (FP32 / FP16, L5 >= 4 / 2); otherwise 0 is used      */
     double us;       /* measured time of one Schur application with this shape (us)   */
 } mdwf_launch_tune;
 

@@ -117,7 +117,7 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
     g.fZb[p] = FastDiv(uint32_t(t.zblock));
     g.xcd_remap[p] = t.xcd_remap ? 1 : 0;
     g.nt_store[p] = t.nt_store ? 1 : 0;
-    g.link_lds[p] = t.link_lds ? 1 : 0;
+    g.link_mode[p] = (t.link_mode >= 0 && t.link_mode <= 2) ? t.link_mode : 0;
 }
 
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
@@ -275,7 +275,7 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     }
     if (const char* e = std::getenv("MDWF_XCD_REMAP")) t0.xcd_remap = std::atoi(e) != 0;
     if (const char* e = std::getenv("MDWF_NT_STORE")) t0.nt_store = std::atoi(e) != 0;
-    if (const char* e = std::getenv("MDWF_LINK_LDS")) t0.link_lds = std::atoi(e) != 0;
+    if (const char* e = std::getenv("MDWF_LINK_MODE")) t0.link_mode = std::atoi(e);
     for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
     if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
@@ -309,6 +309,7 @@ void mdwf_default_opts(mdwf_solver_opts* o) {
     o->delta = 0.1;
     o->check_every = 1;
     o->use_graph = 0;
+    o->profile_iters = 0;
 }
 
 static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_device) {
@@ -459,7 +460,7 @@ mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* o
     out->zblock = c->geo.zb[prec];
     out->xcd_remap = c->geo.xcd_remap[prec];
     out->nt_store = c->geo.nt_store[prec];
-    out->link_lds = c->geo.link_lds[prec];
+    out->link_mode = c->geo.link_mode[prec];
     out->us = c->tuned_us[prec];
     return MDWF_OK;
 }
@@ -489,12 +490,14 @@ mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
         void* b = a ? buf(c, "tune_b", 2 * half_field_bytes(P64, g.Vh), &s) : nullptr;
         if (!a || !b) break;
         launch_pack_parity(g, p, 0, 0, static_cast<const double*>(cin), a, st);
-        mdwf_launch_tune best{g.zb[p], g.xcd_remap[p], g.nt_store[p], g.link_lds[p], 1e30};
-        const int max_lds = (64 / g.L5 <= 8) ? 1 : 0;
+        mdwf_launch_tune best{g.zb[p], g.xcd_remap[p], g.nt_store[p], g.link_mode[p], 1e30};
+        std::vector<int> modes{0};
+        if (64 / g.L5 <= 8) modes.push_back(1);
+        if (p != P64 && g.L5 >= (p == P32 ? 4 : 2)) modes.push_back(2);
         for (int zb : zbs)
             for (int rm = 1; rm >= 0; --rm)
                 for (int nt = 0; nt <= 1; ++nt)
-                for (int ll = 0; ll <= max_lds; ++ll) {
+                for (int ll : modes) {
                     mdwf_launch_tune cand{zb, rm, nt, ll, 0.0};
                     set_tune(g, p, cand);
                     const int warm = 2, reps = 5;

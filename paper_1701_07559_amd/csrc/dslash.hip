@@ -114,6 +114,83 @@ __device__ __forceinline__ void su3_mul(const cx<R> U[9], const cx<R> h[6], cx<R
         }
 }
 
+// ------------------------------------------------ binary16 packed arithmetic
+// FP16 spinors and links hold one complex number per 32-bit word as a pair of
+// binary16 values (re, im).  The FP16 hop keeps them packed: projections are
+// packed-half adds, and the SU(3) product uses v_dot2_f32_f16, which sums two
+// half products into an FP32 accumulator, so the stored values enter the
+// product without conversion and every sum is carried in FP32.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2 as_h2(uint32_t w) { return __builtin_bit_cast(h2, w); }
+__device__ __forceinline__ h2 splat_h2(float f) {
+    const _Float16 h = _Float16(f);
+    return h2{h, h};
+}
+// a.x b.x + a.y b.y + c
+__device__ __forceinline__ float dot2(h2 a, h2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+
+// From z = u + SGN X d (X = i for TI, else 1) the two packed operands that
+// make U z (FWD) or U^+ z a sum of dot2 products with the link element:
+//   U z:   re = sum Ur zr - Ui zi = dot(U, (zr, -zi)),  im = dot(U, (zi, zr))
+//   U^+ z: re = dot(U, (zr, zi)),                     im = dot(U, (zi, -zr))
+// The sign flips and swaps act on u and X d before the packed add, where
+// they are operand modifiers.
+template <bool TI, int SGN, bool FWD>
+__device__ __forceinline__ void comb_h(h2 u, h2 d, h2& z1, h2& z2) {
+    const h2 xd = TI ? h2{-d.y, d.x} : d;   // X d
+    h2 a1, b1, a2, b2;
+    if (FWD) {
+        a1 = h2{u.x, -u.y}, b1 = h2{xd.x, -xd.y};   // conjugate
+        a2 = h2{u.y, u.x}, b2 = h2{xd.y, xd.x};     // swapped
+    } else {
+        a1 = u, b1 = xd;
+        a2 = h2{u.y, -u.x}, b2 = h2{xd.y, -xd.x};   // swapped conjugate
+    }
+    z1 = SGN > 0 ? a1 + b1 : a1 - b1;
+    z2 = SGN > 0 ? a2 + b2 : a2 - b2;
+}
+
+// Packed version of project<MU>, returning the product operands of comb_h.
+template <int MU, int SG, bool FWD>
+__device__ __forceinline__ void project_h(const h2 in[12], h2 z1[6], h2 z2[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const h2 u0 = in[a], u1 = in[3 + a], d0 = in[6 + a], d1 = in[9 + a];
+        if (MU == 0) {
+            comb_h<true, SG, FWD>(u0, d1, z1[a], z2[a]);
+            comb_h<true, SG, FWD>(u1, d0, z1[3 + a], z2[3 + a]);
+        } else if (MU == 1) {
+            comb_h<false, SG, FWD>(u0, d1, z1[a], z2[a]);
+            comb_h<false, -SG, FWD>(u1, d0, z1[3 + a], z2[3 + a]);
+        } else if (MU == 2) {
+            comb_h<true, SG, FWD>(u0, d0, z1[a], z2[a]);
+            comb_h<true, -SG, FWD>(u1, d1, z1[3 + a], z2[3 + a]);
+        } else {
+            comb_h<false, -SG, FWD>(u0, d0, z1[a], z2[a]);
+            comb_h<false, -SG, FWD>(u1, d1, z1[3 + a], z2[3 + a]);
+        }
+    }
+}
+
+// w = U h (FWD) or U^+ h with binary16 inputs and FP32 sums (operands from
+// project_h).
+template <bool FWD>
+__device__ __forceinline__ void su3_mul_h(const h2 U[9], const h2 z1[6], const h2 z2[6], cx<float> w[6]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const h2 u = FWD ? U[a * 3 + b] : U[b * 3 + a];
+                re = dot2(u, z1[sp * 3 + b], re);
+                im = dot2(u, z2[sp * 3 + b], im);
+            }
+            w[sp * 3 + a] = {re, im};
+        }
+}
+
 // ----------------------------------------------------------- hop kernels
 struct HopDev {
     void* out;
@@ -201,6 +278,21 @@ template <> struct Raw<P32> {
         }
         U[8] = {u8.x, u8.y};
     }
+    // Gathered link: lane s of the site group loads 16-byte part min(s, 3)
+    // and the 8-byte tail itself; the other lanes' parts come by lane
+    // exchange from lanes gbase + p (no branch, so loads stay in order).
+    __device__ __forceinline__ void load_part(const char* lseg, uint32_t li, size_t lblk, int s) {
+        u[0] = ldu<nf4>(lseg + size_t(s < 3 ? s : 3) * lblk, li * 16u);
+        u8 = ldu<nf2>(lseg + 4 * lblk, li * 8u);
+    }
+    __device__ __forceinline__ void link_shfl(int a0, cx<float> U[9]) const {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            U[2 * p] = {bperm(a0 + 4 * p, u[0].x), bperm(a0 + 4 * p, u[0].y)};
+            U[2 * p + 1] = {bperm(a0 + 4 * p, u[0].z), bperm(a0 + 4 * p, u[0].w)};
+        }
+        U[8] = {u8.x, u8.y};
+    }
     __device__ __forceinline__ void spinor(cx<float> v[12]) const {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -226,49 +318,70 @@ template <> struct Raw<P16> {
         for (int k = 0; k < 3; ++k) s[k] = ldu<nu4>(in + k * sblk, so);
         n = ldu<float>(in + align256(3 * sblk), jn * 4u);   // norm block (see norm_offset)
     }
-    __device__ __forceinline__ void link(cx<float> U[9]) const {
+    __device__ __forceinline__ void link_h(h2 U[9]) const {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            unpack_h2(u[k].x, 1.f, U[4 * k]);
-            unpack_h2(u[k].y, 1.f, U[4 * k + 1]);
-            unpack_h2(u[k].z, 1.f, U[4 * k + 2]);
-            unpack_h2(u[k].w, 1.f, U[4 * k + 3]);
+            U[4 * k] = as_h2(u[k].x);
+            U[4 * k + 1] = as_h2(u[k].y);
+            U[4 * k + 2] = as_h2(u[k].z);
+            U[4 * k + 3] = as_h2(u[k].w);
         }
-        unpack_h2(u8, 1.f, U[8]);
+        U[8] = as_h2(u8);
     }
-    __device__ __forceinline__ void spinor(cx<float> v[12]) const {
+    // Gathered link: lane s loads 16-byte part min(s, 1) and the 4-byte tail
+    // itself; the two 16-byte parts come by lane exchange from lanes gbase,
+    // gbase + 1.
+    __device__ __forceinline__ void load_part(const char* lseg, uint32_t li, size_t lblk, int s) {
+        u[0] = ldu<nu4>(lseg + size_t(s < 1 ? s : 1) * lblk, li * 16u);
+        u8 = ldu<uint32_t>(lseg + 2 * lblk, li * 4u);
+    }
+    __device__ __forceinline__ void link_shfl_h(int a0, h2 U[9]) const {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            U[4 * p] = as_h2(uint32_t(__builtin_amdgcn_ds_bpermute(a0 + 4 * p, int(u[0].x))));
+            U[4 * p + 1] = as_h2(uint32_t(__builtin_amdgcn_ds_bpermute(a0 + 4 * p, int(u[0].y))));
+            U[4 * p + 2] = as_h2(uint32_t(__builtin_amdgcn_ds_bpermute(a0 + 4 * p, int(u[0].z))));
+            U[4 * p + 3] = as_h2(uint32_t(__builtin_amdgcn_ds_bpermute(a0 + 4 * p, int(u[0].w))));
+        }
+        U[8] = as_h2(u8);
+    }
+    // the stored spinor as binary16 pairs; its value is scale * v
+    __device__ __forceinline__ float spinor_h(h2 v[12]) const {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            unpack_h2(s[k].x, n, v[4 * k]);
-            unpack_h2(s[k].y, n, v[4 * k + 1]);
-            unpack_h2(s[k].z, n, v[4 * k + 2]);
-            unpack_h2(s[k].w, n, v[4 * k + 3]);
+            v[4 * k] = as_h2(s[k].x);
+            v[4 * k + 1] = as_h2(s[k].y);
+            v[4 * k + 2] = as_h2(s[k].z);
+            v[4 * k + 3] = as_h2(s[k].w);
         }
+        return n;
     }
-    // B psi with the slice neighbours' packed words and norms exchanged
-    // (6 + 6 + 2 lane swaps instead of 24 on unpacked floats)
-    __device__ __forceinline__ void spinor_B(const Nbr5<float>& nb, float b5, float c5, cx<float> v[12]) const {
+    // B psi = b5 psi_s + c5 (C psi)_s as binary16 pairs times a returned
+    // scale.  The three contributing slices carry their own norms; with
+    // S = max(b5 n_s, c5 |f| n_s-1, c5 |f| n_s+1, FLT_MIN) every coefficient
+    // divided by S lies in [-1, 1], so the packed sum stays in range
+    // (|v| <= 2).  The FLT_MIN floor keeps 1/S finite: across the wall f is
+    // -m_q, and c5 m_q n can be sub-normal next to a zero slice.
+    __device__ __forceinline__ float spinor_B_h(const Nbr5<float>& nb, float b5, float c5, h2 v[12]) const {
         const uint32_t up[6] = {s[0].x, s[0].y, s[0].z, s[0].w, s[1].x, s[1].y};
         const uint32_t dn[6] = {s[1].z, s[1].w, s[2].x, s[2].y, s[2].z, s[2].w};
-        const float nu = bperm(nb.am1, n) * nb.fm1 * c5;   // (C psi) upper comes from slice s-1
-        const float nd = bperm(nb.ap1, n) * nb.fp1 * c5;   // lower from slice s+1
-        const float nb5 = n * b5;
+        const float a0 = b5 * n;
+        const float au = c5 * nb.fm1 * bperm(nb.am1, n);   // (C psi) upper from slice s-1
+        const float ad = c5 * nb.fp1 * bperm(nb.ap1, n);   // lower from slice s+1
+        const float S = fmaxf(fmaxf(a0, 1.17549435e-38f), fmaxf(fabsf(au), fabsf(ad)));
+        const float inv = __builtin_amdgcn_rcpf(S);
+        const h2 ha = splat_h2(a0 * inv), hu = splat_h2(au * inv), hd = splat_h2(ad * inv);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const uint32_t o = uint32_t(__builtin_amdgcn_ds_bpermute(nb.am1, int(up[k])));
-            cx<float> mine, other;
-            unpack_h2(up[k], nb5, mine);
-            unpack_h2(o, nu, other);
-            v[k] = mine + other;
+            const h2 o = as_h2(uint32_t(__builtin_amdgcn_ds_bpermute(nb.am1, int(up[k]))));
+            v[k] = ha * as_h2(up[k]) + hu * o;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const uint32_t o = uint32_t(__builtin_amdgcn_ds_bpermute(nb.ap1, int(dn[k])));
-            cx<float> mine, other;
-            unpack_h2(dn[k], nb5, mine);
-            unpack_h2(o, nd, other);
-            v[6 + k] = mine + other;
+            const h2 o = as_h2(uint32_t(__builtin_amdgcn_ds_bpermute(nb.ap1, int(dn[k]))));
+            v[6 + k] = ha * as_h2(dn[k]) + hd * o;
         }
+        return S;
     }
 };
 
@@ -316,16 +429,16 @@ template <> struct LinkStage<P16> {
         if (b < 2) *reinterpret_cast<nu4*>(dst) = ldu<nu4>(seg + b * lblk, idx * 16u);
         else *reinterpret_cast<uint32_t*>(dst) = ldu<uint32_t>(seg + 2 * lblk, idx * 4u);
     }
-    static __device__ __forceinline__ void read(const unsigned char* slot, cx<float> U[9]) {
+    static __device__ __forceinline__ void read_h(const unsigned char* slot, h2 U[9]) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const nu4 w = reinterpret_cast<const nu4*>(slot)[k];
-            unpack_h2(w.x, 1.f, U[4 * k]);
-            unpack_h2(w.y, 1.f, U[4 * k + 1]);
-            unpack_h2(w.z, 1.f, U[4 * k + 2]);
-            unpack_h2(w.w, 1.f, U[4 * k + 3]);
+            U[4 * k] = as_h2(w.x);
+            U[4 * k + 1] = as_h2(w.y);
+            U[4 * k + 2] = as_h2(w.z);
+            U[4 * k + 3] = as_h2(w.w);
         }
-        unpack_h2(*reinterpret_cast<const uint32_t*>(slot + 32), 1.f, U[8]);
+        U[8] = as_h2(*reinterpret_cast<const uint32_t*>(slot + 32));
     }
 };
 
@@ -337,16 +450,12 @@ __device__ __forceinline__ void hop_term(cx<typename Real<P>::T> acc[12], const 
                                          typename Real<P>::T c5) {
     using R = typename Real<P>::T;
     cx<R> psi[12];
-    if constexpr (P == P16 && PREB) {
-        r.spinor_B(nb, b5, c5, psi);
-    } else {
-        r.spinor(psi);
-        if (PREB) {
-            cx<R> cpsi[12];
-            apply_C_lanes<R, false>(nb, psi, cpsi);
+    r.spinor(psi);
+    if (PREB) {
+        cx<R> cpsi[12];
+        apply_C_lanes<R, false>(nb, psi, cpsi);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) psi[c] = b5 * psi[c] + c5 * cpsi[c];
-        }
+        for (int c = 0; c < 12; ++c) psi[c] = b5 * psi[c] + c5 * cpsi[c];
     }
     constexpr R sg = ((DIR > 0) != DAG) ? R(1) : R(-1);
     cx<R> h[6], w[6];
@@ -355,23 +464,53 @@ __device__ __forceinline__ void hop_term(cx<typename Real<P>::T> acc[12], const 
     reconstruct_add<MU>(sg, w, acc);
 }
 
-// Direction d of the fixed order x+, x-, y+, y-, z+, z-, t+, t-: the link
-// comes from the LDS stage or from the raw registers.
-template <Prec P, bool DAG, bool PREB, int D, bool STAGED>
-__device__ __forceinline__ void dir_term(cx<typename Real<P>::T> acc[12], const Raw<P>& r,
-                                         const unsigned char* slot, const Nbr5<typename Real<P>::T>& nb,
-                                         typename Real<P>::T b5, typename Real<P>::T c5) {
-    cx<typename Real<P>::T> U[9];
-    if constexpr (STAGED) LinkStage<P>::read(slot, U);
-    else r.link(U);
-    hop_term<P, DAG, PREB, D / 2, (D % 2 == 0) ? +1 : -1>(acc, r, U, nb, b5, c5);
+// FP16 storage: the same term on binary16 pairs (see su3_mul_h); the spinor
+// scale (its norm, or the B pre-hop's common scale) is applied once, in FP32,
+// when the colour product is added to the accumulator.
+template <bool DAG, bool PREB, int MU, int DIR>
+__device__ __forceinline__ void hop_term_h(cx<float> acc[12], const Raw<P16>& r, const h2 U[9],
+                                           const Nbr5<float>& nb, float b5, float c5) {
+    h2 psi[12];
+    const float scale = PREB ? r.spinor_B_h(nb, b5, c5, psi) : r.spinor_h(psi);
+    constexpr int sg = ((DIR > 0) != DAG) ? 1 : -1;
+    h2 z1[6], z2[6];
+    project_h<MU, sg, (DIR > 0)>(psi, z1, z2);
+    cx<float> w[6];
+    su3_mul_h<(DIR > 0)>(U, z1, z2, w);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w[c] = scale * w[c];
+    reconstruct_add<MU>(float(sg), w, acc);
 }
 
-// STAGE: links staged in LDS (requires at most kStageSites sites per wave,
-// i.e. L5 >= 8); otherwise every lane loads its links itself.
-constexpr int kStageSites = 8;
+// Direction d of the fixed order x+, x-, y+, y-, z+, z-, t+, t-.  Link mode
+// LM: 0 every lane holds the whole link, 1 LDS stage, 2 gathered from the
+// part-holding lanes of the site group (a0: byte address of its first lane).
+template <Prec P, bool DAG, bool PREB, int D, int LM>
+__device__ __forceinline__ void dir_term(cx<typename Real<P>::T> acc[12], const Raw<P>& r,
+                                         const unsigned char* slot, int a0, const Nbr5<typename Real<P>::T>& nb,
+                                         typename Real<P>::T b5, typename Real<P>::T c5) {
+    if constexpr (P == P16) {
+        h2 U[9];
+        if constexpr (LM == 1) LinkStage<P16>::read_h(slot, U);
+        else if constexpr (LM == 2) r.link_shfl_h(a0, U);
+        else r.link_h(U);
+        hop_term_h<DAG, PREB, D / 2, (D % 2 == 0) ? +1 : -1>(acc, r, U, nb, b5, c5);
+    } else {
+        cx<typename Real<P>::T> U[9];
+        if constexpr (LM == 1) LinkStage<P>::read(slot, U);
+        else if constexpr (LM == 2) r.link_shfl(a0, U);
+        else r.link(U);
+        hop_term<P, DAG, PREB, D / 2, (D % 2 == 0) ? +1 : -1>(acc, r, U, nb, b5, c5);
+    }
+}
 
-template <Prec P, int K, bool STAGE>
+// Link modes (see dir_term): the LDS stage needs at most kStageSites sites per
+// wave (L5 >= 8), the lane gather needs L5 >= the number of 16-byte parts.
+constexpr int kStageSites = 8;
+// 16-byte parts gathered by lane exchange (the short tail is loaded by every lane)
+template <Prec P> constexpr int link_parts() { return P == P64 ? 9 : P == P32 ? 4 : 2; }
+
+template <Prec P, int K, int LM>
 __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     using R = typename Real<P>::T;
     using TR = HopTraits<K>;
@@ -451,13 +590,13 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     // kernels A / A^+, the epilogue tile, which reuses the same bytes
     constexpr int NP = LinkStage<P>::NP;
     constexpr int kDirBytes = kStageSites * NP * 16;
-    constexpr int kLinkBytes = STAGE ? kWaves * 8 * kDirBytes : 0;
+    constexpr int kLinkBytes = LM == 1 ? kWaves * 8 * kDirBytes : 0;
     constexpr int kEpiBytes = (TR::epi == 1 || TR::epi == 2) ? 12 * kBlock * int(sizeof(cx<R>)) : 0;
     constexpr int kSmem = kLinkBytes > kEpiBytes ? kLinkBytes : kEpiBytes;
     __shared__ __align__(16) unsigned char smem[kSmem > 0 ? kSmem : 16];
-    constexpr bool staged = STAGE;
     unsigned char* lslot = smem + size_t(wave) * 8 * kDirBytes + size_t(sw) * NP * 16;
-    if constexpr (STAGE) {
+    const int a0 = gbase << 2;
+    if constexpr (LM == 1) {
         if (valid) {
             for (int b = s; b < NP; b += L5)
 #pragma unroll
@@ -472,21 +611,23 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
             // FP64: one direction in flight (two would exceed the register file)
             Raw<P> r;
 #define MDWF_DIR(d)                                                                 \
-    r.load(seg[d], lidx[d], lblk, src, jn[d], sblk, !staged);                      \
-    dir_term<P, D, PB, d, STAGE>(res, r, lslot + (d) * kDirBytes, nb, b5, c5);
+    r.load(seg[d], lidx[d], lblk, src, jn[d], sblk, LM == 0);                      \
+    dir_term<P, D, PB, d, LM>(res, r, lslot + (d) * kDirBytes, a0, nb, b5, c5);
             MDWF_DIR(0) MDWF_DIR(1) MDWF_DIR(2) MDWF_DIR(3) MDWF_DIR(4) MDWF_DIR(5) MDWF_DIR(6) MDWF_DIR(7)
 #undef MDWF_DIR
         } else {
             // two directions in flight: load d + 1 before computing d
             Raw<P> r0, r1;
-            r0.load(seg[0], lidx[0], lblk, src, jn[0], sblk, !staged);
+            r0.load(seg[0], lidx[0], lblk, src, jn[0], sblk, LM == 0);
+            if constexpr (LM == 2) r0.load_part(seg[0], lidx[0], lblk, s);
 #define MDWF_STEP(d, rc, rn)                                                          \
-    rn.load(seg[(d) + 1], lidx[(d) + 1], lblk, src, jn[(d) + 1], sblk, !staged);     \
-    dir_term<P, D, PB, d, STAGE>(res, rc, lslot + (d) * kDirBytes, nb, b5, c5);
+    rn.load(seg[(d) + 1], lidx[(d) + 1], lblk, src, jn[(d) + 1], sblk, LM == 0);     \
+    if constexpr (LM == 2) rn.load_part(seg[(d) + 1], lidx[(d) + 1], lblk, s);        \
+    dir_term<P, D, PB, d, LM>(res, rc, lslot + (d) * kDirBytes, a0, nb, b5, c5);
             MDWF_STEP(0, r0, r1) MDWF_STEP(1, r1, r0) MDWF_STEP(2, r0, r1) MDWF_STEP(3, r1, r0)
             MDWF_STEP(4, r0, r1) MDWF_STEP(5, r1, r0) MDWF_STEP(6, r0, r1)
 #undef MDWF_STEP
-            dir_term<P, D, PB, 7, STAGE>(res, r1, lslot + 7 * kDirBytes, nb, b5, c5);
+            dir_term<P, D, PB, 7, LM>(res, r1, lslot + 7 * kDirBytes, a0, nb, b5, c5);
         }
     }
 
@@ -495,7 +636,7 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
         // dense B K5^-1 = sum_k m_k C^k (or its adjoint) across the L5 lanes;
         // the tile reuses the link stage once every wave is past its hop
         cx<R>* sh = reinterpret_cast<cx<R>*>(smem);
-        if constexpr (STAGE) __syncthreads();
+        if constexpr (LM == 1) __syncthreads();
 #pragma unroll
         for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = res[c];
         __syncthreads();
@@ -585,7 +726,9 @@ int hop_blocks_per_rhs(const Geo& g) {
 
 template <Prec P, int K>
 static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
-    const bool stage = g.link_lds[P] && 64 / g.L5 <= kStageSites;
+    int lm = g.link_mode[P];
+    if (lm == 1 && 64 / g.L5 > kStageSites) lm = 0;
+    if (lm == 2 && (P == P64 || g.L5 < link_parts<P>())) lm = 0;
     HopDev a;
     a.out = L.out;
     a.in = L.in;
@@ -603,8 +746,13 @@ static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
     a.partials = L.partials;
     L.nblocks_per_rhs = a.nblk;
     dim3 grid(a.nblk * L.nrhs);
-    if (stage) hipLaunchKernelGGL((k_hop<P, K, true>), grid, dim3(kBlock), 0, st, g, a);
-    else hipLaunchKernelGGL((k_hop<P, K, false>), grid, dim3(kBlock), 0, st, g, a);
+    if (lm == 1) {
+        hipLaunchKernelGGL((k_hop<P, K, 1>), grid, dim3(kBlock), 0, st, g, a);
+    } else if (lm == 2) {
+        if constexpr (P != P64) hipLaunchKernelGGL((k_hop<P, K, 2>), grid, dim3(kBlock), 0, st, g, a);
+    } else {
+        hipLaunchKernelGGL((k_hop<P, K, 0>), grid, dim3(kBlock), 0, st, g, a);
+    }
 }
 
 template <Prec P>

@@ -88,7 +88,7 @@ struct Geo {
     FastDiv fZb[3];
     int xcd_remap[3];   // renumber workgroups per XCD (1) or keep hardware order (0)
     int nt_store[3];    // write hop outputs with non-temporal stores
-    int link_lds[3];    // stage links in LDS (used when 64 / L5 <= 8)
+    int link_mode[3];   // 0 per-lane links, 1 LDS stage, 2 lane gather
 };
 
 // Coefficients of one right-hand side (its mass); all fifth-dimension

@@ -70,6 +70,10 @@ struct Solver {
     double* hsum;
     int* hmask;
     hipEvent_t ev[2];
+    // launch timing of sampled iterations: 6 events per iteration around
+    // kernels A, B of S and of S^+ (first chunk); prof = the current six
+    std::vector<hipEvent_t> pev;
+    hipEvent_t* prof = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     mdwf_status err = MDWF_OK;
@@ -77,6 +81,10 @@ struct Solver {
     double* const* x;
     bool host_io;
     size_t canon_bytes;
+
+    ~Solver() {
+        for (hipEvent_t e : pev) (void)hipEventDestroy(e);
+    }
 
     bool ok(mdwf_status s_) {
         if (s_ != MDWF_OK && err == MDWF_OK) err = s_;
@@ -94,7 +102,7 @@ struct Solver {
     // S or S^+ on nk consecutive RHS (stride apart) starting at the given
     // pointers; tmp holds nk odd half fields at the same stride.
     void schur(Prec pr, const char* in, char* out, char* tmp, size_t stride, int nk, const RhsCoef* cf,
-               const int* mask, bool dag, double* partials) {
+               const int* mask, bool dag, double* partials, hipEvent_t* evs = nullptr) {
         HopLaunch L{};
         L.prec = pr;
         L.stride = stride;
@@ -106,7 +114,9 @@ struct Solver {
         L.out = tmp;
         L.in = in;
         L.partials = nullptr;
+        if (evs) hipok(hipEventRecord(evs[0], st), "event");
         launch_hop(g, c->gs, L, st);
+        if (evs) hipok(hipEventRecord(evs[1], st), "event");
         L.kind = dag ? HOP_SCHUR_B_DAG : HOP_SCHUR_B;
         L.out_parity = 0;
         L.out = out;
@@ -114,14 +124,16 @@ struct Solver {
         L.centre = in;
         L.partials = partials;
         launch_hop(g, c->gs, L, st);
+        if (evs) hipok(hipEventRecord(evs[2], st), "event");
     }
 
     // inner-precision S or S^+ on all RHS, chunk by chunk; partials [n][nbh]
-    void schur_inner(const char* in, char* out, const int* mask, bool dag, double* partials) {
+    void schur_inner(const char* in, char* out, const int* mask, bool dag, double* partials,
+                     hipEvent_t* evs = nullptr) {
         for (int k0 = 0; k0 < n; k0 += chunk) {
             const int nk = std::min(chunk, n - k0);
             schur(pi, in + Hi * k0, out + Hi * k0, t, Hi, nk, coef + k0, mask ? mask + k0 : nullptr, dag,
-                  partials ? partials + size_t(k0) * nbh : nullptr);
+                  partials ? partials + size_t(k0) * nbh : nullptr, k0 == 0 ? evs : nullptr);
         }
     }
 
@@ -151,11 +163,11 @@ struct Solver {
     void one_iteration() {
         void* xcur = mixed ? static_cast<void*>(xl) : static_cast<void*>(xh);
         const size_t sxc = mixed ? Hx : H64;
-        schur_inner(p, q, act, false, part);
+        schur_inner(p, q, act, false, part, prof);
         launch_scalars(SC_ALPHA, part, nbh, n, act, sc, nullptr, st);
         launch_cg_xr(g, mixed ? px : P64, pi, xcur, sxc, r, p, q, Hi, n, act, sc, part, st);
         launch_scalars(SC_RR, part, nbb, n, act, sc, nullptr, st);
-        schur_inner(r, s, act, true, part);
+        schur_inner(r, s, act, true, part, prof ? prof + 3 : nullptr);
         launch_scalars(SC_BETA, part, nbh, n, act, sc, nullptr, st);
         launch_cg_p(g, pi, p, s, Hi, n, act, sc, st);
     }
@@ -384,6 +396,15 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         if (!S.hipok(hipGraphInstantiate(&S.gexec, S.graph, nullptr, nullptr, 0), "graph instantiate")) return S.err;
     }
 
+    // launch timing: sampled iterations from the third on (not with a graph)
+    const int nprof = use_graph ? 0 : std::max(0, std::min(o.profile_iters, 64));
+    int prof_done = 0;
+    for (int e = 0; e < 6 * nprof; ++e) {
+        hipEvent_t ev;
+        if (!S.hipok(hipEventCreate(&ev), "event")) return S.err;
+        S.pev.push_back(ev);
+    }
+
     const double tgt = 0.5 * o.tol;
     int it = 0;
     bool pending = false;
@@ -398,8 +419,13 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         return false;
     };
     while (any_active() && S.err == MDWF_OK) {
-        if (use_graph) S.hipok(hipGraphLaunch(S.gexec, st), "graph launch");
-        else S.one_iteration();
+        if (use_graph) {
+            S.hipok(hipGraphLaunch(S.gexec, st), "graph launch");
+        } else {
+            S.prof = (it >= 2 && prof_done < nprof) ? &S.pev[6 * prof_done++] : nullptr;
+            S.one_iteration();
+            S.prof = nullptr;
+        }
         ++it;
         for (int k = 0; k < n; ++k)
             if (active[k]) ++iters[k];
@@ -462,6 +488,18 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     }
     if (S.err) return S.err;
 
+    // mean launch durations of the sampled iterations (all complete by now)
+    double hop_us[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < prof_done && !S.err; ++j) {
+        S.hipok(hipEventSynchronize(S.pev[6 * j + 5]), "event sync");
+        for (int q = 0; q < 4; ++q) {
+            const int e0 = 6 * j + 3 * (q / 2) + (q % 2);
+            float ms = 0.f;
+            S.hipok(hipEventElapsedTime(&ms, S.pev[e0], S.pev[e0 + 1]), "event time");
+            hop_us[q] += 1e3 * ms / prof_done;
+        }
+    }
+
     // reconstruct every RHS, verify and write x
     for (int k = 0; k < n && !S.err; ++k) true_res[k] = verify(k, true);
     if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
@@ -489,6 +527,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             info[k].seconds = secs;
             info[k].model_bytes = iters[k] * it_bytes + (updates[k] + restarts[k] + 1) * up_bytes;
             info[k].model_flops = iters[k] * it_flops + (updates[k] + restarts[k] + 1) * up_flops;
+            for (int q = 0; q < 4; ++q) info[k].hop_us[q] = hop_us[q];
+            info[k].hop_rhs = prof_done ? std::min(S.chunk, n) : 0;
+            info[k].hop_samples = prof_done;
         }
     }
     if (result == MDWF_ERR_NOCONV) fail(c, result, "solver reached max_iter before the target residual");

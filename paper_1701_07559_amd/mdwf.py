@@ -48,20 +48,23 @@ class mdwf_action(C.Structure):
 
 class mdwf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner", C.c_int), ("delta", C.c_double),
-                ("check_every", C.c_int), ("use_graph", C.c_int)]
+                ("check_every", C.c_int), ("use_graph", C.c_int), ("profile_iters", C.c_int)]
 
 
 class mdwf_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("restarts", C.c_int),
                 ("true_resid", C.c_double), ("seconds", C.c_double), ("model_flops", C.c_double),
-                ("model_bytes", C.c_double)]
+                ("model_bytes", C.c_double), ("hop_us", C.c_double * 4), ("hop_rhs", C.c_int),
+                ("hop_samples", C.c_int)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["hop_us"] = list(self.hop_us)
+        return d
 
 
 class mdwf_launch_tune(C.Structure):
-    _fields_ = [("zblock", C.c_int), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_lds", C.c_int),
+    _fields_ = [("zblock", C.c_int), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int),
                 ("us", C.c_double)]
 
     def as_dict(self):

@@ -127,8 +127,10 @@ def test_operator_parity(M, geom, prec):
 
 
 LAUNCH_VARIANTS = [
-    {"MDWF_LINK_LDS": "1"},
-    {"MDWF_LINK_LDS": "1", "MDWF_NT_STORE": "1", "MDWF_XCD_REMAP": "0"},
+    {"MDWF_LINK_MODE": "1"},
+    {"MDWF_LINK_MODE": "1", "MDWF_NT_STORE": "1", "MDWF_XCD_REMAP": "0"},
+    {"MDWF_LINK_MODE": "2"},
+    {"MDWF_LINK_MODE": "2", "MDWF_NT_STORE": "1", "MDWF_XCD_REMAP": "0"},
     {"MDWF_ZBLOCK": "1", "MDWF_NT_STORE": "1"},
     {"MDWF_ZBLOCK": "2", "MDWF_XCD_REMAP": "0"},
 ]
@@ -137,10 +139,12 @@ LAUNCH_VARIANTS = [
 @pytest.mark.parametrize("env", LAUNCH_VARIANTS, ids=lambda e: "-".join("%s%s" % (k[5:], v) for k, v in e.items()))
 def test_operator_parity_launch_shapes(M, env, monkeypatch):
     """Every launch shape the autotuner can pick computes the same operators
-    (traversal order, XCD numbering, non-temporal stores, LDS link stage)."""
+    (traversal order, XCD numbering, non-temporal stores, link modes; L5 = 4
+    is the smallest group the FP32 lane gather accepts, L5 = 12 leaves idle
+    lanes in every wave)."""
     for k, v in env.items():
         monkeypatch.setenv(k, v)
-    for dims, L5 in (((6, 4, 2, 6), 8), ((4, 6, 6, 4), 12)):
+    for dims, L5 in (((6, 4, 2, 6), 8), ((4, 6, 6, 4), 12), ((4, 4, 2, 4), 4)):
         act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
         U = I.random_links(dims, 0.3, 49)
         psi = I.gaussian_source(dims, L5, 50)
@@ -148,8 +152,8 @@ def test_operator_parity_launch_shapes(M, env, monkeypatch):
         try:
             for prec in (0, 1, 2):
                 t = M.mdwf_get_tune(ctx, prec)
-                if "MDWF_LINK_LDS" in env:
-                    assert t["link_lds"] == 1
+                if "MDWF_LINK_MODE" in env:
+                    assert t["link_mode"] == int(env["MDWF_LINK_MODE"])
                 for op in (M.MDWF_OP_D5, M.MDWF_OP_D5_DAG, M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG,
                            M.MDWF_OP_HOP_EO, M.MDWF_OP_HOP_OE_DAG):
                     err = rel(gpu_op(M, ctx, op, prec, act, psi), oracle_op(M, op, act, U, psi))
@@ -252,6 +256,33 @@ def test_fp16_store_of_sites_below_float_range(M):
         M.mdwf_destroy(ctx)
 
 
+@pytest.mark.parametrize("op", ["D5", "SCHUR"])
+def test_fp16_prehop_wall_coupling_of_tiny_slice(M, op):
+    """FP16 kernels that apply B before the hop rescale the three slices they
+    combine by S = max(b5 n_s, c5 |f| n_s-1, c5 |f| n_s+1).  A site whose only
+    non-zero slice is s = L5-1 with norm 8e-36 makes S = c5 m_q n = 2e-39 on
+    slice 0 (wall coupling f = -m_q), whose reciprocal overflows FP32; the
+    result must stay finite and match.  (Outputs below the smallest normal
+    float are stored as zero; at this scale they are 3e-4 of the largest.)"""
+    dims, L5 = (4, 4, 2, 4), 8
+    act = oracle.Action(dims, L5, mq=0.0005)
+    U = I.random_links(dims, 0.3, 51)
+    psi = np.zeros(act.shape5, complex)
+    rng = np.random.default_rng(52)
+    for x in ((0, 0, 0, 0), (1, 0, 0, 0)):   # one site of each parity (x fastest)
+        v = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        psi[L5 - 1, x[3], x[2], x[1], x[0]] = 8e-36 * v / np.abs(np.stack([v.real, v.imag])).max()
+    code = getattr(M, "MDWF_OP_" + op)
+    ctx = make_ctx(M, act, U)
+    try:
+        out = gpu_op(M, ctx, code, 2, act, psi)
+        ref = oracle_op(M, code, act, U, psi)
+        assert np.all(np.isfinite(out))
+        assert rel(out, ref) <= TOL[2]
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 # ---------------------------------------------------------------- solver
 
 CFG1 = dict(dims=(4, 4, 4, 8), L5=8, M5=1.3, b5=1.5, c5=0.5, mq=0.05, eps=0.3, gseed=101, sseed=301)
@@ -299,6 +330,28 @@ def test_solve_graph_replay_matches_eager(M, cfg1):
         for x, it in xs[1:]:
             assert it == xs[0][1]
             assert np.array_equal(x, xs[0][0])
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_solve_launch_timing_changes_nothing(M, cfg1):
+    """profile_iters records HIP events around the batched hop launches of a
+    few iterations: positive durations, and the solution is bit-identical."""
+    act, U, b, _ = cfg1
+    bs = [b, 0.5 * b]
+    ctx = make_ctx(M, act, U)
+    try:
+        out = []
+        for prof in (0, 3):
+            xs = [np.zeros_like(v) for v in bs]
+            st, info = M.mdwf_solve(ctx, bs, xs, opts=dict(inner=2, profile_iters=prof))
+            assert st == M.MDWF_OK
+            out.append((xs, info))
+        (x0, i0), (x1, i1) = out
+        assert all(np.array_equal(a, c) for a, c in zip(x0, x1))
+        assert i0[0]["hop_samples"] == 0 and i0[0]["hop_us"] == [0.0] * 4
+        assert i1[0]["hop_samples"] == 3 and i1[0]["hop_rhs"] == 2
+        assert all(u > 0.0 for u in i1[0]["hop_us"])
     finally:
         M.mdwf_destroy(ctx)
 
