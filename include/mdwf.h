@@ -199,7 +199,10 @@ void mdwf_default_opts(mdwf_solver_opts *opts);
 
 /* Launch shape of the hop kernels for one storage precision. */
 typedef struct {
-    int zblock;      /* traversal: z-blocks of this many z-planes, t inside (divides Z) */
+    int tile[4];     /* traversal tile in parity-compressed sites (X/2, Y, Z, T
+                        extents, each dividing the lattice's): inside a tile x
+                        runs fastest, then y, z, t; tiles follow t fastest,
+                        then x, y, z.  {X/2, Y, zb, 1} are z-blocks, t inside */
     int xcd_remap;   /* 1: workgroups renumbered so each XCD walks one contiguous range */
     int nt_store;    /* 1: hop outputs written with non-temporal stores               */
     int link_mode;   /* links: 0 loaded by every lane, 1 staged in LDS (L5 >= 8),
@@ -209,10 +212,12 @@ typedef struct {
 } mdwf_launch_tune;
 
 /* Autotuner: for each precision (index mdwf_prec), time one Schur operator
- * application (the two fused hop kernels) for every candidate launch shape on
- * scratch fields and keep the fastest in the context.  out[3] (may be NULL)
- * receives the chosen shapes.  Needs the action and gauge field; allocates
- * scratch device memory (three half fields of each precision). */
+ * application (the two fused hop kernels) on scratch fields, choosing in turn
+ * the traversal tile (z-blocks and compact 4D tiles), the link mode, then
+ * non-temporal stores and workgroup numbering, and keep the fastest in the
+ * context.  out[3] (may be NULL) receives the chosen shapes.  Needs the
+ * action and gauge field; allocates scratch device memory (three half fields
+ * of each precision). */
 mdwf_status mdwf_autotune(mdwf_ctx *ctx, mdwf_launch_tune *out);
 
 /* Current launch shape of precision `prec` (defaults before autotuning). */

@@ -1,4 +1,5 @@
 // C ABI of libmdwf: context, gauge upload, action, operator application.
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -112,9 +113,23 @@ void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes) {
     *bytes = b * Vh;
 }
 
+bool tile_fits(const Geo& g, const int b[4]) {
+    const int ext[4] = {g.Xh, g.Y, g.Z, g.T};
+    for (int k = 0; k < 4; ++k)
+        if (b[k] < 1 || ext[k] % b[k] != 0) return false;
+    return true;
+}
+
 void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
-    g.zb[p] = t.zblock;
-    g.fZb[p] = FastDiv(uint32_t(t.zblock));
+    Trav& tr = g.trav[p];
+    for (int k = 0; k < 4; ++k) tr.b[k] = t.tile[k];
+    tr.fTv = FastDiv(uint32_t(t.tile[0] * t.tile[1] * t.tile[2] * t.tile[3]));
+    tr.fBx = FastDiv(uint32_t(t.tile[0]));
+    tr.fBy = FastDiv(uint32_t(t.tile[1]));
+    tr.fBz = FastDiv(uint32_t(t.tile[2]));
+    tr.fNt = FastDiv(uint32_t(g.T / t.tile[3]));
+    tr.fNx = FastDiv(uint32_t(g.Xh / t.tile[0]));
+    tr.fNy = FastDiv(uint32_t(g.Y / t.tile[1]));
     g.xcd_remap[p] = t.xcd_remap ? 1 : 0;
     g.nt_store[p] = t.nt_store ? 1 : 0;
     g.link_mode[p] = (t.link_mode >= 0 && t.link_mode <= 2) ? t.link_mode : 0;
@@ -263,15 +278,14 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     g.fXh = FastDiv(uint32_t(g.Xh));
     g.fY = FastDiv(uint32_t(g.Y));
     g.fZ = FastDiv(uint32_t(g.Z));
-    g.plane = g.Xh * g.Y;
-    g.fPlane = FastDiv(uint32_t(g.plane));
-    g.fT = FastDiv(uint32_t(g.T));
-    // default launch shape (mdwf_autotune refines it per precision); the
-    // MDWF_ZBLOCK / MDWF_XCD_REMAP / MDWF_NT_STORE variables override it
-    mdwf_launch_tune t0{(g.Z % 4 == 0) ? 4 : 2, 1, 0, 0, 0.0};
-    if (const char* e = std::getenv("MDWF_ZBLOCK")) {
-        const int v = std::atoi(e);
-        if (v >= 1 && g.Z % v == 0) t0.zblock = v;
+    // default launch shape (mdwf_autotune refines it per precision): z-blocks
+    // of 4 (or 2) planes with t inside; the MDWF_TILE ("bx,by,bz,bt"),
+    // MDWF_XCD_REMAP, MDWF_NT_STORE and MDWF_LINK_MODE variables override it
+    mdwf_launch_tune t0{{g.Xh, g.Y, (g.Z % 4 == 0) ? 4 : 2, 1}, 1, 0, 0, 0.0};
+    if (const char* e = std::getenv("MDWF_TILE")) {
+        int b[4];
+        if (std::sscanf(e, "%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3]) == 4 && tile_fits(g, b))
+            for (int k = 0; k < 4; ++k) t0.tile[k] = b[k];
     }
     if (const char* e = std::getenv("MDWF_XCD_REMAP")) t0.xcd_remap = std::atoi(e) != 0;
     if (const char* e = std::getenv("MDWF_NT_STORE")) t0.nt_store = std::atoi(e) != 0;
@@ -457,7 +471,7 @@ mdwf_status mdwf_op_model(const mdwf_ctx* c, mdwf_op op, mdwf_prec prec, double*
 mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* out) {
     if (!c || !out) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "null argument");
     if (!valid_prec(prec)) return fail(const_cast<mdwf_ctx*>(c), MDWF_ERR_ARG, "bad precision");
-    out->zblock = c->geo.zb[prec];
+    for (int k = 0; k < 4; ++k) out->tile[k] = c->geo.trav[prec].b[k];
     out->xcd_remap = c->geo.xcd_remap[prec];
     out->nt_store = c->geo.nt_store[prec];
     out->link_mode = c->geo.link_mode[prec];
@@ -470,11 +484,25 @@ mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
     if (s) return s;
     Geo& g = c->geo;
     hipStream_t st = c->stream;
-    // candidate z-block depths: small powers of two dividing Z, and Z itself
-    std::vector<int> zbs;
-    for (int v : {1, 2, 4, 8, 16})
-        if (g.Z % v == 0) zbs.push_back(v);
-    if (g.Z > 16) zbs.push_back(g.Z);
+    // traversal tiles: z-blocks (full x-y planes, t inside) of small
+    // power-of-two depth and of Z, and compact 4D tiles of 384..6912 sites
+    std::vector<std::array<int, 4>> tiles;
+    auto add_tile = [&](int bx, int by, int bz, int bt) {
+        const int b4[4] = {bx, by, bz, bt};
+        if (!tile_fits(g, b4)) return;
+        for (const auto& t : tiles)
+            if (t[0] == bx && t[1] == by && t[2] == bz && t[3] == bt) return;
+        tiles.push_back({bx, by, bz, bt});
+    };
+    for (int v : {1, 2, 4, 8, 16}) add_tile(g.Xh, g.Y, v, 1);
+    add_tile(g.Xh, g.Y, g.Z, 1);
+    for (int bx : {g.Xh, g.Xh / 2})
+        for (int by : {4, 6, 8, 12, g.Y})
+            for (int bz : {2, 4, 6, 8})
+                for (int bt : {1, 2, 4}) {
+                    const long vol = long(bx) * by * bz * bt;
+                    if (vol >= 384 && vol <= 6912 && (by < g.Y || bt > 1)) add_tile(bx, by, bz, bt);
+                }
     const size_t canon = size_t(g.Vh) * 24 * sizeof(double);
     void* cin = buf(c, "tune_canon", canon, &s);
     if (!cin) return s;
@@ -483,36 +511,59 @@ mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
     hipEvent_t e0, e1;
     if ((s = hip_check(c, hipEventCreate(&e0), "event"))) return s;
     if ((s = hip_check(c, hipEventCreate(&e1), "event"))) return s;
-    for (int pi = 0; pi < 3; ++pi) {
+    for (int pi = 0; pi < 3 && !s; ++pi) {
         const Prec p = Prec(pi);
         const size_t hb = half_field_bytes(p, g.Vh);
         void* a = buf(c, "tune_a", 2 * half_field_bytes(P64, g.Vh), &s);
         void* b = a ? buf(c, "tune_b", 2 * half_field_bytes(P64, g.Vh), &s) : nullptr;
         if (!a || !b) break;
         launch_pack_parity(g, p, 0, 0, static_cast<const double*>(cin), a, st);
-        mdwf_launch_tune best{g.zb[p], g.xcd_remap[p], g.nt_store[p], g.link_mode[p], 1e30};
-        std::vector<int> modes{0};
-        if (64 / g.L5 <= 8) modes.push_back(1);
-        if (p != P64 && g.L5 >= (p == P32 ? 4 : 2)) modes.push_back(2);
-        for (int zb : zbs)
-            for (int rm = 1; rm >= 0; --rm)
-                for (int nt = 0; nt <= 1; ++nt)
-                for (int ll : modes) {
-                    mdwf_launch_tune cand{zb, rm, nt, ll, 0.0};
-                    set_tune(g, p, cand);
-                    const int warm = 2, reps = 5;
-                    for (int r = 0; r < warm; ++r)
-                        if ((s = apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st))) break;
-                    if (s) break;
-                    (void)hipEventRecord(e0, st);
-                    for (int r = 0; r < reps; ++r) apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st);
-                    (void)hipEventRecord(e1, st);
-                    if ((s = hip_check(c, hipEventSynchronize(e1), "autotune"))) break;
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    cand.us = 1e3 * ms / reps;
-                    if (cand.us < best.us) best = cand;
-                }
+        // time one Schur application (2 warm-up, mean of 5) with shape t
+        auto timed = [&](mdwf_launch_tune t) -> mdwf_launch_tune {
+            set_tune(g, p, t);
+            const int warm = 2, reps = 5;
+            for (int r = 0; r < warm && !s; ++r)
+                s = apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st);
+            if (s) return t;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps; ++r) apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st);
+            (void)hipEventRecord(e1, st);
+            if ((s = hip_check(c, hipEventSynchronize(e1), "autotune"))) return t;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t.us = 1e3 * ms / reps;
+            return t;
+        };
+        mdwf_launch_tune best{};
+        for (int k = 0; k < 4; ++k) best.tile[k] = g.trav[p].b[k];
+        best.xcd_remap = 1;
+        best.us = 1e30;
+        // coordinate descent: traversal tile, then link mode, then stores and
+        // workgroup numbering
+        for (const auto& tl : tiles) {
+            mdwf_launch_tune t = best;
+            for (int k = 0; k < 4; ++k) t.tile[k] = tl[k];
+            t = timed(t);
+            if (s) break;
+            if (t.us < best.us) best = t;
+        }
+        std::vector<int> modes{1, 2};
+        for (int lm : modes) {
+            if (s) break;
+            if (lm == 1 && 64 / g.L5 > 8) continue;
+            if (lm == 2 && (p == P64 || g.L5 < (p == P32 ? 4 : 2))) continue;
+            mdwf_launch_tune t = best;
+            t.link_mode = lm;
+            t = timed(t);
+            if (!s && t.us < best.us) best = t;
+        }
+        for (int v = 0; v < 2 && !s; ++v) {
+            mdwf_launch_tune t = best;
+            if (v == 0) t.nt_store = 1 - t.nt_store;
+            else t.xcd_remap = 1 - t.xcd_remap;
+            t = timed(t);
+            if (!s && t.us < best.us) best = t;
+        }
         if (s) break;
         set_tune(g, p, best);
         c->tuned_us[pi] = best.us;

@@ -527,21 +527,22 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     const int pos = (tile * kWaves + wave) * spw + sw;   // traversal position
     const bool valid = (sw < spw) && (pos < g.Vh4);
     const int gbase = lane - s;
-    // position -> (z-block, t, z in block, plane index) -> coordinates and the
-    // parity-compressed index i of the output site
+    // traversal position -> tile and place inside it (see Trav) ->
+    // coordinates and the parity-compressed index i of the output site
     int xh, y, z, t, i;
     {
-        const int zb = g.zb[P];
-        const uint32_t q = g.fPlane.div(uint32_t(pos));
-        const int yx = pos - int(q) * g.plane;
-        const uint32_t q2 = g.fZb[P].div(q);
-        const int zz = int(q) - int(q2) * zb;
-        const uint32_t q3 = g.fT.div(q2);
-        t = int(q2) - int(q3) * g.T;
-        z = int(q3) * zb + zz;
-        y = int(g.fXh.div(uint32_t(yx)));
-        xh = yx - y * g.Xh;
-        i = yx + g.plane * (z + g.Z * t);
+        const Trav& tr = g.trav[P];
+        const uint32_t p = uint32_t(pos);
+        const uint32_t q = tr.fTv.div(p);               // tile number
+        const uint32_t r = p - q * uint32_t(tr.b[0] * tr.b[1] * tr.b[2] * tr.b[3]);
+        const uint32_t r1 = tr.fBx.div(r), r2 = tr.fBy.div(r1), r3 = tr.fBz.div(r2);   // in-tile
+        const uint32_t q1 = tr.fNt.div(q), q2 = tr.fNx.div(q1), q3 = tr.fNy.div(q2);   // tile grid
+        const uint32_t nt = tr.fNt.d, nx = tr.fNx.d, ny = tr.fNy.d;
+        xh = int(q1 - q2 * nx) * tr.b[0] + int(r - r1 * uint32_t(tr.b[0]));
+        y = int(q2 - q3 * ny) * tr.b[1] + int(r1 - r2 * uint32_t(tr.b[1]));
+        z = int(q3) * tr.b[2] + int(r2 - r3 * uint32_t(tr.b[2]));
+        t = int(q - q1 * nt) * tr.b[3] + int(r3);
+        i = xh + g.Xh * (y + g.Y * (z + g.Z * t));
     }
 
     const RhsCoef& cf = a.coef[rhs];

@@ -70,6 +70,18 @@ struct FastDiv {
     }
 };
 
+// Traversal order of the hop kernels over the Xh x Y x Z x T parity-
+// compressed 4D sites of one parity: tiles of b[0] x b[1] x b[2] x b[3]
+// sites (each extent divides the lattice's); inside a tile x runs fastest,
+// then y, z, t; tiles follow each other t fastest, then x, y, z.  Tiles of
+// full x-y planes and b[3] = 1 are z-blocks with t inside; compact 4D tiles
+// keep most neighbours of a site a few tiles apart in traversal order.
+struct Trav {
+    int b[4];
+    FastDiv fTv, fBx, fBy, fBz;   // tile volume and extents
+    FastDiv fNt, fNx, fNy;        // tiles along t, x, y
+};
+
 // -------------------------------------------------------------- geometry
 struct Geo {
     int X, Y, Z, T, Xh;
@@ -78,14 +90,8 @@ struct Geo {
     int Vh;    // 5D sites of one parity = Vh4 * L5
     int antiperiodic;
     FastDiv fXh, fY, fZ;
-    // Traversal order of the hop kernels: z-blocks of zb slices, inside a
-    // block t, then z, then the (x, y) plane of Xh * Y sites.  Neighbours
-    // across t are then zb planes apart instead of a whole time slice.
-    int plane;   // Xh * Y
-    FastDiv fPlane, fT;
     // launch shape per storage precision (index Prec), set by the autotuner
-    int zb[3];          // z-block depth, divides Z
-    FastDiv fZb[3];
+    Trav trav[3];
     int xcd_remap[3];   // renumber workgroups per XCD (1) or keep hardware order (0)
     int nt_store[3];    // write hop outputs with non-temporal stores
     int link_mode[3];   // 0 per-lane links, 1 LDS stage, 2 lane gather

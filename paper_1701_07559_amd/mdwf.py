@@ -64,11 +64,13 @@ class mdwf_solve_info(C.Structure):
 
 
 class mdwf_launch_tune(C.Structure):
-    _fields_ = [("zblock", C.c_int), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int),
+    _fields_ = [("tile", C.c_int * 4), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int),
                 ("us", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["tile"] = list(self.tile)
+        return d
 
 
 class MdwfError(RuntimeError):

@@ -131,9 +131,21 @@ LAUNCH_VARIANTS = [
     {"MDWF_LINK_MODE": "1", "MDWF_NT_STORE": "1", "MDWF_XCD_REMAP": "0"},
     {"MDWF_LINK_MODE": "2"},
     {"MDWF_LINK_MODE": "2", "MDWF_NT_STORE": "1", "MDWF_XCD_REMAP": "0"},
-    {"MDWF_ZBLOCK": "1", "MDWF_NT_STORE": "1"},
-    {"MDWF_ZBLOCK": "2", "MDWF_XCD_REMAP": "0"},
+    {"MDWF_TILE": "zblock1", "MDWF_NT_STORE": "1"},
+    {"MDWF_TILE": "zblock2", "MDWF_XCD_REMAP": "0"},
+    {"MDWF_TILE": "compact"},
+    {"MDWF_TILE": "compact", "MDWF_LINK_MODE": "2", "MDWF_XCD_REMAP": "0"},
 ]
+
+
+def tile_for(kind, dims):
+    """Traversal tile (parity-compressed x, y, z, t) of the named kind."""
+    X, Y, Z, T = dims
+    Xh = X // 2
+    if kind.startswith("zblock"):
+        return (Xh, Y, int(kind[6:]), 1)
+    # compact 4D tile: halves of the extents where they are even
+    return tuple(e // 2 if e % 2 == 0 else e for e in (Xh, Y, Z, T))
 
 
 @pytest.mark.parametrize("env", LAUNCH_VARIANTS, ids=lambda e: "-".join("%s%s" % (k[5:], v) for k, v in e.items()))
@@ -143,8 +155,12 @@ def test_operator_parity_launch_shapes(M, env, monkeypatch):
     is the smallest group the FP32 lane gather accepts, L5 = 12 leaves idle
     lanes in every wave)."""
     for k, v in env.items():
-        monkeypatch.setenv(k, v)
+        if k != "MDWF_TILE":
+            monkeypatch.setenv(k, v)
     for dims, L5 in (((6, 4, 2, 6), 8), ((4, 6, 6, 4), 12), ((4, 4, 2, 4), 4)):
+        tile = tile_for(env["MDWF_TILE"], dims) if "MDWF_TILE" in env else None
+        if tile:
+            monkeypatch.setenv("MDWF_TILE", ",".join(map(str, tile)))
         act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
         U = I.random_links(dims, 0.3, 49)
         psi = I.gaussian_source(dims, L5, 50)
@@ -154,6 +170,8 @@ def test_operator_parity_launch_shapes(M, env, monkeypatch):
                 t = M.mdwf_get_tune(ctx, prec)
                 if "MDWF_LINK_MODE" in env:
                     assert t["link_mode"] == int(env["MDWF_LINK_MODE"])
+                if tile:
+                    assert tuple(t["tile"]) == tile
                 for op in (M.MDWF_OP_D5, M.MDWF_OP_D5_DAG, M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG,
                            M.MDWF_OP_HOP_EO, M.MDWF_OP_HOP_OE_DAG):
                     err = rel(gpu_op(M, ctx, op, prec, act, psi), oracle_op(M, op, act, U, psi))
@@ -172,7 +190,7 @@ def test_autotune_keeps_parity(M):
         tunes = M.mdwf_autotune(ctx)
         assert len(tunes) == 3 and all(t["us"] > 0 for t in tunes)
         for prec in (0, 1, 2):
-            assert M.mdwf_get_tune(ctx, prec)["zblock"] == tunes[prec]["zblock"]
+            assert M.mdwf_get_tune(ctx, prec)["tile"] == tunes[prec]["tile"]
             for op in (M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG, M.MDWF_OP_D5):
                 assert rel(gpu_op(M, ctx, op, prec, act, psi), oracle_op(M, op, act, U, psi)) <= TOL[prec]
     finally:
