@@ -16,6 +16,9 @@ FP64 true-residual check of every column to 1e-10.
 
 value = algorithmic HBM bytes of the step (model of every kernel it ran) /
 step time, in GB/s.  Inputs are resident in HBM before the timed region.
+
+--workload batched: the a12m220 volume, 32^3 x 64 at L5 = 10, 36 RHS (the
+12 columns at m_q = 0.0074, 0.02, 0.04) as three multi-mass launches of 12.
 Beside it: the solve time of plain FP64 CG on the same columns, the dslash
 kernels' achieved bandwidth against the 8 TB/s HBM peak (timed with HIP events
 on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
@@ -35,6 +38,20 @@ DIMS = (24, 24, 24, 64)
 L5 = 8
 ACTION = dict(M5=1.3, b5=1.5, c5=0.5, mq=0.0102)
 EPS, GAUGE_SEED, SITE_SEED, SRC_SEED = 0.25, 103, 403, 303
+MASSES = [0.0102]
+GROUPS = 1   # launches per step; the RHS are split evenly over them
+
+# Workloads: "mixed" is the headline one (the a12m310 volume, Table I);
+# "batched" is the a12m220 volume (Table I) at L5 = 10 with the 12 columns of
+# one point source at three masses, 36 RHS.  Its canonical FP64 solutions
+# (4 GB each) cannot all stay in HBM beside the solver state, so the step is
+# three multi-mass launches of 12 RHS (4 columns x 3 masses each), every
+# input and output resident in HBM.
+WORKLOADS = {
+    "mixed": dict(DIMS=(24, 24, 24, 64), L5=8, MASSES=[0.0102], GAUGE_SEED=103, SITE_SEED=403, GROUPS=1),
+    "batched": dict(DIMS=(32, 32, 32, 64), L5=10, MASSES=[0.0074, 0.02, 0.04], GAUGE_SEED=104, SITE_SEED=404,
+                    GROUPS=3),
+}
 
 
 def log(*a):
@@ -129,9 +146,137 @@ def roofline(info, inner, Vh):
                           for n, u, b in zip(names, us, by)})
 
 
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1701_07559_amd", "csrc", "dslash.hip")
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "schur_f16_24c64_L8_12rhs_counters.md")
+
+
+def kernel_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic():
+    """Per-launch HBM traffic of the batched FP16 S launches (kernels A + B)
+    recorded by a counter run, if the hop source is unchanged since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("traffic-record: "):
+                    rec = json.loads(line[len("traffic-record: "):])
+                    if rec.get("dslash_sha256") == kernel_sha():
+                        return rec
+    except OSError:
+        pass
+    return None
+
+
+def _kernel_label(name):
+    import re
+    n = re.sub(r"\(mdwf::Geo.*", "", name).replace("void ", "")
+    return n.replace("(mdwf::Prec)0", "F64").replace("(mdwf::Prec)1", "F32").replace("(mdwf::Prec)2", "F16")
+
+
+def summarize(args):
+    """Markdown summary of rocprofv3 databases: kernel-trace statistics, the
+    12-RHS kernel A / B launches of the solve (selected by grid size), and
+    FETCH_SIZE / WRITE_SIZE per launch calibrated on the 1 GiB copy."""
+    import collections
+    import sqlite3
+    X, Y, Z, T = DIMS
+    Vh4 = X * Y * Z * T // 2
+    Vh = Vh4 * L5
+    nblk = (Vh4 + 4 * (64 // L5) - 1) // (4 * (64 // L5))
+    grid12 = nblk * 12 * 256
+    lines = []
+    cmds = [c for c in args.summary_cmds.split("||") if c.strip()]
+    lines.append("# rocprofv3 summary: batched FP16 Schur operator in bench.py (24^3x64, L5=8, 12 RHS)")
+    lines.append("")
+    lines.append("Commands (repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):")
+    lines.append("")
+    for c in cmds:
+        lines.append("    " + c.strip())
+    lines.append("")
+    db = sqlite3.connect(args.summarize[0])
+    rows = db.execute("select name, duration, grid_x from kernels").fetchall()
+    agg = collections.defaultdict(list)
+    for name, dur, gx in rows:
+        agg[_kernel_label(name)].append(dur / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    lines.append("Kernel trace (all dispatches of the run):")
+    lines.append("")
+    lines.append("| kernel | calls | total us | average us | % |")
+    lines.append("|---|---|---|---|---|")
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:16]:
+        lines.append("| `%s` | %d | %.1f | %.2f | %.1f |" % (k[:90], len(v), sum(v), sum(v) / len(v), 100 * sum(v) / tot))
+    lines.append("")
+    sel = collections.defaultdict(list)
+    for name, dur, gx in rows:
+        lab = _kernel_label(name)
+        if gx == grid12 and lab.startswith("mdwf::k_hop<F16"):
+            kind = int(lab.split(",")[1])
+            sel[kind].append(dur / 1e3)
+    names = {3: "A", 4: "B", 5: "A_dag", 6: "B_dag"}
+    lines.append("12-RHS launches of the solve (grid %d threads):" % grid12)
+    lines.append("")
+    lines.append("| kernel | launches | average us |")
+    lines.append("|---|---|---|")
+    for kind in (3, 4, 5, 6):
+        v = sel.get(kind, [])
+        if v:
+            lines.append("| %s (`k_hop<F16, %d, *>`) | %d | %.1f |" % (names[kind], kind, len(v), sum(v) / len(v)))
+    lines.append("")
+    rec = None
+    if args.summarize[1] != "-" and args.summarize[2] != "-":
+        def counters(path, cname):
+            d = sqlite3.connect(path)
+            out = collections.defaultdict(list)
+            for kn, gsz, val in d.execute("select kernel_name, grid_size, value from counters_collection "
+                                         "where counter_name = ?", (cname,)):
+                lab = _kernel_label(kn)
+                if gsz == grid12 and lab.startswith("mdwf::k_hop<F16"):
+                    out[int(lab.split(",")[1])].append(val)
+                elif "copybuffer" in lab.lower():
+                    out["copy"].append(val)   # the largest is the 1 GiB calibration copy
+            return out
+        fe = counters(args.summarize[1], "FETCH_SIZE")
+        wr = counters(args.summarize[2], "WRITE_SIZE")
+        gib = float(1 << 30)
+        f_r = gib / (max(fe["copy"]) * 1024.0)
+        f_w = gib / (max(wr["copy"]) * 1024.0)
+        lines.append("Counters (KiB per dispatch; calibration: the 1 GiB device copy reads %.3f GiB by "
+                     "FETCH_SIZE and writes %.3f GiB by WRITE_SIZE, so FETCH_SIZE is scaled by %.3f and "
+                     "WRITE_SIZE by %.3f):" % (1 / f_r, 1 / f_w, f_r, f_w))
+        lines.append("")
+        lines.append("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |")
+        lines.append("|---|---|---|---|")
+        per = {}
+        for kind in (3, 4, 5, 6):
+            if fe.get(kind) and wr.get(kind):
+                fk = sum(fe[kind]) / len(fe[kind])
+                wk = sum(wr[kind]) / len(wr[kind])
+                per[kind] = fk * 1024 * f_r + wk * 1024 * f_w
+                lines.append("| %s | %.0f | %.0f | %.4g |" % (names[kind], fk, wk, per[kind]))
+        lines.append("")
+        if 3 in per and 4 in per:
+            rec = dict(traffic_bytes_per_launch=per[3] + per[4], kernels="A+B, 12 RHS, FP16",
+                       fetch_scale=round(f_r, 4), write_scale=round(f_w, 4), dslash_sha256=kernel_sha())
+            lines.append("HBM traffic of one batched S application (kernels A + B): %.4g bytes." %
+                         rec["traffic_bytes_per_launch"])
+            lines.append("")
+            lines.append("traffic-record: " + json.dumps(rec))
+    text = "\n".join(lines) + "\n"
+    if args.summary_out:
+        with open(args.summary_out, "w") as f:
+            f.write(text)
+    print(text)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="mixed")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--inner", choices=["f16", "f32"], default="f16")
@@ -147,8 +292,23 @@ def main():
     ap.add_argument("--micro-precs", default="f64,f32,f16")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--max-iter", type=int, default=50000,
+                    help="cap on CG iterations (a short cap only for counter runs)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
+                    help="write the rocprofv3 summary of the dominant kernels (no GPU use); "
+                         "FETCH_DB / WRITE_DB may be '-'")
+    ap.add_argument("--summary-out", default=None)
+    ap.add_argument("--summary-cmds", default="", help="commands that produced the databases ('||'-separated)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
 
+    global DIMS, L5, MASSES, GAUGE_SEED, SITE_SEED, GROUPS
+    wl = WORKLOADS[args.workload]
+    DIMS, L5, MASSES, GROUPS = wl["DIMS"], wl["L5"], wl["MASSES"], wl["GROUPS"]
+    GAUGE_SEED, SITE_SEED = wl["GAUGE_SEED"], wl["SITE_SEED"]
+    ACTION["mq"] = MASSES[0]
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
@@ -206,29 +366,42 @@ def main():
         return
 
     # right-hand sides: the 12 spin-colour columns of a point source, FP64
-    # canonical, built on the device
-    nrhs = args.nrhs
+    # canonical, built on the device; RHS k is column k // len(MASSES) at
+    # mass k % len(MASSES)
+    nrhs = args.nrhs if args.workload == "mixed" else 12 * len(MASSES)
+    ncol = min(12, nrhs) if args.workload == "mixed" else 12
     ncan = L5 * V * 24
-    b = torch.zeros((nrhs, ncan), dtype=torch.float64, device=dev)
-    x = torch.zeros_like(b)
+    b = torch.zeros((ncol, ncan), dtype=torch.float64, device=dev)
     xs, ys, zs, ts = site
-    for k in range(nrhs):
-        col = k % 12
-        spin, colour = col // 3, col % 3
+    for k in range(ncol):
+        spin, colour = k // 3, k % 3
         s = L5 - 1 if spin < 2 else 0
         idx = ((((s * T + ts) * Z + zs) * Y + ys) * X + xs) * 12 + spin * 3 + colour
         b[k, 2 * idx] = 1.0
+    per = nrhs // GROUPS
+    x = torch.zeros((per, ncan), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    rhs_col = [(k // len(MASSES)) % ncol for k in range(nrhs)]
+    rhs_mass = [MASSES[k % len(MASSES)] for k in range(nrhs)]
     inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
     # profile_iters: the library times its batched hop launches of 10 CG
     # iterations with HIP events on the solve stream (the roofline figure)
-    opts = dict(tol=1e-10, inner=inner, max_iter=50000, delta=0.1, use_graph=args.graph,
+    opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1, use_graph=args.graph,
                 profile_iters=0 if args.graph else 10)
-    bptr = [b[k].data_ptr() for k in range(nrhs)]
-    xptr = [x[k].data_ptr() for k in range(nrhs)]
+    bptr = [b[rhs_col[k]].data_ptr() for k in range(nrhs)]
+    xptr = [x[k].data_ptr() for k in range(per)]
 
     def step():
-        return M.mdwf_solve_dev(ctx, bptr, xptr, opts=opts, stream=stream)
+        """The whole step: every launch group solved to 1e-10 (status, infos)."""
+        st_all, info_all = M.MDWF_OK, []
+        for g in range(GROUPS):
+            ks = range(g * per, (g + 1) * per)
+            st, inf = M.mdwf_solve_dev(ctx, [bptr[k] for k in ks], xptr, mq=[rhs_mass[k] for k in ks],
+                                       opts=opts, stream=stream)
+            if st != M.MDWF_OK and st_all == M.MDWF_OK:
+                st_all = st
+            info_all += inf
+        return st_all, info_all
 
     for w in range(args.warmup):
         st, info = step()
@@ -259,7 +432,7 @@ def main():
         it64 = []
         for k in range(min(args.fp64_cols, nrhs)):
             t_a = time.perf_counter()
-            st64, i64 = M.mdwf_solve_dev(ctx, [bptr[k]], [xptr[k]], opts=o64, stream=stream)
+            st64, i64 = M.mdwf_solve_dev(ctx, [bptr[k]], [xptr[0]], mq=[rhs_mass[k]], opts=o64, stream=stream)
             torch.cuda.synchronize()
             t64.append(time.perf_counter() - t_a)
             it64.append(i64[0]["iters"])
@@ -277,6 +450,11 @@ def main():
         log("cpu oracle %.3f GB/s" % cpu["value"])
 
     roof = roofline(infos[0], args.inner, V * L5 // 2)
+    rec = stored_traffic() if (roof and args.inner == "f16" and args.workload == "mixed" and nrhs == 12) else None
+    if rec:
+        roof["traffic"] = round(rec["traffic_bytes_per_launch"], 0)
+        roof["traffic_note"] = "HBM bytes per S application (kernels A + B) from rocprofv3 FETCH_SIZE / WRITE_SIZE, " \
+                               "scaled by the 1 GiB copy calibration; %s" % os.path.relpath(TRAFFIC_FILE)
 
     out = {
         "metric": "Moebius DWF dslash GB/s (% HBM peak); time to r=1e-10 solve, mixed vs FP64",
@@ -292,10 +470,13 @@ def main():
         "dtype": args.inner,
         "data": "synthetic",
         "config": {
-            "workload": "24^3x64 L5=8 M5=1.3 b5=1.5 c5=0.5 m_q=0.0102, exp(i0.25H) links (plaquette %.3f), "
-                        "%d point-source columns, one multi-RHS %s-inner solve to true residual 1e-10" %
-                        (plaq, nrhs, args.inner),
-            "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "inner": args.inner,
+            "workload": "%dx%dx%dx%d L5=%d M5=1.3 b5=1.5 c5=0.5 m_q=%s, exp(i0.25H) links (plaquette %.3f), "
+                        "%d point-source RHS (%d columns x %d masses) in %d multi-RHS %s-inner launch(es) of %d, "
+                        "each to true residual 1e-10" %
+                        (X, Y, Z, T, L5, "/".join(str(m) for m in MASSES), plaq, nrhs, ncol, len(MASSES),
+                         GROUPS, args.inner, per),
+            "name": args.workload,
+            "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": args.inner,
             "launch_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), tune)} if tune else None),
         },
         "solve": {

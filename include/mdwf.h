@@ -183,6 +183,8 @@ mdwf_status mdwf_apply_dev(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const void
 /* Solve D5 x_k = b_k for k < nrhs (host canonical full FP64 fields).
  * mq: per-RHS quark mass (NULL = the action's m_q); all other action
  * parameters are shared.  info: array of nrhs records (may be NULL).
+ * All RHS share every operator launch; when their vectors do not fit in
+ * free device memory together, consecutive sub-batches are solved in turn.
  * Returns ERR_NOCONV if any RHS hit max_iter (its best x is still written). */
 mdwf_status mdwf_solve(mdwf_ctx *ctx, int nrhs, const double *const *b, double *const *x,
                        const double *mq, const mdwf_solver_opts *opts, mdwf_solve_info *info);
@@ -208,6 +210,9 @@ typedef struct {
     int link_mode;   /* links: 0 loaded by every lane, 1 staged in LDS (L5 >= 8),
                         2 one 16-byte part per lane, gathered by lane exchange
                         (FP32 / FP16, L5 >= 4 / 2); otherwise 0 is used      */
+    int rhs_group;   /* multi-RHS launches: groups of this many RHS sweep the tiles
+                        together, RHS fastest (they share each tile's links);
+                        groups follow each other; 0 = all RHS in one group    */
     double us;       /* measured time of one Schur application with this shape (us)   */
 } mdwf_launch_tune;
 

@@ -75,6 +75,7 @@ def _load():
             ("oracle_hop", [P, d, d, d, C.c_int, C.c_int], None),
             ("oracle_D5", [P, d, d, d, C.c_int], None),
             ("oracle_schur", [P, d, d, d, C.c_int], None),
+            ("oracle_schur_sym", [P, d, d, d, C.c_int], None),
             ("oracle_prep_source", [P, d, d, d], None),
             ("oracle_reconstruct", [P, d, d, d], None),
             ("oracle_true_residual", [P, d, d, d], C.c_double),
@@ -184,6 +185,15 @@ def schur(act: Action, U, psi, dag=False):
     psi, pi = _c(psi)
     out = np.empty_like(psi)
     _load().oracle_schur(C.byref(act.params()), pu, pi, out.ctypes.data, int(dag))
+    return out
+
+
+def schur_sym(act: Action, U, psi, dag=False):
+    """Symmetric even-odd operator K5^-1 S (or S^+ K5^-+) on the even sites."""
+    U, pu = _c(U)
+    psi, pi = _c(psi)
+    out = np.empty_like(psi)
+    _load().oracle_schur_sym(C.byref(act.params()), pu, pi, out.ctypes.data, int(dag))
     return out
 
 

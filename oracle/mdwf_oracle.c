@@ -431,6 +431,29 @@ void oracle_schur(const oracle_params *p, const double *Ud, const double *ind, d
     free(x); free(t1); free(t2);
 }
 
+/* Symmetric form of the even-odd operator (Sec. VII names it beside the
+ * asymmetric one): Shat = K5^-1 S = 1 - 1/4 K5^-1 D_eo B K5^-1 D_oe B on the
+ * even sites, or its adjoint Shat^+ = S^+ K5^-+.  Solving Shat x_e = K5^-1 b'_e
+ * gives the same x_e as S x_e = b'_e. */
+void oracle_schur_sym(const oracle_params *p, const double *Ud, const double *ind, double *outd, int dag)
+{
+    cplx *out = (cplx *)outd;
+    const long n = n5(p);
+    cplx *t = malloc(n * sizeof(cplx));
+    if (!dag) {
+        oracle_schur(p, Ud, ind, (double *)t, 0);
+        apply_K5inv(p, t, out, 0);
+    } else {
+        memcpy(t, ind, n * sizeof(cplx));
+        mask_parity(p, t, 0);
+        apply_K5inv(p, t, out, 1);
+        memcpy(t, out, n * sizeof(cplx));
+        oracle_schur(p, Ud, (const double *)t, outd, 1);
+    }
+    mask_parity(p, out, 0);
+    free(t);
+}
+
 /* b'_e = b_e + 1/2 D_eo B K5^-1 b_o (odd half of the output zero). */
 void oracle_prep_source(const oracle_params *p, const double *Ud, const double *bd, double *outd)
 {

@@ -133,6 +133,7 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
     g.xcd_remap[p] = t.xcd_remap ? 1 : 0;
     g.nt_store[p] = t.nt_store ? 1 : 0;
     g.link_mode[p] = (t.link_mode >= 0 && t.link_mode <= 2) ? t.link_mode : 0;
+    g.rhs_group[p] = t.rhs_group > 0 ? t.rhs_group : 0;
 }
 
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
@@ -280,8 +281,9 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     g.fZ = FastDiv(uint32_t(g.Z));
     // default launch shape (mdwf_autotune refines it per precision): z-blocks
     // of 4 (or 2) planes with t inside; the MDWF_TILE ("bx,by,bz,bt"),
-    // MDWF_XCD_REMAP, MDWF_NT_STORE and MDWF_LINK_MODE variables override it
-    mdwf_launch_tune t0{{g.Xh, g.Y, (g.Z % 4 == 0) ? 4 : 2, 1}, 1, 0, 0, 0.0};
+    // MDWF_XCD_REMAP, MDWF_NT_STORE, MDWF_LINK_MODE and MDWF_RHS_GROUP
+    // variables override it
+    mdwf_launch_tune t0{{g.Xh, g.Y, (g.Z % 4 == 0) ? 4 : 2, 1}, 1, 0, 0, 0, 0.0};
     if (const char* e = std::getenv("MDWF_TILE")) {
         int b[4];
         if (std::sscanf(e, "%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3]) == 4 && tile_fits(g, b))
@@ -290,6 +292,7 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     if (const char* e = std::getenv("MDWF_XCD_REMAP")) t0.xcd_remap = std::atoi(e) != 0;
     if (const char* e = std::getenv("MDWF_NT_STORE")) t0.nt_store = std::atoi(e) != 0;
     if (const char* e = std::getenv("MDWF_LINK_MODE")) t0.link_mode = std::atoi(e);
+    if (const char* e = std::getenv("MDWF_RHS_GROUP")) t0.rhs_group = std::atoi(e);
     for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
     if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
@@ -475,6 +478,7 @@ mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* o
     out->xcd_remap = c->geo.xcd_remap[prec];
     out->nt_store = c->geo.nt_store[prec];
     out->link_mode = c->geo.link_mode[prec];
+    out->rhs_group = c->geo.rhs_group[prec];
     out->us = c->tuned_us[prec];
     return MDWF_OK;
 }
@@ -537,6 +541,7 @@ mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
         mdwf_launch_tune best{};
         for (int k = 0; k < 4; ++k) best.tile[k] = g.trav[p].b[k];
         best.xcd_remap = 1;
+        best.rhs_group = g.rhs_group[p];
         best.us = 1e30;
         // coordinate descent: traversal tile, then link mode, then stores and
         // workgroup numbering

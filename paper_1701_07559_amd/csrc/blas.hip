@@ -274,77 +274,78 @@ void launch_norm2(const Geo& g, Prec p, const void* x, size_t stride, int nrhs, 
 
 // ------------------------------------------------------ CG vector updates
 // x += alpha p ; r -= alpha q ; partial |r|^2 of the stored r
-template <Prec PX, Prec PI>
-__global__ void __launch_bounds__(kBlas) k_cg_xr(const Geo g, void* x, size_t sx, void* r, const void* p,
-                                                 const void* q, size_t si, const int* active, const CGScal* sc,
-                                                 double* partials) {
+// r -= alpha q, with the partials of |r|^2
+template <Prec PI>
+__global__ void __launch_bounds__(kBlas) k_cg_r(const Geo g, void* r, const void* q, size_t si, const int* active,
+                                                const CGScal* sc, double* partials) {
     const int rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const double alpha = sc[rhs].alpha;
     double n2 = 0.0;
     if (j < g.Vh) {
-        cx<double> vx[12], vp[12], vr[12], vq[12];
-        Ld<PX>::load(at_rhs(x, sx, rhs), g.Vh, j, vx);
-        Ld<PI>::load(at_rhs(p, si, rhs), g.Vh, j, vp);
+        cx<double> vr[12], vq[12];
         Ld<PI>::load(at_rhs(r, si, rhs), g.Vh, j, vr);
         Ld<PI>::load(at_rhs(q, si, rhs), g.Vh, j, vq);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            vx[c] = vx[c] + alpha * vp[c];
-            vr[c] = vr[c] - alpha * vq[c];
-        }
-        Ld<PX>::store(at_rhs(x, sx, rhs), g.Vh, j, vx);
+        for (int c = 0; c < 12; ++c) vr[c] = vr[c] - alpha * vq[c];
         Ld<PI>::store(at_rhs(r, si, rhs), g.Vh, j, vr);
         n2 = site_norm2(vr);
     }
     block_partial(n2, partials, rhs, gridDim.x, blockIdx.x);
 }
 
-template <Prec PX>
-static void cg_xr_px(const Geo& g, Prec pi, void* x, size_t sx, void* r, const void* p, const void* q, size_t si,
-                     int nrhs, const int* active, const CGScal* sc, double* partials, hipStream_t st) {
+void launch_cg_r(const Geo& g, Prec pi, void* r, const void* q, size_t si, int nrhs, const int* active,
+                 const CGScal* sc, double* partials, hipStream_t st) {
     const dim3 grid(blas_blocks_per_rhs(g), nrhs), blk(kBlas);
     switch (pi) {
-        case P64: hipLaunchKernelGGL((k_cg_xr<PX, P64>), grid, blk, 0, st, g, x, sx, r, p, q, si, active, sc, partials); break;
-        case P32: hipLaunchKernelGGL((k_cg_xr<PX, P32>), grid, blk, 0, st, g, x, sx, r, p, q, si, active, sc, partials); break;
-        case P16: hipLaunchKernelGGL((k_cg_xr<PX, P16>), grid, blk, 0, st, g, x, sx, r, p, q, si, active, sc, partials); break;
+        case P64: hipLaunchKernelGGL(k_cg_r<P64>, grid, blk, 0, st, g, r, q, si, active, sc, partials); break;
+        case P32: hipLaunchKernelGGL(k_cg_r<P32>, grid, blk, 0, st, g, r, q, si, active, sc, partials); break;
+        case P16: hipLaunchKernelGGL(k_cg_r<P16>, grid, blk, 0, st, g, r, q, si, active, sc, partials); break;
     }
 }
 
-void launch_cg_xr(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* r, const void* p, const void* q,
-                  size_t si, int nrhs, const int* active, const CGScal* sc, double* partials, hipStream_t st) {
-    switch (px) {
-        case P64: cg_xr_px<P64>(g, pi, x, sx, r, p, q, si, nrhs, active, sc, partials, st); break;
-        case P32: cg_xr_px<P32>(g, pi, x, sx, r, p, q, si, nrhs, active, sc, partials, st); break;
-        case P16: cg_xr_px<P16>(g, pi, x, sx, r, p, q, si, nrhs, active, sc, partials, st); break;
-    }
-}
-
-// p = s + beta p
-template <Prec PI>
-__global__ void __launch_bounds__(kBlas) k_cg_p(const Geo g, void* p, const void* s, size_t si, const int* active,
-                                                const CGScal* sc) {
+// x += alpha p, then p = s + beta p: the solution update of this iteration,
+// deferred to the pass that reads p anyway (alpha of this iteration, p before
+// its update), so p is read once per iteration
+template <Prec PX, Prec PI>
+__global__ void __launch_bounds__(kBlas) k_cg_xp(const Geo g, void* x, size_t sx, void* p, const void* s, size_t si,
+                                                 const int* active, const CGScal* sc) {
     const int rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= g.Vh) return;
-    const double beta = sc[rhs].beta;
-    cx<double> vp[12], vs[12];
+    const double alpha = sc[rhs].alpha, beta = sc[rhs].beta;
+    cx<double> vx[12], vp[12], vs[12];
+    Ld<PX>::load(at_rhs(x, sx, rhs), g.Vh, j, vx);
     Ld<PI>::load(at_rhs(p, si, rhs), g.Vh, j, vp);
     Ld<PI>::load(at_rhs(s, si, rhs), g.Vh, j, vs);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) vp[c] = vs[c] + beta * vp[c];
+    for (int c = 0; c < 12; ++c) {
+        vx[c] = vx[c] + alpha * vp[c];
+        vp[c] = vs[c] + beta * vp[c];
+    }
+    Ld<PX>::store(at_rhs(x, sx, rhs), g.Vh, j, vx);
     Ld<PI>::store(at_rhs(p, si, rhs), g.Vh, j, vp);
 }
 
-void launch_cg_p(const Geo& g, Prec pi, void* p, const void* s, size_t si, int nrhs, const int* active,
-                 const CGScal* sc, hipStream_t st) {
+template <Prec PX>
+static void cg_xp_px(const Geo& g, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
+                     const int* active, const CGScal* sc, hipStream_t st) {
     const dim3 grid(blas_blocks_per_rhs(g), nrhs), blk(kBlas);
     switch (pi) {
-        case P64: hipLaunchKernelGGL(k_cg_p<P64>, grid, blk, 0, st, g, p, s, si, active, sc); break;
-        case P32: hipLaunchKernelGGL(k_cg_p<P32>, grid, blk, 0, st, g, p, s, si, active, sc); break;
-        case P16: hipLaunchKernelGGL(k_cg_p<P16>, grid, blk, 0, st, g, p, s, si, active, sc); break;
+        case P64: hipLaunchKernelGGL((k_cg_xp<PX, P64>), grid, blk, 0, st, g, x, sx, p, s, si, active, sc); break;
+        case P32: hipLaunchKernelGGL((k_cg_xp<PX, P32>), grid, blk, 0, st, g, x, sx, p, s, si, active, sc); break;
+        case P16: hipLaunchKernelGGL((k_cg_xp<PX, P16>), grid, blk, 0, st, g, x, sx, p, s, si, active, sc); break;
+    }
+}
+
+void launch_cg_xp(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
+                  const int* active, const CGScal* sc, hipStream_t st) {
+    switch (px) {
+        case P64: cg_xp_px<P64>(g, pi, x, sx, p, s, si, nrhs, active, sc, st); break;
+        case P32: cg_xp_px<P32>(g, pi, x, sx, p, s, si, nrhs, active, sc, st); break;
+        case P16: cg_xp_px<P16>(g, pi, x, sx, p, s, si, nrhs, active, sc, st); break;
     }
 }
 

@@ -217,6 +217,8 @@ template <int K> struct HopTraits {
     // centre term: 0 none, 1 K5, 2 K5^+, 3 identity
     static constexpr int cen = (K == HOP_D5 || K == HOP_SCHUR_B) ? 1
                              : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 2 : (K == HOP_PREP) ? 3 : 0;
+    // kernels B and B^+ also return block partial sums of |out|^2 (CG norms)
+    static constexpr bool norm = (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG);
     static constexpr double coef = (K == HOP_D5 || K == HOP_D5_DAG) ? -0.5
                                  : (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG) ? -0.25
                                  : (K == HOP_PREP) ? 0.5 : 1.0;
@@ -517,8 +519,19 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     const int L5 = g.L5;
     const int spw = 64 / L5;
     const int lb = g.xcd_remap[P] ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
-    const int rhs = lb % a.nrhs;
-    const int tile = lb / a.nrhs;
+    // RHS groups of rg: the blocks of one group sweep the tiles with the
+    // group's RHS fastest (they share each tile's links in L2); groups follow
+    // each other, so a spinor's neighbour reuse spans rg RHS, not all of them
+    int rhs, tile;
+    {
+        const int rg = (g.rhs_group[P] > 0 && g.rhs_group[P] < a.nrhs) ? g.rhs_group[P] : a.nrhs;
+        const int grp = lb / (a.nblk * rg);
+        const int base = grp * rg;
+        const int gs = min(rg, a.nrhs - base);
+        const int off = lb - grp * a.nblk * rg;
+        tile = off / gs;
+        rhs = base + (off - tile * gs);
+    }
     if (a.active && !a.active[rhs]) return;   // uniform over the block
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -696,14 +709,14 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
         }
         if (g.nt_store[P]) Field<P>::template store<true>(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
         else Field<P>::store(at_rhs(a.out, a.stride, rhs), g.Vh, j, res);
-        if (a.partials) {
+        if (TR::norm && a.partials) {
             R acc = R(0);
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc += res[c].re * res[c].re + res[c].im * res[c].im;
             n2 = double(acc);
         }
     }
-    if (a.partials) {
+    if (TR::norm && a.partials) {
         // fixed-order reduction: wave (xor butterfly), then the 4 waves
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) n2 += __shfl_xor(n2, off, 64);

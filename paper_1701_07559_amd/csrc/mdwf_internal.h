@@ -95,6 +95,7 @@ struct Geo {
     int xcd_remap[3];   // renumber workgroups per XCD (1) or keep hardware order (0)
     int nt_store[3];    // write hop outputs with non-temporal stores
     int link_mode[3];   // 0 per-lane links, 1 LDS stage, 2 lane gather
+    int rhs_group[3];   // multi-RHS launches: RHS per group sweeping the tiles together (0 = all)
 };
 
 // Coefficients of one right-hand side (its mass); all fifth-dimension
@@ -213,7 +214,7 @@ template <> struct Field<P16> {
         float n = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) n = fmaxf(n, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
-        float inv = 1.0f / n;
+        float inv = __builtin_amdgcn_rcpf(n);   // scale into [-1, 1] before rounding
         if (n < 1.17549435e-38f) {
             n = 0.f;
             inv = 0.f;
@@ -389,13 +390,13 @@ void launch_axpby(const Geo& g, Prec p, double a, const void* x, double b, const
                   int nrhs, const int* active, double* partials, hipStream_t st);
 void launch_norm2(const Geo& g, Prec p, const void* x, size_t stride, int nrhs, const int* active,
                   double* partials, hipStream_t st);
-// x(px) += alpha[r] * p(pi); r(pi) -= alpha[r] * q(pi); partials <- |r|^2
+// r(pi) -= alpha[r] * q(pi); partials <- |r|^2
 struct CGScal;
-void launch_cg_xr(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* r, const void* p, const void* q,
-                  size_t si, int nrhs, const int* active, const CGScal* sc, double* partials, hipStream_t st);
-// p = s + beta[r] p
-void launch_cg_p(const Geo& g, Prec pi, void* p, const void* s, size_t si, int nrhs, const int* active,
-                 const CGScal* sc, hipStream_t st);
+void launch_cg_r(const Geo& g, Prec pi, void* r, const void* q, size_t si, int nrhs, const int* active,
+                 const CGScal* sc, double* partials, hipStream_t st);
+// x(px) += alpha[r] * p(pi); then p = s + beta[r] p
+void launch_cg_xp(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
+                  const int* active, const CGScal* sc, hipStream_t st);
 // x_hi(P64) += x_lo(px); x_lo = 0
 void launch_flush(const Geo& g, Prec px, void* xhi, size_t shi, void* xlo, size_t slo, int nrhs,
                   const int* active, hipStream_t st);

@@ -6,13 +6,15 @@
 //   CG on the normal equations of S x_e = b'_e in least-squares form:
 //     q = S p, alpha = |s|^2/|q|^2, x += alpha p, r -= alpha q,
 //     s = S^+ r, beta = |s_new|^2/|s|^2, p = s + beta p
+// (x += alpha p runs in the same pass as the update of p, which reads p
+// anyway; alpha and the old p are what they were right after q = S p).
 //   x_o = K5^-1 (b_o + 1/2 D_oe B x_e)
 // The recursion tracks r = b' - S x_e, whose norm equals the full residual
 // |b - D5 x| after reconstruction, so it stops on the quantity that matters;
 // every stop is confirmed by an FP64 true residual of the full system.
 //
 // Mixed precision: the inner vectors r, p, s, q and the hop temporary live in
-// FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32 or FP16;
+// FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32;
 // the FP64 solution x_hi, the prepared source and all reductions stay FP64.
 // When the iterated |r| falls below delta times its value at the last update
 // (or reaches the target) the solver flushes x_lo into x_hi, recomputes
@@ -165,11 +167,11 @@ struct Solver {
         const size_t sxc = mixed ? Hx : H64;
         schur_inner(p, q, act, false, part, prof);
         launch_scalars(SC_ALPHA, part, nbh, n, act, sc, nullptr, st);
-        launch_cg_xr(g, mixed ? px : P64, pi, xcur, sxc, r, p, q, Hi, n, act, sc, part, st);
+        launch_cg_r(g, pi, r, q, Hi, n, act, sc, part, st);
         launch_scalars(SC_RR, part, nbb, n, act, sc, nullptr, st);
         schur_inner(r, s, act, true, part, prof ? prof + 3 : nullptr);
         launch_scalars(SC_BETA, part, nbh, n, act, sc, nullptr, st);
-        launch_cg_p(g, pi, p, s, Hi, n, act, sc, st);
+        launch_cg_xp(g, mixed ? px : P64, pi, xcur, sxc, p, s, Hi, n, act, sc, st);
     }
 };
 
@@ -230,6 +232,26 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     if (!S.hipok(hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo")) return S.err;
     const size_t avail = freeb + held;
     const size_t need_fixed = per_rhs * n + shared + (size_t(64) << 20);
+    int cap = 0;   // explicit sub-batch size (memory / tests)
+    if (const char* e = std::getenv("MDWF_SOLVE_BATCH")) cap = std::max(0, std::atoi(e));
+    if (n > 1 && (need_fixed + S.Hi > avail || (cap > 0 && cap < n))) {
+        // the batch does not fit even with a one-RHS hop temporary: solve it
+        // in consecutive sub-batches that do (same arithmetic per RHS)
+        const size_t base = shared + (size_t(64) << 20);
+        int nb = avail > base + per_rhs + S.Hi ? int((avail - base - S.Hi) / per_rhs) : 1;
+        if (cap > 0) nb = std::min(nb, cap);
+        if (nb < n) {
+            mdwf_status worst = MDWF_OK;
+            for (int k0 = 0; k0 < n; k0 += nb) {
+                const int nk = std::min(nb, n - k0);
+                const mdwf_status r = mdwf_solve_impl(c, nk, b_in + k0, x_out + k0, host_io, mq ? mq + k0 : nullptr,
+                                                      &o, info ? info + k0 : nullptr, st);
+                if (r != MDWF_OK && r != MDWF_ERR_NOCONV && r != MDWF_ERR_NUMERIC) return r;
+                if (r != MDWF_OK && worst == MDWF_OK) worst = r;
+            }
+            return worst;
+        }
+    }
     S.chunk = n;
     if (need_fixed + size_t(n) * S.Hi > avail) {
         const size_t room = avail > need_fixed ? avail - need_fixed : 0;
@@ -512,7 +534,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     // model counts per RHS
     const double bsI = spinor_site_bytes(S.pi), bsX = spinor_site_bytes(S.px), bs64 = spinor_site_bytes(P64);
     const double blI = link_site_bytes(S.pi, g.L5), bl64 = link_site_bytes(P64, g.L5);
-    const double it_bytes = g.Vh * (17 * bsI + 2 * bsX + 4 * blI);
+    // A, B, A^+, B^+ (10 inner fields), r -= alpha q (3), x += alpha p with
+    // p = s + beta p (3 inner + x_lo read and written)
+    const double it_bytes = g.Vh * (16 * bsI + 2 * bsX + 4 * blI);
     const double it_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 5 * 48.0);
     const double up_bytes = g.Vh * (5 * bs64 + 2 * bl64 + 3 * bs64 + bs64 + bsI + 5 * bsI + 2 * blI + 2 * bs64 + 2 * bsX);
     const double up_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 3 * 48.0);

@@ -64,7 +64,7 @@ class mdwf_solve_info(C.Structure):
 
 
 class mdwf_launch_tune(C.Structure):
-    _fields_ = [("tile", C.c_int * 4), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int),
+    _fields_ = [("tile", C.c_int * 4), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int), ("rhs_group", C.c_int),
                 ("us", C.c_double)]
 
     def as_dict(self):

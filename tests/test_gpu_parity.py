@@ -402,7 +402,8 @@ def test_multi_rhs_multi_mass_equals_single(M):
 
 
 def test_multi_rhs_chunked_schur_is_bitwise_identical(M, monkeypatch):
-    """Splitting the RHS into chunks that share the hop temporary changes no bit."""
+    """Splitting the RHS into chunks that share the hop temporary, or the
+    batch into sub-batches solved in turn, changes no bit."""
     dims, L5 = (4, 4, 4, 8), 8
     act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
     U = I.random_links(dims, 0.3, 53)
@@ -411,9 +412,12 @@ def test_multi_rhs_chunked_schur_is_bitwise_identical(M, monkeypatch):
     ctx = make_ctx(M, act, U)
     try:
         res = []
-        for chunk in (None, "2", "1"):
+        for chunk, batch in ((None, None), ("2", None), ("1", None), (None, "2")):
+            monkeypatch.delenv("MDWF_SOLVE_CHUNK", raising=False)
             if chunk:
                 monkeypatch.setenv("MDWF_SOLVE_CHUNK", chunk)
+            if batch:   # sub-batches of 2, 2, 1 RHS solved in turn
+                monkeypatch.setenv("MDWF_SOLVE_BATCH", batch)
             xs = [np.zeros_like(b) for b in bs]
             st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=2))
             assert st == M.MDWF_OK
@@ -426,6 +430,30 @@ def test_multi_rhs_chunked_schur_is_bitwise_identical(M, monkeypatch):
             assert oracle.true_residual(act.with_mass(masses[k]), U, b, res[0][0][k]) <= 1e-10
     finally:
         M.mdwf_destroy(ctx)
+
+
+def test_multi_rhs_group_order_is_bitwise_identical(M, monkeypatch):
+    """The order in which RHS groups sweep the tiles (rhs_group) changes no bit."""
+    dims, L5 = (4, 4, 4, 8), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 54)
+    bs = [I.gaussian_source(dims, L5, 70 + k) for k in range(5)]
+    masses = [0.05, 0.03, 0.08, 0.05, 0.2]
+    res = []
+    for rg in ("0", "1", "2", "3"):
+        monkeypatch.setenv("MDWF_RHS_GROUP", rg)
+        ctx = make_ctx(M, act, U)
+        try:
+            assert M.mdwf_get_tune(ctx, 2)["rhs_group"] == int(rg)
+            xs = [np.zeros_like(b) for b in bs]
+            st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=2))
+            assert st == M.MDWF_OK
+            res.append((xs, [i["iters"] for i in info]))
+        finally:
+            M.mdwf_destroy(ctx)
+    for xs, its in res[1:]:
+        assert its == res[0][1]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, res[0][0]))
 
 
 def test_solve_dev_with_torch_buffers(M, cfg1):
