@@ -16,12 +16,13 @@ FP64 true-residual check of every column to 1e-10.
 
 value = algorithmic HBM bytes of the step (model of every kernel it ran) /
 step time, in GB/s.  Inputs are resident in HBM before the timed region.
-
---workload batched: the a12m220 volume, 32^3 x 64 at L5 = 10, 36 RHS (the
-12 columns at m_q = 0.0074, 0.02, 0.04) as three multi-mass launches of 12.
 Beside it: the solve time of plain FP64 CG on the same columns, the dslash
 kernels' achieved bandwidth against the 8 TB/s HBM peak (timed with HIP events
 on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
+
+--workload batched: the a12m220 volume, 32^3 x 64 at L5 = 10, 36 RHS (the
+12 columns at m_q = 0.0074, 0.02, 0.04) as three multi-mass launches of 12.
+--summarize: write the rocprofv3 summary of the dominant kernels (no GPU).
 """
 from __future__ import annotations
 
@@ -193,7 +194,7 @@ def summarize(args):
     cmds = [c for c in args.summary_cmds.split("||") if c.strip()]
     lines.append("# rocprofv3 summary: batched FP16 Schur operator in bench.py (24^3x64, L5=8, 12 RHS)")
     lines.append("")
-    lines.append("Commands (repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):")
+    lines.append("Commands (from the repository root on one MI355X, with `export TMPDIR=/tmp`):")
     lines.append("")
     for c in cmds:
         lines.append("    " + c.strip())
@@ -227,6 +228,17 @@ def summarize(args):
         if v:
             lines.append("| %s (`k_hop<F16, %d, *>`) | %d | %.1f |" % (names[kind], kind, len(v), sum(v) / len(v)))
     lines.append("")
+    if args.summary_bench:
+        with open(args.summary_bench) as f:
+            bl = [json.loads(x) for x in f if x.startswith("{")]
+        la = (bl[-1].get("roofline") or {}).get("launches") if bl else None
+        if la:
+            tr = {k: sum(sel.get(kind, [0])) / max(1, len(sel.get(kind, []))) for k, kind in (("A", 3), ("B", 4))}
+            lines.append("Agreement: bench.py in the traced run timed the same launches with HIP events on the "
+                         "solve stream (`mdwf_solve_info.hop_us`): A %.1f us, B %.1f us, against %.1f and %.1f us "
+                         "in the trace (sum %+.1f %%)." % (la["A"]["us"], la["B"]["us"], tr["A"], tr["B"],
+                         100 * ((la["A"]["us"] + la["B"]["us"]) / (tr["A"] + tr["B"]) - 1)))
+            lines.append("")
     rec = None
     if args.summarize[1] != "-" and args.summarize[2] != "-":
         def counters(path, cname):
@@ -299,6 +311,7 @@ def main():
                          "FETCH_DB / WRITE_DB may be '-'")
     ap.add_argument("--summary-out", default=None)
     ap.add_argument("--summary-cmds", default="", help="commands that produced the databases ('||'-separated)")
+    ap.add_argument("--summary-bench", default=None, help="the JSON line bench.py printed in the traced run")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
