@@ -231,6 +231,51 @@ mdwf_status mdwf_get_tune(const mdwf_ctx *ctx, mdwf_prec prec, mdwf_launch_tune 
 /* Model flop and byte counts for one application of an operator (per call). */
 mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, double *flops, double *bytes);
 
+/* ------------------------------------------------------------ serving
+ * A request server for many solves of D5 x = b (the paper computes
+ * propagators for several ensembles, masses and sources, Sec. III): gauge
+ * fields are uploaded once and stay resident; requests (field, action incl.
+ * L5, per-RHS masses, 1..n RHS, solver options) may be submitted at any time
+ * from any thread.  Each is admitted in arrival order as soon as its device
+ * footprint (the solver's memory plan) fits in the budget next to the
+ * requests already running, and runs on one of max_active worker threads
+ * with its own HIP stream, so the work of concurrent requests overlaps on the
+ * device.  A request's result is bitwise the same as the same mdwf_solve run
+ * alone.  b and x are host canonical fields owned by the caller; they must
+ * stay valid until mdwf_server_wait returns for the request. */
+typedef struct mdwf_server mdwf_server;
+
+/* mem_budget: device bytes the requests may occupy together (0 = 90 % of the
+ * free memory now); resident links are taken out of it.  ERR_ARG if
+ * max_active < 1, ERR_HIP on a bad device. */
+mdwf_status mdwf_server_create(int hip_device, size_t mem_budget, int max_active, mdwf_server **out);
+
+/* Finish every submitted request, stop the workers and free everything. */
+void mdwf_server_destroy(mdwf_server *srv);
+
+/* Description of the last failure reported by the server. */
+const char *mdwf_server_last_error(const mdwf_server *srv);
+
+/* Upload a gauge field (host canonical, as mdwf_load_gauge); *field_id
+ * names it in requests. */
+mdwf_status mdwf_server_add_field(mdwf_server *srv, const mdwf_geometry *geom, const double *U, int *field_id);
+
+/* Queue a solve of nrhs RHS on field_id with action act (mq: per-RHS masses
+ * or NULL for act->mq; opts NULL = defaults; use_graph and profile_iters are
+ * ignored).  Returns at once with *req_id.  ERR_ARG on bad arguments, ERR_OOM
+ * if the request can never fit the budget. */
+mdwf_status mdwf_server_submit(mdwf_server *srv, int field_id, const mdwf_action *act, int nrhs,
+                               const double *const *b, double *const *x, const double *mq,
+                               const mdwf_solver_opts *opts, int *req_id);
+
+/* Block until request req_id has finished; fill info[nrhs] (may be NULL) and
+ * times[3] (may be NULL): seconds queued, seconds running, total latency.
+ * Returns the solve's status; the request is forgotten afterwards. */
+mdwf_status mdwf_server_wait(mdwf_server *srv, int req_id, mdwf_solve_info *info, double *times);
+
+/* Budget, the largest footprint reserved at once so far, and requests queued. */
+mdwf_status mdwf_server_stats(mdwf_server *srv, size_t *budget, size_t *peak_reserved, int *queued);
+
 #ifdef __cplusplus
 }
 #endif

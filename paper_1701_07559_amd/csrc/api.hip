@@ -136,6 +136,26 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
     g.rhs_group[p] = t.rhs_group > 0 ? t.rhs_group : 0;
 }
 
+void release_solver_buffers(mdwf_ctx* c) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    c->bufs.clear();
+}
+
+void share_gauge(mdwf_ctx* dst, const mdwf_ctx* src) {
+    dst->gs = src->gs;
+    dst->have_gauge = src->have_gauge;
+    dst->gauge_mem = nullptr;   // borrowed: src frees it
+}
+
+size_t gauge_bytes(const mdwf_ctx* c) {
+    size_t tot = 0;
+    for (int p = 0; p < 3; ++p) tot += 8 * link_segment_bytes(Prec(p), c->geo.Vh4);
+    return tot;
+}
+
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
                          const RhsCoef* d_coef, const int* d_active, hipStream_t st) {
     const Geo& g = c->geo;

@@ -69,3 +69,15 @@ double link_site_bytes(Prec p, int L5);
 // host_io: b and x are host pointers, streamed through one device staging field
 mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, bool host_io,
                             const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st);
+
+namespace mdwf {
+// Device bytes a solve of nrhs RHS allocates (solver vectors, shared
+// scratch, hop temporary for all RHS at once), as its memory plan counts them.
+size_t solve_footprint(const Geo& g, Prec inner, int nrhs, bool host_io);
+// Free the solver's device buffers held by the context (grow-only otherwise).
+void release_solver_buffers(mdwf_ctx* c);
+// Make dst use src's resident links (same geometry; src must outlive dst).
+void share_gauge(mdwf_ctx* dst, const mdwf_ctx* src);
+// Device bytes of the resident links of a context.
+size_t gauge_bytes(const mdwf_ctx* c);
+}  // namespace mdwf

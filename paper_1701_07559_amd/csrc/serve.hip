@@ -1,0 +1,256 @@
+// Serving loop for the Moebius domain-wall solve: requests to solve D5 x = b
+// (any resident gauge field, any L5 / M5 / b5 / c5, per-RHS masses, 1..n
+// RHS) arrive at any time.  Each is admitted, in arrival order, as soon as its
+// device footprint fits next to the requests already running, and runs on
+// one of several worker threads, each with its own HIP stream, so the
+// kernels of concurrent requests overlap on the device.  Gauge fields stay
+// resident for the server's lifetime and are shared by every worker; solver
+// buffers are released when a request finishes, returning its footprint.
+//
+// A request's arithmetic does not depend on what else runs (no reduction
+// crosses requests, chunking and sub-batching are bitwise neutral), so its
+// result equals the same solve run alone.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <utility>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace mdwf;
+
+namespace {
+
+double wall() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    int field = 0;
+    mdwf_action act{};
+    std::vector<const double*> b;
+    std::vector<double*> x;
+    std::vector<double> mq;
+    mdwf_solver_opts opts{};
+    size_t footprint = 0;
+    double t_submit = 0, t_start = 0, t_end = 0;
+    bool done = false;
+    mdwf_status status = MDWF_OK;
+    std::string err;
+    std::vector<mdwf_solve_info> info;
+};
+
+struct GaugeField {
+    mdwf_geometry geom{};
+    mdwf_ctx* master = nullptr;   // owns the resident links
+};
+
+}  // namespace
+
+struct mdwf_server {
+    int device = 0;
+    size_t budget = 0;          // device bytes requests may reserve together
+    size_t reserved = 0, peak = 0;
+    std::mutex m;
+    std::condition_variable cv_work, cv_done;
+    std::deque<int> pending;
+    std::map<int, Request> reqs;
+    std::vector<GaugeField> fields;
+    std::vector<std::thread> workers;
+    bool stop = false;
+    int next_id = 1;
+    std::string err;
+};
+
+namespace {
+
+mdwf_status sfail(mdwf_server* s, mdwf_status st, const std::string& msg) {
+    if (s) s->err = msg;
+    return st;
+}
+
+// footprint of a request (solver buffers with host I/O; links are resident)
+size_t footprint(const GaugeField& f, const mdwf_action& a, int nrhs, mdwf_prec inner) {
+    Geo g{};
+    g.X = f.geom.X; g.Y = f.geom.Y; g.Z = f.geom.Z; g.T = f.geom.T;
+    g.Vh4 = g.X * g.Y * g.Z * g.T / 2;
+    g.L5 = a.L5;
+    g.Vh = g.Vh4 * a.L5;
+    return solve_footprint(g, Prec(inner), nrhs, true);
+}
+
+void worker_loop(mdwf_server* s) {
+    (void)hipSetDevice(s->device);
+    std::map<std::pair<int, int>, mdwf_ctx*> ctxs;   // (field, L5) -> context on this worker's stream
+    for (;;) {
+        int id = 0;
+        Request* r = nullptr;
+        GaugeField f;
+        {
+            std::unique_lock<std::mutex> lk(s->m);
+            s->cv_work.wait(lk, [&] {
+                if (s->pending.empty()) return s->stop;
+                const Request& f = s->reqs[s->pending.front()];
+                return s->reserved + f.footprint <= s->budget;
+            });
+            if (s->pending.empty()) break;   // stop requested and nothing left
+            id = s->pending.front();
+            s->pending.pop_front();
+            r = &s->reqs[id];
+            s->reserved += r->footprint;
+            s->peak = std::max(s->peak, s->reserved);
+            r->t_start = wall();
+            f = s->fields[r->field];   // copied: add_field may grow the list meanwhile
+        }
+        // the request record (a map node) is not touched by other threads until done
+        mdwf_ctx*& c = ctxs[{r->field, r->act.L5}];
+        mdwf_status st = MDWF_OK;
+        if (!c) {
+            st = mdwf_create(&f.geom, s->device, nullptr, &c);
+            if (st == MDWF_OK) share_gauge(c, f.master);
+        }
+        if (st == MDWF_OK) st = mdwf_set_action(c, &r->act);
+        const int n = int(r->b.size());
+        if (st == MDWF_OK)
+            st = mdwf_solve(c, n, r->b.data(), r->x.data(), r->mq.data(), &r->opts, r->info.data());
+        std::string msg = st == MDWF_OK ? std::string() : std::string(mdwf_last_error(c));
+        if (c) release_solver_buffers(c);
+        {
+            std::lock_guard<std::mutex> lk(s->m);
+            r->status = st;
+            r->err = msg;
+            r->t_end = wall();
+            r->done = true;
+            s->reserved -= r->footprint;
+        }
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+    for (auto& kv : ctxs) mdwf_destroy(kv.second);
+}
+
+}  // namespace
+
+extern "C" {
+
+mdwf_status mdwf_server_create(int hip_device, size_t mem_budget, int max_active, mdwf_server** out) {
+    if (!out || max_active < 1) return MDWF_ERR_ARG;
+    *out = nullptr;
+    if (hipSetDevice(hip_device) != hipSuccess) return MDWF_ERR_HIP;
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return MDWF_ERR_HIP;
+    mdwf_server* s = new (std::nothrow) mdwf_server;
+    if (!s) return MDWF_ERR_OOM;
+    s->device = hip_device;
+    const size_t cap = freeb / 10 * 9;
+    s->budget = (mem_budget == 0 || mem_budget > cap) ? cap : mem_budget;
+    for (int w = 0; w < max_active; ++w) s->workers.emplace_back(worker_loop, s);
+    *out = s;
+    return MDWF_OK;
+}
+
+void mdwf_server_destroy(mdwf_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    for (auto& f : s->fields) mdwf_destroy(f.master);
+    delete s;
+}
+
+const char* mdwf_server_last_error(const mdwf_server* s) { return s ? s->err.c_str() : ""; }
+
+mdwf_status mdwf_server_add_field(mdwf_server* s, const mdwf_geometry* geom, const double* U, int* field_id) {
+    if (!s || !geom || !U || !field_id) return sfail(s, MDWF_ERR_ARG, "null argument");
+    mdwf_ctx* c = nullptr;
+    mdwf_status st = mdwf_create(geom, s->device, nullptr, &c);
+    if (st) return sfail(s, st, mdwf_last_error(nullptr));
+    st = mdwf_load_gauge(c, U);
+    if (st) {
+        const std::string msg = mdwf_last_error(c);
+        mdwf_destroy(c);
+        return sfail(s, st, msg);
+    }
+    release_solver_buffers(c);   // drop the upload staging
+    std::lock_guard<std::mutex> lk(s->m);
+    const size_t gb = gauge_bytes(c);
+    s->budget = s->budget > gb ? s->budget - gb : 0;   // the links stay resident
+    s->fields.push_back({*geom, c});
+    *field_id = int(s->fields.size()) - 1;
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* act, int nrhs,
+                               const double* const* b, double* const* x, const double* mq,
+                               const mdwf_solver_opts* opts, int* req_id) {
+    if (!s || !act || !b || !x || !req_id || nrhs < 1) return sfail(s, MDWF_ERR_ARG, "bad request arguments");
+    Request r;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        if (field_id < 0 || field_id >= int(s->fields.size())) return sfail(s, MDWF_ERR_ARG, "unknown field");
+        r.field = field_id;
+    }
+    if (act->L5 < 1 || act->L5 > kMaxL5) return sfail(s, MDWF_ERR_ARG, "need 1 <= L5 <= 32");
+    r.act = *act;
+    r.b.assign(b, b + nrhs);
+    r.x.assign(x, x + nrhs);
+    for (int k = 0; k < nrhs; ++k)
+        if (!r.b[k] || !r.x[k]) return sfail(s, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+    r.mq.assign(nrhs, act->mq);
+    if (mq) r.mq.assign(mq, mq + nrhs);
+    mdwf_default_opts(&r.opts);
+    if (opts) r.opts = *opts;
+    r.opts.use_graph = 0;       // each solve runs eagerly on its worker's stream
+    r.opts.profile_iters = 0;
+    r.info.assign(nrhs, mdwf_solve_info{});
+    std::lock_guard<std::mutex> lk(s->m);
+    r.footprint = footprint(s->fields[field_id], r.act, nrhs, r.opts.inner);
+    if (r.footprint > s->budget)
+        return sfail(s, MDWF_ERR_OOM, "request needs " + std::to_string(r.footprint) + " device bytes, the budget is " +
+                                          std::to_string(s->budget));
+    r.t_submit = wall();
+    const int id = s->next_id++;
+    s->reqs.emplace(id, std::move(r));
+    s->pending.push_back(id);
+    *req_id = id;
+    s->cv_work.notify_all();
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_server_wait(mdwf_server* s, int req_id, mdwf_solve_info* info, double* times) {
+    if (!s) return MDWF_ERR_ARG;
+    std::unique_lock<std::mutex> lk(s->m);
+    auto it = s->reqs.find(req_id);
+    if (it == s->reqs.end()) return sfail(s, MDWF_ERR_ARG, "unknown request");
+    s->cv_done.wait(lk, [&] { return it->second.done; });
+    Request& r = it->second;
+    if (info) std::copy(r.info.begin(), r.info.end(), info);
+    if (times) {
+        times[0] = r.t_start - r.t_submit;   // queued
+        times[1] = r.t_end - r.t_start;      // on a worker
+        times[2] = r.t_end - r.t_submit;     // latency
+    }
+    const mdwf_status st = r.status;
+    if (st != MDWF_OK) s->err = r.err;
+    s->reqs.erase(it);
+    return st;
+}
+
+mdwf_status mdwf_server_stats(mdwf_server* s, size_t* budget, size_t* peak_reserved, int* queued) {
+    if (!s) return MDWF_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    if (budget) *budget = s->budget;
+    if (peak_reserved) *peak_reserved = s->peak;
+    if (queued) *queued = int(s->pending.size());
+    return MDWF_OK;
+}
+
+}  // extern "C"

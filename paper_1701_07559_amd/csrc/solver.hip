@@ -181,6 +181,18 @@ double now() {
 
 }  // namespace
 
+namespace mdwf {
+size_t solve_footprint(const Geo& g, Prec inner, int n, bool host_io) {
+    const bool mixed = inner != P64;
+    const size_t H64 = half_field_bytes(P64, g.Vh), Hi = half_field_bytes(inner, g.Vh);
+    const size_t Hx = half_field_bytes(P32, g.Vh);
+    const size_t per_rhs = 2 * H64 + (mixed ? 4 * Hi + Hx : 4 * H64);
+    const size_t shared = 6 * H64 + (host_io ? size_t(2) * g.Vh * 24 * sizeof(double) : 0);
+    const size_t tmp = size_t(n) * (mixed ? Hi : H64);   // hop temporary for every RHS at once
+    return per_rhs * n + shared + tmp + (size_t(64) << 20);
+}
+}  // namespace mdwf
+
 mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, double* const* x_out, bool host_io,
                             const double* mq, const mdwf_solver_opts* o_in, mdwf_solve_info* info, hipStream_t st) {
     const double t_start = now();

@@ -121,6 +121,14 @@ def _load():
         "mdwf_op_model": ([vp, ip, ip, C.POINTER(dp), C.POINTER(dp)], ip),
         "mdwf_autotune": ([vp, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_get_tune": ([vp, ip, C.POINTER(mdwf_launch_tune)], ip),
+        "mdwf_server_create": ([ip, C.c_size_t, ip, C.POINTER(vp)], ip),
+        "mdwf_server_destroy": ([vp], None),
+        "mdwf_server_last_error": ([vp], C.c_char_p),
+        "mdwf_server_add_field": ([vp, C.POINTER(mdwf_geometry), vp, C.POINTER(ip)], ip),
+        "mdwf_server_submit": ([vp, ip, C.POINTER(mdwf_action), ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp),
+                                C.POINTER(mdwf_solver_opts), C.POINTER(ip)], ip),
+        "mdwf_server_wait": ([vp, ip, C.POINTER(mdwf_solve_info), C.POINTER(dp)], ip),
+        "mdwf_server_stats": ([vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(ip)], ip),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -264,9 +272,78 @@ def mdwf_get_tune(ctx, prec):
     return t.as_dict()
 
 
+class Server:
+    """Request server (mdwf_server_*): resident gauge fields, solves admitted
+    by device footprint and run concurrently on worker streams.  Host arrays
+    of a request are kept alive here until its wait returns."""
+
+    def __init__(self, hip_device=0, mem_budget=0, max_active=4):
+        h = C.c_void_p()
+        st = lib.mdwf_server_create(int(hip_device), int(mem_budget), int(max_active), C.byref(h))
+        if st != MDWF_OK:
+            raise MdwfError(st, "mdwf_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def _err(self):
+        s = lib.mdwf_server_last_error(self.h)
+        return s.decode() if s else ""
+
+    def add_field(self, dims, U, antiperiodic_t=True):
+        g = mdwf_geometry(*[int(d) for d in dims], int(bool(antiperiodic_t)))
+        U = _c128(U)
+        fid = C.c_int()
+        st = lib.mdwf_server_add_field(self.h, C.byref(g), U.ctypes.data, C.byref(fid))
+        if st != MDWF_OK:
+            raise MdwfError(st, self._err())
+        return fid.value
+
+    def submit(self, field, M5, b5, c5, mq, L5, b_list, x_list, masses=None, opts=None):
+        """Queue a solve; b_list / x_list are host complex128 canonical fields."""
+        n = len(b_list)
+        bs = [_c128(b) for b in b_list]
+        for x in x_list:
+            if not (x.flags.c_contiguous and x.dtype == np.complex128):
+                raise ValueError("x must be C-contiguous complex128 arrays")
+        a = mdwf_action(float(M5), float(b5), float(c5), float(mq), int(L5))
+        bp = (C.c_void_p * n)(*[b.ctypes.data for b in bs])
+        xp = (C.c_void_p * n)(*[x.ctypes.data for x in x_list])
+        m = (C.c_double * n)(*masses) if masses is not None else None
+        o = _opts(opts)
+        rid = C.c_int()
+        st = lib.mdwf_server_submit(self.h, int(field), C.byref(a), n, bp, xp, m, C.byref(o), C.byref(rid))
+        if st != MDWF_OK:
+            raise MdwfError(st, self._err())
+        self._keep[rid.value] = (bs, list(x_list), bp, xp, m, n)
+        return rid.value
+
+    def wait(self, rid):
+        """(status, [info dicts], (queued s, running s, latency s))."""
+        n = self._keep[rid][5]
+        infos = (mdwf_solve_info * n)()
+        t = (C.c_double * 3)()
+        st = lib.mdwf_server_wait(self.h, int(rid), infos, t)
+        del self._keep[rid]
+        if st not in (MDWF_OK, MDWF_ERR_NOCONV, MDWF_ERR_NUMERIC):
+            raise MdwfError(st, self._err())
+        return st, [i.as_dict() for i in infos], tuple(t)
+
+    def stats(self):
+        b, p, q = C.c_size_t(), C.c_size_t(), C.c_int()
+        lib.mdwf_server_stats(self.h, C.byref(b), C.byref(p), C.byref(q))
+        return dict(budget=b.value, peak_reserved=p.value, queued=q.value)
+
+    def close(self):
+        if self.h:
+            lib.mdwf_server_destroy(self.h)
+            self.h = None
+
+
 def exported_symbols():
     """Names of the C entry points declared in include/mdwf.h."""
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
             "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
-            "mdwf_autotune", "mdwf_get_tune"]
+            "mdwf_autotune", "mdwf_get_tune", "mdwf_server_create", "mdwf_server_destroy",
+            "mdwf_server_last_error", "mdwf_server_add_field", "mdwf_server_submit", "mdwf_server_wait",
+            "mdwf_server_stats"]

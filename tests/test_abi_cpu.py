@@ -62,3 +62,17 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_server_null_and_argument_errors_without_device():
+    from paper_1701_07559_amd import mdwf
+    out = C.c_void_p()
+    assert mdwf.lib.mdwf_server_create(0, 0, 0, C.byref(out)) == mdwf.MDWF_ERR_ARG   # max_active < 1
+    assert mdwf.lib.mdwf_server_create(0, 0, 2, None) == mdwf.MDWF_ERR_ARG
+    a = mdwf.mdwf_action(1.3, 1.5, 0.5, 0.05, 8)
+    rid = C.c_int()
+    assert mdwf.lib.mdwf_server_submit(None, 0, C.byref(a), 1, None, None, None, None,
+                                       C.byref(rid)) == mdwf.MDWF_ERR_ARG
+    assert mdwf.lib.mdwf_server_wait(None, 1, None, None) == mdwf.MDWF_ERR_ARG
+    assert mdwf.lib.mdwf_server_add_field(None, None, None, None) == mdwf.MDWF_ERR_ARG
+    mdwf.lib.mdwf_server_destroy(None)   # ignored

@@ -1,0 +1,106 @@
+"""Serving loop (mdwf_server_*): requests of different lattices, L5, masses,
+RHS counts and inner precisions, submitted together, admitted by device
+footprint and run concurrently on worker streams.  Each result must be the
+same as the same solve run alone (bitwise: no reduction crosses requests),
+every true residual at most 1e-10, and the reserved footprint never above the
+budget."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_07559_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = [((4, 4, 4, 8), 0.3, 61), ((6, 4, 2, 4), 0.3, 62)]
+# (field, L5, masses, inner, seeds of the Gaussian RHS)
+REQUESTS = [
+    (0, 8, [0.05, 0.1], 2, (70, 71)),
+    (1, 4, [0.05], 1, (72,)),
+    (0, 4, [0.02], 0, (73,)),
+    (1, 8, [0.05, 0.05, 0.2], 2, (74, 75, 76)),
+    (0, 8, [0.05], 1, (77,)),
+    (1, 4, [0.1, 0.03], 2, (78, 79)),
+]
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1701_07559_amd import mdwf
+    try:
+        ctx = mdwf.mdwf_create((2, 2, 2, 2))
+    except mdwf.MdwfError as e:
+        pytest.skip("no HIP device: %s" % e)
+    mdwf.mdwf_destroy(ctx)
+    return mdwf
+
+
+def alone(M, dims, U, L5, masses, inner, bs):
+    ctx = M.mdwf_create(dims)
+    try:
+        M.mdwf_set_action(ctx, 1.3, 1.5, 0.5, masses[0], L5)
+        M.mdwf_load_gauge(ctx, U)
+        xs = [np.zeros_like(b) for b in bs]
+        st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=inner))
+        assert st == M.MDWF_OK
+        return xs, [i["iters"] for i in info]
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_requests_in_the_mix_equal_alone(M):
+    links = [I.random_links(d, eps, seed) for d, eps, seed in FIELDS]
+    budget = 150 << 20   # room for two of these requests at a time: the rest queue
+    srv = M.Server(mem_budget=budget, max_active=3)
+    try:
+        fids = [srv.add_field(d, U) for (d, _, _), U in zip(FIELDS, links)]
+        jobs = []
+        for f, L5, masses, inner, seeds in REQUESTS:
+            dims = FIELDS[f][0]
+            bs = [I.gaussian_source(dims, L5, s) for s in seeds]
+            xs = [np.zeros_like(b) for b in bs]
+            rid = srv.submit(fids[f], 1.3, 1.5, 0.5, masses[0], L5, bs, xs, masses=masses,
+                             opts=dict(inner=inner))
+            jobs.append((rid, f, L5, masses, inner, bs, xs))
+        lat = []
+        for rid, f, L5, masses, inner, bs, xs in jobs:
+            st, info, times = srv.wait(rid)
+            assert st == M.MDWF_OK, info
+            assert all(i["true_resid"] <= 1e-10 for i in info)
+            assert times[2] >= times[1] > 0.0 and times[0] >= 0.0
+            lat.append(times[2])
+            dims = FIELDS[f][0]
+            ref, its = alone(M, dims, links[f], L5, masses, inner, bs)
+            assert [i["iters"] for i in info] == its
+            for a, b in zip(xs, ref):
+                assert np.array_equal(a, b), "request on field %d, L5 %d differs in the mix" % (f, L5)
+        # the oracle confirms one solution of each field
+        for rid, f, L5, masses, inner, bs, xs in jobs[:2]:
+            act = oracle.Action(FIELDS[f][0], L5, M5=1.3, b5=1.5, c5=0.5, mq=masses[0])
+            assert oracle.true_residual(act, links[f], bs[0], xs[0]) <= 1e-10
+        stats = srv.stats()
+        assert 0 < stats["peak_reserved"] <= stats["budget"] <= budget
+        assert stats["queued"] == 0
+    finally:
+        srv.close()
+
+
+def test_server_rejects_bad_requests(M):
+    srv = M.Server(mem_budget=80 << 20, max_active=1)
+    try:
+        dims = (4, 4, 4, 8)
+        fid = srv.add_field(dims, I.random_links(dims, 0.3, 63))
+        b = I.gaussian_source(dims, 8, 64)
+        x = np.zeros_like(b)
+        with pytest.raises(M.MdwfError) as e:   # unknown field
+            srv.submit(fid + 5, 1.3, 1.5, 0.5, 0.05, 8, [b], [x])
+        assert e.value.status == M.MDWF_ERR_ARG
+        many = [b] * 40                          # can never fit the budget
+        with pytest.raises(M.MdwfError) as e:
+            srv.submit(fid, 1.3, 1.5, 0.5, 0.05, 8, many, [np.zeros_like(b) for _ in many])
+        assert e.value.status == M.MDWF_ERR_OOM
+        rid = srv.submit(fid, 1.3, 1.5, 0.5, 0.05, 8, [b], [x], opts=dict(inner=2))
+        st, info, _ = srv.wait(rid)
+        assert st == M.MDWF_OK and info[0]["true_resid"] <= 1e-10
+    finally:
+        srv.close()
