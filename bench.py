@@ -52,7 +52,20 @@ WORKLOADS = {
     "mixed": dict(DIMS=(24, 24, 24, 64), L5=8, MASSES=[0.0102], GAUGE_SEED=103, SITE_SEED=403, GROUPS=1),
     "batched": dict(DIMS=(32, 32, 32, 64), L5=10, MASSES=[0.0074, 0.02, 0.04], GAUGE_SEED=104, SITE_SEED=404,
                     GROUPS=3),
+    "serving": None,   # its own driver, serve_main
 }
+
+# Serving: four resident gauge fields shaped like the paper's ensembles
+# (Table I): (lattice, L5, gauge seed, point-source site seed).  Requests draw
+# a field, 1..n RHS (spin-colour columns of that field's point source) and a
+# mass per RHS.  A 48^3 x 64 x 10 FP64 field is 13.6 GB of host memory, for the
+# source and for the solution of every RHS, so requests on it carry 1..2 RHS.
+SERVE_FIELDS = [((16, 16, 16, 48), 12, 201, 401), ((24, 24, 24, 64), 8, 202, 402),
+                ((32, 32, 32, 64), 10, 203, 403), ((48, 48, 48, 64), 10, 204, 404)]
+SERVE_MASSES = (0.0048, 0.0102, 0.02)
+SERVE_WEIGHTS = (0.35, 0.3, 0.2, 0.15)
+SERVE_MAX_RHS = (12, 12, 12, 2)
+ARRIVAL_SEED = 501
 
 
 def log(*a):
@@ -285,6 +298,244 @@ def summarize(args):
     print(text)
 
 
+def serve_requests(n, rng):
+    """n requests of the serving mix: (field index, RHS count, mass per RHS)."""
+    out = []
+    for _ in range(n):
+        f = int(rng.choice(len(SERVE_FIELDS), p=SERVE_WEIGHTS))
+        k = int(rng.integers(1, SERVE_MAX_RHS[f] + 1))
+        out.append((f, k, [float(SERVE_MASSES[j]) for j in rng.integers(0, len(SERVE_MASSES), size=k)]))
+    return out
+
+
+def _digest(a):
+    try:
+        import xxhash
+        return xxhash.xxh3_64_hexdigest(memoryview(a).cast("B"))
+    except ImportError:
+        import hashlib
+        return hashlib.blake2b(memoryview(a).cast("B"), digest_size=16).hexdigest()
+
+
+def run_phase(M, srv, fids, cols, reqs, arrivals, opts, host_cap, serial=False, digest=True):
+    """Submit reqs at the given arrival offsets (s) while a waiter thread
+    collects them in submission order; a request's solutions are hashed
+    (digest) and freed once it is collected.  Outstanding solution memory on
+    the host is bounded by host_cap bytes (a submission past it waits, and the
+    wait is recorded).  serial: submit each request only after the previous
+    one finished (no overlap).  Returns (records, wall seconds from the first
+    submission to the last completion the server recorded)."""
+    import threading
+    cv = threading.Condition()
+    queue, recs = [], [None] * len(reqs)
+    state = dict(out=0, closed=False, done=0)
+
+    def waiter():
+        i = 0
+        while True:
+            with cv:
+                cv.wait_for(lambda: i < len(queue) or state["closed"])
+                if i >= len(queue):
+                    return
+                rid, idx, xs, nbytes, held, t_sub = queue[i]
+            i += 1
+            st, info, times = srv.wait(rid)
+            recs[idx] = dict(status=st, info=info, times=times, held=held, t_end=t_sub + times[2],
+                             digest=[_digest(x) for x in xs] if digest else None)
+            xs.clear()
+            with cv:
+                state["out"] -= nbytes
+                state["done"] += 1
+                cv.notify_all()
+
+    th = threading.Thread(target=waiter, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for idx, ((f, k, masses), ta) in enumerate(zip(reqs, arrivals)):
+        delay = ta - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        dims, l5 = SERVE_FIELDS[f][0], SERVE_FIELDS[f][1]
+        nbytes = k * cols[f][0].nbytes
+        with cv:
+            if serial:
+                cv.wait_for(lambda: state["done"] == idx)
+            t_ready = time.perf_counter()
+            cv.wait_for(lambda: state["out"] == 0 or state["out"] + nbytes <= host_cap)
+            state["out"] += nbytes
+        held = time.perf_counter() - t_ready
+        xs = [np.empty_like(cols[f][0]) for _ in range(k)]
+        t_sub = time.perf_counter() - t0
+        rid = srv.submit(fids[f], ACTION["M5"], ACTION["b5"], ACTION["c5"], masses[0], l5, cols[f][:k], xs,
+                         masses=masses, opts=opts)
+        with cv:
+            queue.append((rid, idx, xs, nbytes, held, t_sub))
+            cv.notify_all()
+        del xs
+    with cv:
+        state["closed"] = True
+        cv.notify_all()
+    th.join()
+    return recs, max(r["t_end"] for r in recs)
+
+
+def serve_work(req):
+    """Work of a request in RHS x 5D sites (the Poisson rate is set in it)."""
+    f, k, _ = req
+    dims, l5 = SERVE_FIELDS[f][0], SERVE_FIELDS[f][1]
+    return k * float(np.prod(dims)) * l5
+
+
+def phase_summary(reqs, recs, wall):
+    lat = np.array([r["times"][2] for r in recs])
+    nrhs = sum(k for _, k, _ in reqs)
+    by = {}
+    for (f, k, _), r in zip(reqs, recs):
+        by.setdefault("%dx%dx%dx%d L5=%d" % (tuple(SERVE_FIELDS[f][0]) + (SERVE_FIELDS[f][1],)), []).append(
+            r["times"][2])
+    return dict(by_lattice={n: dict(requests=len(v), p50_latency_s=round(float(np.percentile(v, 50)), 3))
+                            for n, v in sorted(by.items())},
+                requests=len(reqs), rhs=nrhs, wall_s=round(wall, 3),
+                solves_per_s=round(len(reqs) / wall, 4), rhs_solves_per_s=round(nrhs / wall, 3),
+                p50_latency_s=round(float(np.percentile(lat, 50)), 3),
+                p99_latency_s=round(float(np.percentile(lat, 99)), 3),
+                mean_queued_s=round(float(np.mean([r["times"][0] for r in recs])), 3),
+                host_cap_wait_s=round(float(sum(r["held"] for r in recs)), 3),
+                model_GBps=round(sum(i["model_bytes"] for r in recs for i in r["info"]) / wall / 1e9, 1),
+                max_true_resid=max(i["true_resid"] for r in recs for i in r["info"]),
+                all_ok=all(r["status"] == 0 and all(i["true_resid"] <= 1e-10 for i in r["info"]) for r in recs))
+
+
+def serve_main(args):
+    """Serving workload: a burst of requests (throughput), the same requests
+    one at a time (no overlap; also the alone-vs-mix bitwise check), then a
+    Poisson stream at a fraction of the measured throughput (latency)."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_1701_07559_amd import inputs as I
+    # links first, in forked workers, before this process touches the GPU
+    workers = max(1, min(16, os.cpu_count() or 1))
+    links = []
+    for dims, l5, gseed, _ in SERVE_FIELDS:
+        t = time.perf_counter()
+        links.append(I.random_links(dims, EPS, gseed, workers=workers))
+        log("links %s seed %d: %.1f s (%d workers)" % (dims, gseed, time.perf_counter() - t, workers))
+    from paper_1701_07559_amd import mdwf as M
+
+    rng = np.random.default_rng(ARRIVAL_SEED)
+    burst = serve_requests(args.requests, rng)
+    stream = serve_requests(args.poisson_requests, rng)
+    gaps = rng.exponential(1.0, size=len(stream))   # unit-rate gaps, scaled once the rate is known
+    srv = M.Server(hip_device=0, mem_budget=0, max_active=args.max_active)
+    out = None
+    try:
+        fids = []
+        for i, ((dims, l5, _, _), U) in enumerate(zip(SERVE_FIELDS, links)):
+            fids.append(srv.add_field(dims, U))
+            if i > 0:
+                links[i] = None
+        cols = []
+        for f, (dims, l5, _, sseed) in enumerate(SERVE_FIELDS):
+            site = I.random_point_site(dims, sseed)
+            cols.append([I.point_source(dims, l5, site, c // 3, c % 3) for c in range(SERVE_MAX_RHS[f])])
+        st0 = srv.stats()
+        log("server: budget %.1f GB after %d resident fields" % (st0["budget"] / 1e9, len(fids)))
+        inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
+        opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1)
+        cap = int(args.host_cap_gb * 1e9)
+        for f, k, ms in burst:
+            log("burst request: %s L5=%d nrhs=%d masses=%s" % (SERVE_FIELDS[f][0], SERVE_FIELDS[f][1], k, ms))
+
+        serial = None
+        if not args.no_serial:
+            rs, ws = run_phase(M, srv, fids, cols, burst, [0.0] * len(burst), opts, cap, serial=True)
+            serial = phase_summary(burst, rs, ws)
+            log("one at a time: %s" % serial)
+        ra, wa = run_phase(M, srv, fids, cols, burst, [0.0] * len(burst), opts, cap)
+        conc = phase_summary(burst, ra, wa)
+        log("burst: %s" % conc)
+        same = None
+        if serial is not None:
+            same = all(a["digest"] == b["digest"] for a, b in zip(ra, rs))
+            conc["bitwise_equal_to_one_at_a_time"] = same
+            conc["speedup_vs_one_at_a_time"] = round(serial["wall_s"] / wa, 3)
+        # offered load: args.load x the burst's throughput in RHS x 5D sites
+        rate = args.load * sum(serve_work(q) for q in burst) / wa / np.mean([serve_work(q) for q in stream])
+        arrivals = list(np.cumsum(gaps / rate))
+        for f, k, ms in stream:
+            log("poisson request: %s L5=%d nrhs=%d" % (SERVE_FIELDS[f][0], SERVE_FIELDS[f][1], k))
+        rp, wp = run_phase(M, srv, fids, cols, stream, arrivals, opts, cap, digest=False)
+        pois = phase_summary(stream, rp, wp)
+        pois["arrival_rate_per_s"] = round(rate, 4)
+        log("poisson: %s" % pois)
+        stats = srv.stats()
+    finally:
+        srv.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = serve_cpu_baseline(links[0], burst, ra)
+    value = conc["model_GBps"]
+    out = {
+        "metric": "Moebius DWF dslash GB/s (% HBM peak); time to r=1e-10 solve, mixed vs FP64",
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(wa * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.inner,
+        "data": "synthetic",
+        "config": {
+            "workload": "serving: %d resident exp(i0.25H) fields %s, M5=1.3 b5=1.5 c5=0.5, m_q per RHS from %s, "
+                        "point-source columns, %s inner, every solve to true residual 1e-10; a burst of %d "
+                        "requests (throughput) then %d Poisson arrivals offering %.2f x that throughput in RHS x 5D sites (latency)" %
+                        (len(SERVE_FIELDS), ["%dx%dx%dx%d L5=%d" % (tuple(d) + (l5,)) for d, l5, _, _ in SERVE_FIELDS],
+                         list(SERVE_MASSES), args.inner, len(burst), len(stream), args.load),
+            "name": "serving", "max_active": args.max_active, "host_cap_gb": args.host_cap_gb,
+            "request_seed": ARRIVAL_SEED,
+        },
+        "serving": dict(burst=conc, one_at_a_time=serial, poisson=pois,
+                        budget_bytes=stats["budget"], peak_reserved_bytes=stats["peak_reserved"]),
+        "roofline": None,
+        "roofline_note": "per-launch timing is off in the server: launches of concurrent requests share the "
+                         "device, so one stream's events do not time one kernel",
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_cpu_baseline(U16, burst, recs, budget_s=25.0):
+    """The FP64 oracle's Schur operator timed on the 16^3 x 48 x 12 field and
+    projected to the burst: two applications (S and S^+) per CG iteration of
+    every RHS, at the iteration counts the burst ran, time scaled by the
+    5D volume of each request's lattice."""
+    import oracle
+    dims, l5 = SERVE_FIELDS[0][0], SERVE_FIELDS[0][1]
+    act = oracle.Action(dims, l5, M5=ACTION["M5"], b5=ACTION["b5"], c5=ACTION["c5"], mq=SERVE_MASSES[1])
+    rng = np.random.default_rng(SRC_SEED)
+    psi = rng.standard_normal(act.shape5) + 1j * rng.standard_normal(act.shape5)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.schur(act, U16, psi)
+        n += 1
+        if time.perf_counter() - t0 > budget_s * 0.5 or n >= 3:
+            break
+    dt = (time.perf_counter() - t0) / n
+    vol0 = np.prod(dims) * l5
+    secs = 0.0
+    for (f, k, _), r in zip(burst, recs):
+        d, lf = SERVE_FIELDS[f][0], SERVE_FIELDS[f][1]
+        secs += sum(i["iters"] for i in r["info"]) * 2 * dt * (np.prod(d) * lf / vol0)
+    return dict(value=float("%.4g" % (len(burst) / secs)), unit="solves/s", cores=1, kind="oracle",
+                sample="%d FP64 Schur applications on 16^3x48 L5=12 (single thread, %.2f s each), projected "
+                       "over the burst's %d requests at their CG iteration counts (2 applications per "
+                       "iteration, time proportional to 5D volume)" % (n, dt, len(burst)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,20 +563,29 @@ def main():
     ap.add_argument("--summary-out", default=None)
     ap.add_argument("--summary-cmds", default="", help="commands that produced the databases ('||'-separated)")
     ap.add_argument("--summary-bench", default=None, help="the JSON line bench.py printed in the traced run")
+    ap.add_argument("--requests", type=int, default=12, help="serving: requests in the burst")
+    ap.add_argument("--poisson-requests", type=int, default=16, help="serving: requests in the Poisson stream")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: Poisson rate / burst throughput")
+    ap.add_argument("--max-active", type=int, default=4, help="serving: worker streams")
+    ap.add_argument("--host-cap-gb", type=float, default=160.0, help="serving: outstanding solution memory on the host")
+    ap.add_argument("--no-serial", action="store_true", help="serving: skip the one-at-a-time pass")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
         return
 
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "serving":
+        serve_main(args)
+        return
     global DIMS, L5, MASSES, GAUGE_SEED, SITE_SEED, GROUPS
     wl = WORKLOADS[args.workload]
     DIMS, L5, MASSES, GROUPS = wl["DIMS"], wl["L5"], wl["MASSES"], wl["GROUPS"]
     GAUGE_SEED, SITE_SEED = wl["GAUGE_SEED"], wl["SITE_SEED"]
     ACTION["mq"] = MASSES[0]
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
 
     import torch
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))

@@ -262,8 +262,10 @@ mdwf_status mdwf_server_add_field(mdwf_server *srv, const mdwf_geometry *geom, c
 
 /* Queue a solve of nrhs RHS on field_id with action act (mq: per-RHS masses
  * or NULL for act->mq; opts NULL = defaults; use_graph and profile_iters are
- * ignored).  Returns at once with *req_id.  ERR_ARG on bad arguments, ERR_OOM
- * if the request can never fit the budget. */
+ * ignored).  Returns at once with *req_id.  A request whose footprint exceeds
+ * the budget is split into sub-batches of the most RHS that fit, solved one
+ * after another (bitwise the same results).  ERR_ARG on bad arguments,
+ * ERR_OOM if not even one RHS fits the budget. */
 mdwf_status mdwf_server_submit(mdwf_server *srv, int field_id, const mdwf_action *act, int nrhs,
                                const double *const *b, double *const *x, const double *mq,
                                const mdwf_solver_opts *opts, int *req_id);

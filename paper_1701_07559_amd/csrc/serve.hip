@@ -6,6 +6,9 @@
 // kernels of concurrent requests overlap on the device.  Gauge fields stay
 // resident for the server's lifetime and are shared by every worker; solver
 // buffers are released when a request finishes, returning its footprint.
+// A request whose footprint exceeds the whole budget is split into
+// sub-batches of the most RHS that fit, solved one after another on its
+// worker.
 //
 // A request's arithmetic does not depend on what else runs (no reduction
 // crosses requests, chunking and sub-batching are bitwise neutral), so its
@@ -37,7 +40,8 @@ struct Request {
     std::vector<double*> x;
     std::vector<double> mq;
     mdwf_solver_opts opts{};
-    size_t footprint = 0;
+    size_t footprint = 0;       // of one sub-batch
+    int batch = 0;              // RHS per sub-batch
     double t_submit = 0, t_start = 0, t_end = 0;
     bool done = false;
     mdwf_status status = MDWF_OK;
@@ -115,10 +119,22 @@ void worker_loop(mdwf_server* s) {
             if (st == MDWF_OK) share_gauge(c, f.master);
         }
         if (st == MDWF_OK) st = mdwf_set_action(c, &r->act);
-        const int n = int(r->b.size());
-        if (st == MDWF_OK)
-            st = mdwf_solve(c, n, r->b.data(), r->x.data(), r->mq.data(), &r->opts, r->info.data());
         std::string msg = st == MDWF_OK ? std::string() : std::string(mdwf_last_error(c));
+        const int n = int(r->b.size());
+        // sub-batches in order; one that did not converge still wrote its
+        // results, so the rest still run; a hard error stops the request
+        for (int k0 = 0; st == MDWF_OK || st == MDWF_ERR_NOCONV || st == MDWF_ERR_NUMERIC; k0 += r->batch) {
+            if (k0 >= n) break;
+            const int k = std::min(r->batch, n - k0);
+            const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0,
+                                              &r->opts, r->info.data() + k0);
+            if (sk == MDWF_OK) continue;
+            const bool hard = sk != MDWF_ERR_NOCONV && sk != MDWF_ERR_NUMERIC;
+            if (st == MDWF_OK || hard) {
+                st = sk;
+                msg = mdwf_last_error(c);
+            }
+        }
         if (c) release_solver_buffers(c);
         {
             std::lock_guard<std::mutex> lk(s->m);
@@ -212,10 +228,14 @@ mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* 
     r.opts.profile_iters = 0;
     r.info.assign(nrhs, mdwf_solve_info{});
     std::lock_guard<std::mutex> lk(s->m);
-    r.footprint = footprint(s->fields[field_id], r.act, nrhs, r.opts.inner);
-    if (r.footprint > s->budget)
-        return sfail(s, MDWF_ERR_OOM, "request needs " + std::to_string(r.footprint) + " device bytes, the budget is " +
-                                          std::to_string(s->budget));
+    // the most RHS per sub-batch whose footprint fits the budget
+    const GaugeField& fld = s->fields[field_id];
+    r.batch = nrhs;
+    while (r.batch > 0 && footprint(fld, r.act, r.batch, r.opts.inner) > s->budget) --r.batch;
+    if (r.batch == 0)
+        return sfail(s, MDWF_ERR_OOM, "one RHS needs " + std::to_string(footprint(fld, r.act, 1, r.opts.inner)) +
+                                          " device bytes, the budget is " + std::to_string(s->budget));
+    r.footprint = footprint(fld, r.act, r.batch, r.opts.inner);
     r.t_submit = wall();
     const int id = s->next_id++;
     s->reqs.emplace(id, std::move(r));

@@ -66,21 +66,34 @@ def _exp_iH(H: np.ndarray, eps: float) -> np.ndarray:
     return np.einsum("...ab,...b,...cb->...ac", v, ph, v.conj())
 
 
-def random_links(dims, eps: float, seed: int) -> np.ndarray:
+def _links_slice(h: np.ndarray, lam: np.ndarray, eps: float) -> np.ndarray:
+    return _exp_iH(np.tensordot(h, lam, axes=([4], [0])), eps)
+
+
+def random_links(dims, eps: float, seed: int, workers: int = 1) -> np.ndarray:
     """Smooth random SU(3) links ``U = exp(i eps H)``, i.i.d. per link.
 
     ``dims`` = (X, Y, Z, T).  ``H = sqrt(5/8) sum_a h_a lambda_a`` with
     h_a ~ N(0, 1).  Generated one time-slice at a time so that memory stays
     bounded at the largest shapes; the stream order does not depend on that.
+    ``workers`` > 1 draws the normals in the same order in this process and
+    exponentiates the slices in forked worker processes (bitwise the same
+    field); call it before the process has touched a GPU.
     """
     X, Y, Z, T = (int(d) for d in dims)
     lam = gell_mann() * np.sqrt(5.0 / 8.0)
     rng = _rng(seed)
     U = np.empty((T, Z, Y, X, 4, 3, 3), dtype=np.complex128)
-    for t in range(T):
-        h = rng.standard_normal((Z, Y, X, 4, 8))
-        H = np.tensordot(h, lam, axes=([4], [0]))
-        U[t] = _exp_iH(H, eps)
+    if workers <= 1 or T < 2:
+        for t in range(T):
+            U[t] = _links_slice(rng.standard_normal((Z, Y, X, 4, 8)), lam, eps)
+        return U
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(int(workers), mp_context=mp.get_context("fork")) as ex:
+        futs = [ex.submit(_links_slice, rng.standard_normal((Z, Y, X, 4, 8)), lam, eps) for _ in range(T)]
+        for t, f in enumerate(futs):
+            U[t] = f.result()
     return U
 
 

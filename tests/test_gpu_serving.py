@@ -95,12 +95,45 @@ def test_server_rejects_bad_requests(M):
         with pytest.raises(M.MdwfError) as e:   # unknown field
             srv.submit(fid + 5, 1.3, 1.5, 0.5, 0.05, 8, [b], [x])
         assert e.value.status == M.MDWF_ERR_ARG
-        many = [b] * 40                          # can never fit the budget
-        with pytest.raises(M.MdwfError) as e:
-            srv.submit(fid, 1.3, 1.5, 0.5, 0.05, 8, many, [np.zeros_like(b) for _ in many])
-        assert e.value.status == M.MDWF_ERR_OOM
+        with pytest.raises(M.MdwfError) as e:   # L5 beyond the lane group
+            srv.submit(fid, 1.3, 1.5, 0.5, 0.05, 40, [b], [x])
+        assert e.value.status == M.MDWF_ERR_ARG
         rid = srv.submit(fid, 1.3, 1.5, 0.5, 0.05, 8, [b], [x], opts=dict(inner=2))
         st, info, _ = srv.wait(rid)
         assert st == M.MDWF_OK and info[0]["true_resid"] <= 1e-10
     finally:
         srv.close()
+    # the fixed part of a solve's footprint alone exceeds this budget
+    tiny = M.Server(mem_budget=32 << 20, max_active=1)
+    try:
+        fid = tiny.add_field(dims, I.random_links(dims, 0.3, 63))
+        with pytest.raises(M.MdwfError) as e:
+            tiny.submit(fid, 1.3, 1.5, 0.5, 0.05, 8, [b], [x])
+        assert e.value.status == M.MDWF_ERR_OOM
+    finally:
+        tiny.close()
+
+
+def test_request_larger_than_the_budget_runs_in_sub_batches(M):
+    # 24 RHS need more than the budget; the server splits them into
+    # sub-batches that fit, and the results equal one solve of all 24
+    dims, L5 = (4, 4, 4, 8), 8
+    U = I.random_links(dims, 0.3, 65)
+    bs = [I.gaussian_source(dims, L5, 900 + k) for k in range(24)]
+    masses = [(0.05, 0.1, 0.2)[k % 3] for k in range(24)]
+    budget = 80 << 20
+    srv = M.Server(mem_budget=budget, max_active=2)
+    try:
+        fid = srv.add_field(dims, U)
+        xs = [np.zeros_like(b) for b in bs]
+        rid = srv.submit(fid, 1.3, 1.5, 0.5, masses[0], L5, bs, xs, masses=masses, opts=dict(inner=2))
+        st, info, _ = srv.wait(rid)
+        assert st == M.MDWF_OK and all(i["true_resid"] <= 1e-10 for i in info)
+        stats = srv.stats()
+        assert 0 < stats["peak_reserved"] <= stats["budget"] <= budget
+    finally:
+        srv.close()
+    ref, its = alone(M, dims, U, L5, masses, 2, bs)
+    assert [i["iters"] for i in info] == its
+    for a, b in zip(xs, ref):
+        assert np.array_equal(a, b)
