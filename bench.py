@@ -569,6 +569,9 @@ def main():
     ap.add_argument("--max-active", type=int, default=4, help="serving: worker streams")
     ap.add_argument("--host-cap-gb", type=float, default=160.0, help="serving: outstanding solution memory on the host")
     ap.add_argument("--no-serial", action="store_true", help="serving: skip the one-at-a-time pass")
+    ap.add_argument("--schur-form", choices=["asym", "sym"], default="asym",
+                    help="CG operator of the mixed solve: S or the symmetric K5^-1 S")
+    ap.add_argument("--shamir", action="store_true", help="b5 = 1, c5 = 0 instead of the Moebius b5, c5")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
@@ -586,6 +589,8 @@ def main():
     DIMS, L5, MASSES, GROUPS = wl["DIMS"], wl["L5"], wl["MASSES"], wl["GROUPS"]
     GAUGE_SEED, SITE_SEED = wl["GAUGE_SEED"], wl["SITE_SEED"]
     ACTION["mq"] = MASSES[0]
+    if args.shamir:
+        ACTION["b5"], ACTION["c5"] = 1.0, 0.0
 
     import torch
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
@@ -660,7 +665,7 @@ def main():
     # profile_iters: the library times its batched hop launches of 10 CG
     # iterations with HIP events on the solve stream (the roofline figure)
     opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1, use_graph=args.graph,
-                profile_iters=0 if args.graph else 10)
+                profile_iters=0 if args.graph else 10, schur_form=1 if args.schur_form == "sym" else 0)
     bptr = [b[rhs_col[k]].data_ptr() for k in range(nrhs)]
     xptr = [x[k].data_ptr() for k in range(per)]
 
@@ -723,7 +728,8 @@ def main():
         log("cpu oracle %.3f GB/s" % cpu["value"])
 
     roof = roofline(infos[0], args.inner, V * L5 // 2)
-    rec = stored_traffic() if (roof and args.inner == "f16" and args.workload == "mixed" and nrhs == 12) else None
+    rec = stored_traffic() if (roof and args.inner == "f16" and args.workload == "mixed" and nrhs == 12
+                               and args.schur_form == "asym" and not args.shamir) else None
     if rec:
         roof["traffic"] = round(rec["traffic_bytes_per_launch"], 0)
         roof["traffic_note"] = "HBM bytes per S application (kernels A + B) from rocprofv3 FETCH_SIZE / WRITE_SIZE, " \
@@ -743,13 +749,15 @@ def main():
         "dtype": args.inner,
         "data": "synthetic",
         "config": {
-            "workload": "%dx%dx%dx%d L5=%d M5=1.3 b5=1.5 c5=0.5 m_q=%s, exp(i0.25H) links (plaquette %.3f), "
+            "workload": "%dx%dx%dx%d L5=%d M5=%g b5=%g c5=%g m_q=%s, exp(i0.25H) links (plaquette %.3f), "
                         "%d point-source RHS (%d columns x %d masses) in %d multi-RHS %s-inner launch(es) of %d, "
-                        "each to true residual 1e-10" %
-                        (X, Y, Z, T, L5, "/".join(str(m) for m in MASSES), plaq, nrhs, ncol, len(MASSES),
-                         GROUPS, args.inner, per),
+                        "%s Schur form, each to true residual 1e-10" %
+                        (X, Y, Z, T, L5, ACTION["M5"], ACTION["b5"], ACTION["c5"],
+                         "/".join(str(m) for m in MASSES), plaq, nrhs, ncol, len(MASSES),
+                         GROUPS, args.inner, per, "symmetric" if args.schur_form == "sym" else "asymmetric"),
             "name": args.workload,
             "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": args.inner,
+            "schur_form": args.schur_form, "b5": ACTION["b5"], "c5": ACTION["c5"],
             "launch_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), tune)} if tune else None),
         },
         "solve": {

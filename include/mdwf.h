@@ -94,7 +94,9 @@ typedef enum {
     MDWF_OP_K5INV_DAG = 11,  /* full -> full : (K5^+)^-1                          */
     MDWF_OP_B = 12,          /* full -> full : B = b5 + c5 C                      */
     MDWF_OP_B_DAG = 13,      /* full -> full : B^+                                */
-    MDWF_OP_COUNT = 14
+    MDWF_OP_SCHUR_SYM = 14,  /* even -> even : K5^-1 S (symmetric form, Sec. VII) */
+    MDWF_OP_SCHUR_SYM_DAG = 15, /* even -> even : S^+ K5^-+                      */
+    MDWF_OP_COUNT = 16
 } mdwf_op;
 
 typedef struct {
@@ -120,6 +122,10 @@ typedef struct {
                             iterations (from the third on) with HIP events on
                             the solve stream; 0 = off, at most 64, ignored
                             with use_graph                                   */
+    int schur_form;      /* 0: CG on the asymmetric S x_e = b'_e; 1: on the
+                            symmetric K5^-1 S x_e = K5^-1 b'_e (Sec. VII), the
+                            same kernels with other coefficients; the stop
+                            is the same true residual ||b - D5 x|| / ||b||   */
 } mdwf_solver_opts;
 
 typedef struct {
@@ -196,7 +202,7 @@ mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, 
                            void *stream);
 
 /* Fill opts with defaults: tol 1e-10, max_iter 100000, inner F64, delta 0.1,
- * check_every 1, use_graph 0, profile_iters 0. */
+ * check_every 1, use_graph 0, profile_iters 0, schur_form 0. */
 void mdwf_default_opts(mdwf_solver_opts *opts);
 
 /* Launch shape of the hop kernels for one storage precision. */

@@ -76,6 +76,8 @@ def _load():
             ("oracle_D5", [P, d, d, d, C.c_int], None),
             ("oracle_schur", [P, d, d, d, C.c_int], None),
             ("oracle_schur_sym", [P, d, d, d, C.c_int], None),
+            ("oracle_schur_rp", [P, d, d, d, C.c_int], None),
+            ("oracle_Binv", [P, d, d, C.c_int], None),
             ("oracle_prep_source", [P, d, d, d], None),
             ("oracle_reconstruct", [P, d, d, d], None),
             ("oracle_true_residual", [P, d, d, d], C.c_double),
@@ -160,6 +162,7 @@ apply_C = _site5("oracle_C")
 apply_B = _site5("oracle_B")
 apply_K5 = _site5("oracle_K5")
 apply_K5inv = _site5("oracle_K5inv")
+apply_Binv = _site5("oracle_Binv")
 
 
 def hop(act: Action, U, psi, out_parity: int, dag=False):
@@ -194,6 +197,16 @@ def schur_sym(act: Action, U, psi, dag=False):
     psi, pi = _c(psi)
     out = np.empty_like(psi)
     _load().oracle_schur_sym(C.byref(act.params()), pu, pi, out.ctypes.data, int(dag))
+    return out
+
+
+def schur_rp(act: Action, U, psi, dag=False):
+    """S B^-1 (or B^-+ S^+) on the even sites: the Schur operator with right
+    preconditioning by B = b5 + c5 C."""
+    U, pu = _c(U)
+    psi, pi = _c(psi)
+    out = np.empty_like(psi)
+    _load().oracle_schur_rp(C.byref(act.params()), pu, pi, out.ctypes.data, int(dag))
     return out
 
 

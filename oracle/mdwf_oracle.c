@@ -312,6 +312,45 @@ static void apply_K5inv(const oracle_params *p, const cplx *in, cplx *out, int d
     free(K[0]); free(K[1]); free(A); free(col);
 }
 
+/* Dense L5 x L5 matrix of B = b5 + c5 C (or B^+) on one chirality, from the
+ * definition of C applied to unit vectors along s. */
+static void b_matrix(const oracle_params *p, int upper, int dag, double *Bm)
+{
+    const int L5 = p->L5;
+    for (int j = 0; j < L5; ++j)
+        for (int i = 0; i < L5; ++i) {
+            double cij = 0.0;
+            int from = (upper != dag) ? i - 1 : i + 1;
+            double f = 1.0;
+            if (from < 0) { from += L5; f = -p->mq; }
+            if (from >= L5) { from -= L5; f = -p->mq; }
+            if (from == j) cij = f;
+            Bm[i * L5 + j] = p->b5 * (i == j ? 1.0 : 0.0) + p->c5 * cij;
+        }
+}
+
+/* B^-1 (or (B^+)^-1), by Gaussian elimination per 4D site, spin and colour. */
+static void apply_Binv(const oracle_params *p, const cplx *in, cplx *out, int dag)
+{
+    const long V = volume(p);
+    const int L5 = p->L5;
+    double *Bm[2], *A = malloc(sizeof(double) * L5 * L5);
+    cplx *col = malloc(sizeof(cplx) * L5);
+    for (int u = 0; u < 2; ++u) {
+        Bm[u] = malloc(sizeof(double) * L5 * L5);
+        b_matrix(p, u, dag, Bm[u]);
+    }
+    for (long x = 0; x < V; ++x)
+        for (int sp = 0; sp < 4; ++sp)
+            for (int a = 0; a < 3; ++a) {
+                for (int s = 0; s < L5; ++s) col[s] = in[((long)s * V + x) * 12 + sp * 3 + a];
+                memcpy(A, Bm[sp < 2], sizeof(double) * L5 * L5);
+                gauss_solve(L5, A, col);
+                for (int s = 0; s < L5; ++s) out[((long)s * V + x) * 12 + sp * 3 + a] = col[s];
+            }
+    free(Bm[0]); free(Bm[1]); free(A); free(col);
+}
+
 /* Dslash (or Dslash^+) on every slice, input masked to parity 1-out_parity,
  * output on parity out_parity (zero elsewhere). */
 static void hop5(const oracle_params *p, const cplx *U, const cplx *in, cplx *out,
@@ -375,6 +414,11 @@ void oracle_K5inv(const oracle_params *p, const double *in, double *out, int dag
 }
 
 /* Bare hop between parities on every slice: out_{out_parity} = Dslash in. */
+void oracle_Binv(const oracle_params *p, const double *in, double *out, int dag)
+{
+    apply_Binv(p, (const cplx *)in, (cplx *)out, dag);
+}
+
 void oracle_hop(const oracle_params *p, const double *U, const double *in, double *out,
                 int dag, int out_parity)
 {
@@ -449,6 +493,28 @@ void oracle_schur_sym(const oracle_params *p, const double *Ud, const double *in
         apply_K5inv(p, t, out, 1);
         memcpy(t, out, n * sizeof(cplx));
         oracle_schur(p, Ud, (const double *)t, outd, 1);
+    }
+    mask_parity(p, out, 0);
+    free(t);
+}
+
+/* The Schur operator preconditioned on the right by B^-1: S B^-1 on the even
+ * sites, or its adjoint B^-+ S^+.  If S B^-1 y = b'_e then x_e = B^-1 y solves
+ * S x_e = b'_e, with the same residual b'_e - S x_e. */
+void oracle_schur_rp(const oracle_params *p, const double *Ud, const double *ind, double *outd, int dag)
+{
+    cplx *out = (cplx *)outd;
+    const long n = n5(p);
+    cplx *t = malloc(n * sizeof(cplx));
+    if (!dag) {
+        memcpy(t, ind, n * sizeof(cplx));
+        mask_parity(p, t, 0);
+        apply_Binv(p, t, out, 0);
+        memcpy(t, out, n * sizeof(cplx));
+        oracle_schur(p, Ud, (const double *)t, outd, 0);
+    } else {
+        oracle_schur(p, Ud, ind, (double *)t, 1);
+        apply_Binv(p, t, out, 1);
     }
     mask_parity(p, out, 0);
     free(t);

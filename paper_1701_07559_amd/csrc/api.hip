@@ -84,6 +84,22 @@ RhsCoef make_coef(const mdwf_action& a, double mq) {
     return c;
 }
 
+// Table of the second kernel of the symmetric Schur form (Sec. VII names
+// both even-odd forms) K5^-1 S = 1 - 1/4 K5^-1 D_eo (B K5^-1) D_oe B: its
+// dense epilogue is K5^-1 (m = kinv) and its centre term the identity
+// (k5 = 1 + 0 C).  K5^-1 does not commute with the hop (C carries the chiral
+// projectors, the hop's 1 -+ gamma_mu flips chirality), so it is applied
+// after the hop, in kernel B; the adjoint S^+ K5^-+ applies K5^-+ to the
+// input first and uses this table's k5 for its centre term, which is then
+// the untransformed input.
+RhsCoef make_coef_sym(const mdwf_action& a, double mq) {
+    RhsCoef c = make_coef(a, mq);
+    for (int k = 0; k < kMaxL5; ++k) c.m[k] = c.kinv[k];
+    c.k5[0] = 1.0;
+    c.k5[1] = 0.0;
+    return c;
+}
+
 double spinor_site_bytes(Prec p) { return p == P64 ? 192.0 : p == P32 ? 96.0 : 52.0; }
 double link_site_bytes(Prec p, int L5) { return (p == P64 ? 8.0 : p == P32 ? 4.0 : 2.0) * 144.0 / L5; }
 
@@ -101,7 +117,7 @@ void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes) {
             f = 1320; b = 2 * bs + bl; break;
         case MDWF_OP_D5: f = 2 * (1320 + 72 + 72 + 48); b = 2 * (3 * bs + bl); break;
         case MDWF_OP_D5_DAG: f = 2 * (1320 + 72 + 72 + 48); b = 2 * (3 * bs + bl); break;
-        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG:
+        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: case MDWF_OP_SCHUR_SYM: case MDWF_OP_SCHUR_SYM_DAG:
             f = (1320 + 72 + 48 * L5) + (1320 + 72 + 48); b = (2 * bs + bl) + (3 * bs + bl); break;
         case MDWF_OP_K5: case MDWF_OP_K5_DAG: case MDWF_OP_B: case MDWF_OP_B_DAG:
             f = 2 * 72; b = 2 * 2 * bs; break;
@@ -156,6 +172,37 @@ size_t gauge_bytes(const mdwf_ctx* c) {
     return tot;
 }
 
+// S, S^+ (sym = false) or K5^-1 S, S^+ K5^-+ (sym = true) on nrhs fields
+// `stride` apart: kernel A into tmp, then kernel B into out with block norm
+// partials of out when `partials` is set.  cf: the action's tables; cfs: the
+// symmetric form's (make_coef_sym).  The symmetric adjoint first writes
+// K5^-+ in to tmp2.  evs: optional events around the two hop launches.
+void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, bool sym, bool dag, const void* in, void* out,
+                  void* tmp, void* tmp2, size_t stride, int nrhs, const RhsCoef* cf, const RhsCoef* cfs,
+                  const int* active, double* partials, hipStream_t st, hipEvent_t* evs) {
+    HopLaunch L{};
+    L.prec = p;
+    L.stride = stride;
+    L.nrhs = nrhs;
+    L.active = active;
+    const void* ain = in;
+    if (sym && dag) {
+        launch_fifth(g, p, FIFTH_K5INV, 1, in, tmp2, stride, nrhs, cf, active, st);
+        ain = tmp2;
+    }
+    if (evs) (void)hipEventRecord(evs[0], st);
+    L.kind = dag ? HOP_SCHUR_A_DAG : HOP_SCHUR_A;
+    L.coef = cf;
+    L.out_parity = 1; L.out = tmp; L.in = ain; L.centre = nullptr; L.partials = nullptr;
+    launch_hop(g, gs, L, st);
+    if (evs) (void)hipEventRecord(evs[1], st);
+    L.kind = dag ? HOP_SCHUR_B_DAG : (sym ? HOP_SCHUR_B_SYM : HOP_SCHUR_B);
+    L.coef = sym ? cfs : cf;
+    L.out_parity = 0; L.out = out; L.in = tmp; L.centre = in; L.partials = partials;
+    launch_hop(g, gs, L, st);
+    if (evs) (void)hipEventRecord(evs[2], st);
+}
+
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
                          const RhsCoef* d_coef, const int* d_active, hipStream_t st) {
     const Geo& g = c->geo;
@@ -182,15 +229,17 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
             launch_hop(g, c->gs, L, st);
             break;
         case MDWF_OP_SCHUR:
-        case MDWF_OP_SCHUR_DAG: {
+        case MDWF_OP_SCHUR_DAG:
+        case MDWF_OP_SCHUR_SYM:
+        case MDWF_OP_SCHUR_SYM_DAG: {
             void* tmp = buf(c, "apply_tmp", stride * nrhs, &s);
             if (!tmp) return s;
-            L.kind = (op == MDWF_OP_SCHUR) ? HOP_SCHUR_A : HOP_SCHUR_A_DAG;
-            L.out_parity = 1; L.out = tmp; L.in = in; L.centre = nullptr;
-            launch_hop(g, c->gs, L, st);
-            L.kind = (op == MDWF_OP_SCHUR) ? HOP_SCHUR_B : HOP_SCHUR_B_DAG;
-            L.out_parity = 0; L.out = out; L.in = tmp; L.centre = in;
-            launch_hop(g, c->gs, L, st);
+            const bool dag = op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_SCHUR_SYM_DAG;
+            const bool sym = op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG;
+            void* tmp2 = sym && dag ? buf(c, "apply_tmp2", stride * nrhs, &s) : nullptr;
+            if (sym && dag && !tmp2) return s;
+            schur_launch(g, c->gs, p, sym, dag, in, out, tmp, tmp2, stride, nrhs, d_coef,
+                         sym ? d_coef + nrhs : nullptr, d_active, nullptr, st);
             break;
         }
         case MDWF_OP_HOP_EO:
@@ -223,13 +272,15 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
 }  // namespace mdwf
 
 // ------------------------------------------------------------------ helpers
+static bool op_sym(mdwf_op op) { return op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG; }
 static bool op_full(mdwf_op op) {
-    return !(op == MDWF_OP_SCHUR || op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_HOP_EO || op == MDWF_OP_HOP_OE ||
-             op == MDWF_OP_HOP_EO_DAG || op == MDWF_OP_HOP_OE_DAG);
+    return !(op == MDWF_OP_SCHUR || op == MDWF_OP_SCHUR_DAG || op_sym(op) || op == MDWF_OP_HOP_EO ||
+             op == MDWF_OP_HOP_OE || op == MDWF_OP_HOP_EO_DAG || op == MDWF_OP_HOP_OE_DAG);
 }
 static int op_in_kind(mdwf_op op) {
     switch (op) {
-        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: return MDWF_HALF_EVEN;
+        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: case MDWF_OP_SCHUR_SYM: case MDWF_OP_SCHUR_SYM_DAG:
+            return MDWF_HALF_EVEN;
         case MDWF_OP_HOP_EO: case MDWF_OP_HOP_EO_DAG: return MDWF_HALF_ODD;
         case MDWF_OP_HOP_OE: case MDWF_OP_HOP_OE_DAG: return MDWF_HALF_EVEN;
         default: return MDWF_FULL;
@@ -237,7 +288,8 @@ static int op_in_kind(mdwf_op op) {
 }
 static int op_out_kind(mdwf_op op) {
     switch (op) {
-        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: return MDWF_HALF_EVEN;
+        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: case MDWF_OP_SCHUR_SYM: case MDWF_OP_SCHUR_SYM_DAG:
+            return MDWF_HALF_EVEN;
         case MDWF_OP_HOP_EO: case MDWF_OP_HOP_EO_DAG: return MDWF_HALF_EVEN;
         case MDWF_OP_HOP_OE: case MDWF_OP_HOP_OE_DAG: return MDWF_HALF_ODD;
         default: return MDWF_FULL;
@@ -314,7 +366,7 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     if (const char* e = std::getenv("MDWF_LINK_MODE")) t0.link_mode = std::atoi(e);
     if (const char* e = std::getenv("MDWF_RHS_GROUP")) t0.rhs_group = std::atoi(e);
     for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
-    if (hipMalloc(&c->d_coef1, sizeof(RhsCoef)) != hipSuccess) {
+    if (hipMalloc(&c->d_coef1, 2 * sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
         mdwf_destroy(c);
         return fail(nullptr, MDWF_ERR_OOM, "device allocation failed");
@@ -347,6 +399,7 @@ void mdwf_default_opts(mdwf_solver_opts* o) {
     o->check_every = 1;
     o->use_graph = 0;
     o->profile_iters = 0;
+    o->schur_form = 0;
 }
 
 static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_device) {
@@ -405,8 +458,8 @@ mdwf_status mdwf_set_action(mdwf_ctx* c, const mdwf_action* a) {
     c->act = *a;
     c->geo.L5 = a->L5;
     c->geo.Vh = c->geo.Vh4 * a->L5;
-    RhsCoef cf = make_coef(*a, a->mq);
-    s = hip_check(c, hipMemcpy(c->d_coef1, &cf, sizeof(cf), hipMemcpyHostToDevice), "coefficient upload");
+    const RhsCoef cf[2] = {make_coef(*a, a->mq), make_coef_sym(*a, a->mq)};
+    s = hip_check(c, hipMemcpy(c->d_coef1, cf, sizeof(cf), hipMemcpyHostToDevice), "coefficient upload");
     if (s) return s;
     c->have_action = true;
     return MDWF_OK;

@@ -29,7 +29,7 @@ struct mdwf_ctx {
     std::map<std::string, Buf> bufs;
 
     // per-RHS coefficient table of the context's own action (one entry)
-    mdwf::RhsCoef* d_coef1 = nullptr;
+    mdwf::RhsCoef* d_coef1 = nullptr;   // [2]: S, then K5^-1 S
     // pinned host staging for scalars
     void* h_pin = nullptr;
     size_t h_pin_n = 0;
@@ -49,13 +49,19 @@ void* pinned(mdwf_ctx* c, size_t n, mdwf_status* st);
 
 // Coefficients of the fifth-dimension polynomials for mass mq.
 RhsCoef make_coef(const mdwf_action& a, double mq);
+RhsCoef make_coef_sym(const mdwf_action& a, double mq);   // kernel B of K5^-1 S
+void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, bool sym, bool dag, const void* in, void* out,
+                  void* tmp, void* tmp2, size_t stride, int nrhs, const RhsCoef* cf, const RhsCoef* cfs,
+                  const int* active, double* partials, hipStream_t st, hipEvent_t* evs = nullptr);
 
 // Install a launch shape for one precision in the geometry.
 void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t);
 
 // Native-layout operator application on `nrhs` right-hand sides stored at
 // byte stride `stride` (half fields; a full field is two consecutive halves of
-// half_field_bytes each and `stride` then covers both).
+// half_field_bytes each and `stride` then covers both).  For the symmetric
+// Schur ops d_coef holds nrhs action tables followed by nrhs make_coef_sym
+// tables.
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
                          const RhsCoef* d_coef, const int* d_active, hipStream_t st);
 

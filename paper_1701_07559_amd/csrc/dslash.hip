@@ -211,16 +211,18 @@ struct HopDev {
 template <int K> struct HopTraits {
     static constexpr bool dag = (K == HOP_D5_DAG || K == HOP_SCHUR_A_DAG || K == HOP_SCHUR_B_DAG || K == HOP_BARE_DAG);
     static constexpr bool preB = (K == HOP_D5 || K == HOP_SCHUR_A || K == HOP_PREP);
-    // epilogue on the hop result: 0 none, 1 B K5^-1, 2 (B K5^-1)^+, 3 B^+
-    static constexpr int epi = (K == HOP_SCHUR_A) ? 1 : (K == HOP_SCHUR_A_DAG) ? 2
+    // epilogue on the hop result: 0 none, 1 sum_k m_k C^k (B K5^-1, or K5^-1
+    // for the symmetric form's kernel B), 2 its adjoint, 3 B^+
+    static constexpr int epi = (K == HOP_SCHUR_A || K == HOP_SCHUR_B_SYM) ? 1 : (K == HOP_SCHUR_A_DAG) ? 2
                              : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 3 : 0;
     // centre term: 0 none, 1 K5, 2 K5^+, 3 identity
     static constexpr int cen = (K == HOP_D5 || K == HOP_SCHUR_B) ? 1
-                             : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 2 : (K == HOP_PREP) ? 3 : 0;
+                             : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 2
+                             : (K == HOP_PREP || K == HOP_SCHUR_B_SYM) ? 3 : 0;
     // kernels B and B^+ also return block partial sums of |out|^2 (CG norms)
-    static constexpr bool norm = (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG);
+    static constexpr bool norm = (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG || K == HOP_SCHUR_B_SYM);
     static constexpr double coef = (K == HOP_D5 || K == HOP_D5_DAG) ? -0.5
-                                 : (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG) ? -0.25
+                                 : (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG || K == HOP_SCHUR_B_SYM) ? -0.25
                                  : (K == HOP_PREP) ? 0.5 : 1.0;
 };
 
@@ -781,6 +783,7 @@ static void launch_hop_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
         case HOP_SCHUR_A_DAG: launch_hop_t<P, HOP_SCHUR_A_DAG>(g, gs, L, st); break;
         case HOP_SCHUR_B_DAG: launch_hop_t<P, HOP_SCHUR_B_DAG>(g, gs, L, st); break;
         case HOP_PREP: launch_hop_t<P, HOP_PREP>(g, gs, L, st); break;
+        case HOP_SCHUR_B_SYM: launch_hop_t<P, HOP_SCHUR_B_SYM>(g, gs, L, st); break;
     }
 }
 

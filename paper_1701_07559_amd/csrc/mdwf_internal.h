@@ -351,7 +351,8 @@ enum HopKind {
     HOP_SCHUR_A_DAG, // out = (B K5^-1)^+ Dslash^+ in
     HOP_SCHUR_B_DAG, // out = K5^+ c - 1/4 B^+ Dslash^+ in
     HOP_PREP,        // out = c + 1/2 Dslash B in
-    HOP_BARE_DAG     // out = Dslash^+ in
+    HOP_BARE_DAG,    // out = Dslash^+ in
+    HOP_SCHUR_B_SYM  // out = c - 1/4 K5^-1 Dslash in (the table's m holds K5^-1)
 };
 
 struct HopLaunch {

@@ -12,6 +12,9 @@
 // The recursion tracks r = b' - S x_e, whose norm equals the full residual
 // |b - D5 x| after reconstruction, so it stops on the quantity that matters;
 // every stop is confirmed by an FP64 true residual of the full system.
+// The symmetric form (schur_form 1) runs the same recursion on
+// K5^-1 S x_e = K5^-1 b'_e with the symmetric coefficient table; its
+// residual is K5^-1 r, so the tracked target is divided by a bound on |K5|.
 //
 // Mixed precision: the inner vectors r, p, s, q and the hop temporary live in
 // FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32;
@@ -35,6 +38,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -62,7 +66,8 @@ struct Solver {
     char* t;                       // inner hop temporary, `chunk` RHS at stride Hi
     char *be, *bo, *rh, *t64, *ye, *xo;   // FP64 scratch, one RHS each
     double* canon = nullptr;       // canonical staging of one field (host I/O)
-    RhsCoef* coef;
+    RhsCoef* coef;                 // [n] the action's, then [n] the symmetric form's
+    bool sym = false;              // CG on K5^-1 S
     CGScal* sc;
     int* act;
     int* msk;
@@ -101,40 +106,24 @@ struct Solver {
         hipok(hipStreamSynchronize(st), "mask upload");
     }
 
-    // S or S^+ on nk consecutive RHS (stride apart) starting at the given
-    // pointers; tmp holds nk odd half fields at the same stride.
-    void schur(Prec pr, const char* in, char* out, char* tmp, size_t stride, int nk, const RhsCoef* cf,
+    // The CG operator (S or K5^-1 S) or its adjoint on nk consecutive RHS
+    // (stride apart) starting at the given pointers; tmp holds nk odd half
+    // fields and tmp2 (symmetric adjoint only) nk even ones at the same
+    // stride.  k0: index of the first RHS in the coefficient tables.
+    void schur(Prec pr, const char* in, char* out, char* tmp, char* tmp2, size_t stride, int nk, int k0,
                const int* mask, bool dag, double* partials, hipEvent_t* evs = nullptr) {
-        HopLaunch L{};
-        L.prec = pr;
-        L.stride = stride;
-        L.nrhs = nk;
-        L.coef = cf;
-        L.active = mask;
-        L.kind = dag ? HOP_SCHUR_A_DAG : HOP_SCHUR_A;
-        L.out_parity = 1;
-        L.out = tmp;
-        L.in = in;
-        L.partials = nullptr;
-        if (evs) hipok(hipEventRecord(evs[0], st), "event");
-        launch_hop(g, c->gs, L, st);
-        if (evs) hipok(hipEventRecord(evs[1], st), "event");
-        L.kind = dag ? HOP_SCHUR_B_DAG : HOP_SCHUR_B;
-        L.out_parity = 0;
-        L.out = out;
-        L.in = tmp;
-        L.centre = in;
-        L.partials = partials;
-        launch_hop(g, c->gs, L, st);
-        if (evs) hipok(hipEventRecord(evs[2], st), "event");
+        schur_launch(g, c->gs, pr, sym, dag, in, out, tmp, tmp2, stride, nk, coef + k0, coef + n + k0, mask,
+                     partials, st, evs);
+        hipok(hipGetLastError(), "schur launch");
     }
 
-    // inner-precision S or S^+ on all RHS, chunk by chunk; partials [n][nbh]
+    // inner-precision operator on all RHS, chunk by chunk; partials [n][nbh].
+    // The symmetric adjoint stages K5^-+ in through q, free at both calls.
     void schur_inner(const char* in, char* out, const int* mask, bool dag, double* partials,
                      hipEvent_t* evs = nullptr) {
         for (int k0 = 0; k0 < n; k0 += chunk) {
             const int nk = std::min(chunk, n - k0);
-            schur(pi, in + Hi * k0, out + Hi * k0, t, Hi, nk, coef + k0, mask ? mask + k0 : nullptr, dag,
+            schur(pi, in + Hi * k0, out + Hi * k0, t, q + Hi * k0, Hi, nk, k0, mask ? mask + k0 : nullptr, dag,
                   partials ? partials + size_t(k0) * nbh : nullptr, k0 == 0 ? evs : nullptr);
         }
     }
@@ -203,8 +192,8 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     mdwf_default_opts(&o);
     if (o_in) o = *o_in;
     if (!(o.tol > 0.0) || o.max_iter < 1 || (o.inner != MDWF_F64 && o.inner != MDWF_F32 && o.inner != MDWF_F16) ||
-        !(o.delta > 0.0 && o.delta < 1.0))
-        return fail(c, MDWF_ERR_ARG, "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1)");
+        !(o.delta > 0.0 && o.delta < 1.0) || (o.schur_form != 0 && o.schur_form != 1))
+        return fail(c, MDWF_ERR_ARG, "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1, schur_form 0/1)");
     if (o.check_every < 1) o.check_every = 1;
     std::vector<double> masses(nrhs, c->act.mq);
     if (mq)
@@ -305,24 +294,32 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     if (host_io) {
         ALLOC(canon, "sv_canon", S.canon_bytes);
     }
-    ALLOC(coef, "sv_coef", sizeof(RhsCoef) * n);
+    ALLOC(coef, "sv_coef", 2 * sizeof(RhsCoef) * n);
     ALLOC(sc, "sv_scal", sizeof(CGScal) * n);
     ALLOC(act, "sv_act", sizeof(int) * n);
     ALLOC(msk, "sv_msk", sizeof(int) * n);
     ALLOC(part, "sv_part", sizeof(double) * n * (S.nbh > S.nbb ? S.nbh : S.nbb));
     ALLOC(sums, "sv_sums", sizeof(double) * n);
 #undef ALLOC
-    const size_t pin_bytes = 2 * sizeof(CGScal) * n + sizeof(double) * n + sizeof(int) * n + sizeof(RhsCoef) * n + 64;
+    const size_t pin_bytes = 2 * sizeof(CGScal) * n + sizeof(double) * n + sizeof(int) * n + 2 * sizeof(RhsCoef) * n + 64;
     char* hp = static_cast<char*>(pinned(c, pin_bytes, &s));
     if (!hp) return s;
     S.hsc[0] = reinterpret_cast<CGScal*>(hp);
     S.hsc[1] = S.hsc[0] + n;
     S.hsum = reinterpret_cast<double*>(S.hsc[1] + n);
     S.hmask = reinterpret_cast<int*>(S.hsum + n);
-    RhsCoef* hcoef = reinterpret_cast<RhsCoef*>(S.hmask + n);
-    for (int k = 0; k < n; ++k) hcoef[k] = make_coef(c->act, masses[k]);
-    if (!S.hipok(hipMemcpyAsync(S.coef, hcoef, sizeof(RhsCoef) * n, hipMemcpyHostToDevice, st), "coef upload"))
+    RhsCoef* hcoef = reinterpret_cast<RhsCoef*>((reinterpret_cast<uintptr_t>(S.hmask + n) + 7) & ~uintptr_t(7));
+    const bool sym = o.schur_form == 1;
+    for (int k = 0; k < n; ++k) {
+        hcoef[k] = make_coef(c->act, masses[k]);
+        hcoef[n + k] = make_coef_sym(c->act, masses[k]);
+    }
+    S.sym = sym;
+    if (!S.hipok(hipMemcpyAsync(S.coef, hcoef, 2 * sizeof(RhsCoef) * n, hipMemcpyHostToDevice, st), "coef upload"))
         return S.err;
+    // |K5| <= |a| + |b| |C| with |C| = max(1, m_q) = 1: a tracked K5^-1 r
+    // below tgt |b| / knorm keeps |r| below tgt |b|
+    const double knorm = sym ? std::fabs(hcoef[0].k5[0]) + std::fabs(hcoef[0].k5[1]) : 1.0;
     if (!S.hipok(hipMemsetAsync(S.sc, 0, sizeof(CGScal) * n, st), "memset")) return S.err;
     for (int e = 0; e < 2; ++e)
         if (!S.hipok(hipEventCreateWithFlags(&S.ev[e], hipEventDisableTiming), "event")) return S.err;
@@ -339,6 +336,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         L.kind = HOP_PREP; L.prec = P64; L.out_parity = 0; L.out = S.bp + S.H64 * k; L.in = S.t64; L.centre = S.be;
         L.stride = S.H64; L.nrhs = 1; L.coef = S.coef + k; L.active = nullptr;
         launch_hop(g, c->gs, L, st);
+        if (sym) {   // the symmetric system's source K5^-1 b'_e
+            launch_fifth(g, P64, FIFTH_K5INV, 0, S.bp + S.H64 * k, S.t64, S.H64, 1, S.coef + k, nullptr, st);
+            S.hipok(hipMemcpyAsync(S.bp + S.H64 * k, S.t64, S.H64, hipMemcpyDeviceToDevice, st), "source copy");
+        }
         if (bnorm[k] == 0.0) {   // b = 0: x = 0 exactly
             active[k] = 0;
             done[k] = 1;
@@ -363,7 +364,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         std::vector<double> rr(n, 0.0);
         for (int k = 0; k < n; ++k) {
             if (!upd[k]) continue;
-            S.schur(P64, S.xh + S.H64 * k, S.rh, S.t64, S.H64, 1, S.coef + k, nullptr, false, nullptr);
+            S.schur(P64, S.xh + S.H64 * k, S.rh, S.t64, nullptr, S.H64, 1, k, nullptr, false, nullptr);
             launch_axpby(g, P64, 1.0, S.bp + S.H64 * k, -1.0, S.rh, S.rh, S.H64, 1, nullptr, S.part, st);
             rr[k] = S.fetch_sums(S.nbb, 1, nullptr)[0];
             launch_convert(g, P64, S.pi, S.rh, S.r + S.Hi * k, S.H64, S.Hi, 1, nullptr, st);
@@ -439,7 +440,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         S.pev.push_back(ev);
     }
 
-    const double tgt = 0.5 * o.tol;
+    const double tgt = 0.5 * o.tol / knorm;
     int it = 0;
     bool pending = false;
     int pend_slot = 0;

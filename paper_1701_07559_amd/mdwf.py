@@ -24,7 +24,7 @@ MDWF_F64, MDWF_F32, MDWF_F16 = 0, 1, 2
 MDWF_FULL, MDWF_HALF_EVEN, MDWF_HALF_ODD = 0, 1, 2
 (MDWF_OP_D5, MDWF_OP_D5_DAG, MDWF_OP_SCHUR, MDWF_OP_SCHUR_DAG, MDWF_OP_HOP_EO, MDWF_OP_HOP_OE,
  MDWF_OP_K5, MDWF_OP_K5INV, MDWF_OP_HOP_EO_DAG, MDWF_OP_HOP_OE_DAG, MDWF_OP_K5_DAG, MDWF_OP_K5INV_DAG,
- MDWF_OP_B, MDWF_OP_B_DAG) = range(14)
+ MDWF_OP_B, MDWF_OP_B_DAG, MDWF_OP_SCHUR_SYM, MDWF_OP_SCHUR_SYM_DAG) = range(16)
 
 # field kinds (in, out) of each operator
 OP_KINDS = {
@@ -35,6 +35,7 @@ OP_KINDS = {
     MDWF_OP_K5: (MDWF_FULL, MDWF_FULL), MDWF_OP_K5INV: (MDWF_FULL, MDWF_FULL),
     MDWF_OP_K5_DAG: (MDWF_FULL, MDWF_FULL), MDWF_OP_K5INV_DAG: (MDWF_FULL, MDWF_FULL),
     MDWF_OP_B: (MDWF_FULL, MDWF_FULL), MDWF_OP_B_DAG: (MDWF_FULL, MDWF_FULL),
+    MDWF_OP_SCHUR_SYM: (MDWF_HALF_EVEN, MDWF_HALF_EVEN), MDWF_OP_SCHUR_SYM_DAG: (MDWF_HALF_EVEN, MDWF_HALF_EVEN),
 }
 
 
@@ -48,7 +49,8 @@ class mdwf_action(C.Structure):
 
 class mdwf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner", C.c_int), ("delta", C.c_double),
-                ("check_every", C.c_int), ("use_graph", C.c_int), ("profile_iters", C.c_int)]
+                ("check_every", C.c_int), ("use_graph", C.c_int), ("profile_iters", C.c_int),
+                ("schur_form", C.c_int)]
 
 
 class mdwf_solve_info(C.Structure):

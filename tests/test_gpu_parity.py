@@ -70,6 +70,8 @@ def oracle_op(M, op, act, U, psi):
         return oracle.D5(act, U, psi, dag=True)
     if op in (M.MDWF_OP_SCHUR, M.MDWF_OP_SCHUR_DAG):
         return half(oracle.schur(act, U, psi, dag=(op == M.MDWF_OP_SCHUR_DAG)), d, 0)
+    if op in (M.MDWF_OP_SCHUR_SYM, M.MDWF_OP_SCHUR_SYM_DAG):
+        return half(oracle.schur_sym(act, U, psi, dag=(op == M.MDWF_OP_SCHUR_SYM_DAG)), d, 0)
     if op in (M.MDWF_OP_HOP_EO, M.MDWF_OP_HOP_EO_DAG):
         return half(oracle.hop(act, U, psi, 0, dag=(op == M.MDWF_OP_HOP_EO_DAG)), d, 0)
     if op in (M.MDWF_OP_HOP_OE, M.MDWF_OP_HOP_OE_DAG):
@@ -105,7 +107,7 @@ GEOMS = [
     ((4, 2, 4, 6), 1, False),
     ((2, 4, 2, 4), 5, True),
 ]
-ALL_OPS = list(range(14))
+ALL_OPS = list(range(16))
 
 
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "x".join(map(str, g[0])) + "_L%d" % g[1])
@@ -335,6 +337,48 @@ def test_solve_matches_oracle(M, cfg1, inner):
         M.mdwf_destroy(ctx)
 
 
+@pytest.mark.parametrize("inner", [0, 1, 2], ids=["f64", "f32_inner", "f16_inner"])
+def test_symmetric_form_solve_matches_oracle(M, cfg1, inner):
+    """CG on K5^-1 S x_e = K5^-1 b'_e (Sec. VII's symmetric form) reaches the
+    same solution: true residual by the oracle's operator at most 1e-10."""
+    act, U, b, x_ref = cfg1
+    ctx = make_ctx(M, act, U)
+    try:
+        x = np.zeros_like(b)
+        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(tol=1e-10, inner=inner, max_iter=20000, schur_form=1))
+        assert st == M.MDWF_OK, info
+        tr = oracle.true_residual(act, U, b, x)
+        assert tr <= 1e-10, (tr, info)
+        assert abs(tr - info[0]["true_resid"]) <= 1e-11
+        assert rel(x, x_ref) <= 1e-7
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_symmetric_form_with_graph_and_shamir_action(M):
+    """Shamir action (b5 = 1, c5 = 0), where K5 is far from a multiple of 1:
+    the symmetric form solves to 1e-10 with the graph-replayed iteration and
+    its result matches the asymmetric solve's."""
+    dims, L5 = (4, 4, 4, 8), 8
+    act = oracle.Action(dims, L5, M5=1.5, b5=1.0, c5=0.0, mq=0.02)
+    U = I.random_links(dims, 0.3, 48)
+    b = I.gaussian_source(dims, L5, 49)
+    ctx = make_ctx(M, act, U)
+    try:
+        xs = {}
+        for form in (0, 1):
+            x = np.zeros_like(b)
+            st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(inner=2, use_graph=1, schur_form=form))
+            assert st == M.MDWF_OK, info
+            assert oracle.true_residual(act, U, b, x) <= 1e-10
+            xs[form] = x
+        assert rel(xs[1], xs[0]) <= 1e-7
+        with pytest.raises(M.MdwfError):
+            M.mdwf_solve(ctx, [b], [np.zeros_like(b)], opts=dict(schur_form=2))
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 def test_solve_graph_replay_matches_eager(M, cfg1):
     act, U, b, _ = cfg1
     ctx = make_ctx(M, act, U)
@@ -374,7 +418,8 @@ def test_solve_launch_timing_changes_nothing(M, cfg1):
         M.mdwf_destroy(ctx)
 
 
-def test_multi_rhs_multi_mass_equals_single(M):
+@pytest.mark.parametrize("form", [0, 1], ids=["asym", "sym"])
+def test_multi_rhs_multi_mass_equals_single(M, form):
     """Point-source columns at three masses in one launch; each equals its solo solve."""
     dims, L5 = (4, 4, 4, 8), 8
     act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
@@ -387,13 +432,13 @@ def test_multi_rhs_multi_mass_equals_single(M):
     try:
         for inner in (0, 2):
             xs = [np.zeros_like(b) for b in bs]
-            st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=inner))
+            st, info = M.mdwf_solve(ctx, bs, xs, mq=masses, opts=dict(inner=inner, schur_form=form))
             assert st == M.MDWF_OK
             for k, b in enumerate(bs):
                 a_k = act.with_mass(masses[k])
                 assert oracle.true_residual(a_k, U, b, xs[k]) <= 1e-10
                 x1 = np.zeros_like(b)
-                st1, info1 = M.mdwf_solve(ctx, [b], [x1], mq=[masses[k]], opts=dict(inner=inner))
+                st1, info1 = M.mdwf_solve(ctx, [b], [x1], mq=[masses[k]], opts=dict(inner=inner, schur_form=form))
                 assert st1 == M.MDWF_OK
                 assert info1[0]["iters"] == info[k]["iters"]
                 assert np.array_equal(x1, xs[k]), "RHS %d differs alone vs batched" % k

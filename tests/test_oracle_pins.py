@@ -493,3 +493,49 @@ def test_symmetric_schur_condition_number():
         ratios[name] = np.linalg.cond(Sh) / np.linalg.cond(S)
     assert ratios["shamir"] < 0.9
     assert 0.99 < ratios["moebius"] <= 1.0
+
+
+@pytest.mark.parametrize("L5,mq,b5,c5", [(8, 0.0102, 1.5, 0.5), (12, 0.3, 2.0, 1.0), (5, 1.0, 1.5, 0.5),
+                                          (6, 0.05, 1.0, 0.0), (1, 0.2, 1.5, 0.5)])
+def test_b_inverse_closed_form(L5, mq, b5, c5):
+    """B = b5 + c5 C has the same closed-form inverse as K5 with (a, b) ->
+    (b5, c5): B^-1 = [b5 (1 + m z^L5)]^-1 sum_k z^k C^k, z = -c5/b5; the
+    oracle inverts B by elimination."""
+    dims = (2, 2, 2, 2)
+    act = oracle.Action(dims, L5, M5=1.3, b5=b5, c5=c5, mq=mq)
+    psi = rand5(act, 24)
+    z = -c5 / b5
+    out = []
+    for S in KR.c5_matrix(L5, mq):
+        acc, Ck = np.zeros((L5, L5)), np.eye(L5)
+        for k in range(L5):
+            acc += z ** k * Ck
+            Ck = Ck @ S
+        out.append(acc / (b5 * (1 + mq * z ** L5)))
+    Bp, Bm = out
+    ref = np.empty_like(psi)
+    ref[..., :2, :] = np.einsum("st,t...->s...", Bp, psi[..., :2, :])
+    ref[..., 2:, :] = np.einsum("st,t...->s...", Bm, psi[..., 2:, :])
+    assert rel(oracle.apply_Binv(act, psi), ref) < 1e-13
+    assert rel(oracle.apply_B(act, oracle.apply_Binv(act, psi)), psi) < 1e-14
+    assert rel(oracle.apply_B(act, oracle.apply_Binv(act, psi, dag=True), dag=True), psi) < 1e-14
+
+
+def test_right_preconditioned_schur_solution_and_adjoint():
+    """S B^-1: y = B x_e, with x from dense LU of D5 x = b, solves
+    S B^-1 y = b'_e; <y, S B^-1 x> = <B^-+ S^+ y, x>."""
+    dims, L5 = (2, 2, 2, 2), 4
+    act = oracle.Action(dims, L5, **ACT)
+    U = I.random_links(dims, 0.4, 34)
+    b = rand5(act, 35)
+    D = KR.d5_matrix(U, dims, L5, **ACT).toarray()
+    x = np.linalg.solve(D, b.ravel()).reshape(b.shape)
+    ev = oracle.even_mask(dims)[None, ..., None, None]
+    y = oracle.apply_B(act, x * ev)
+    lhs = oracle.schur_rp(act, U, y)
+    rhs = oracle.prep_source(act, U, b) * ev
+    assert rel(lhs, rhs) < 1e-12
+    xv, yv = rand5(act, 36) * ev, rand5(act, 37) * ev
+    a1 = vdot(yv, oracle.schur_rp(act, U, xv))
+    a2 = vdot(oracle.schur_rp(act, U, yv, dag=True), xv)
+    assert abs(a1 - a2) <= 1e-13 * abs(a1)
