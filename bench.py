@@ -12,7 +12,9 @@ One step = one pass of the whole hot path: source preparation, the
 mixed-precision CG on the normal equations of the even-odd Schur operator for
 all 12 columns in one multi-RHS launch (fused hop kernels, reductions,
 precision conversions, FP64 reliable updates), odd-site reconstruction and the
-FP64 true-residual check of every column to 1e-10.
+FP64 true-residual check of every column to 1e-10.  By default the CG runs on
+S B^-1 (right preconditioning by B = b5 + c5 C, --schur-form rp); the plain
+FP64 CG it is compared with runs on S (--fp64-form asym).
 
 value = algorithmic HBM bytes of the step (model of every kernel it ran) /
 step time, in GB/s.  Inputs are resident in HBM before the timed region.
@@ -66,6 +68,8 @@ SERVE_MASSES = (0.0048, 0.0102, 0.02)
 SERVE_WEIGHTS = (0.35, 0.3, 0.2, 0.15)
 SERVE_MAX_RHS = (12, 12, 12, 2)
 ARRIVAL_SEED = 501
+FORMS = {"asym": 0, "sym": 1, "rp": 2}
+FORM_NAMES = {"asym": "asymmetric", "sym": "symmetric", "rp": "right-B-preconditioned"}
 
 
 def log(*a):
@@ -141,10 +145,10 @@ def hop_launch_bytes(inner, Vh, nr):
     return [a, b_, a, b_]
 
 
-def roofline(info, inner, Vh):
-    """Dominant kernels of the step: the batched Schur operator S = kernel A
-    then kernel B, as launched inside the timed solve (durations from HIP
-    events the library records on its launch stream)."""
+def roofline(info, inner, Vh, form):
+    """Dominant kernels of the step: the batched CG operator (S, K5^-1 S or
+    S B^-1) = kernel A then kernel B, as launched inside the timed solve
+    (durations from HIP events the library records on its launch stream)."""
     us, nr = info.get("hop_us"), info.get("hop_rhs", 0)
     if not us or nr <= 0 or us[0] <= 0:
         return None
@@ -152,8 +156,10 @@ def roofline(info, inner, Vh):
     ach = (by[0] + by[1]) / ((us[0] + us[1]) * 1e-6) / 1e9
     names = ("A", "B", "A_dag", "B_dag")
     return dict(bound="hbm",
-                kernel="Schur operator S: k_hop<%s, kernel A> + k_hop<%s, kernel B>, %d RHS per launch, "
-                       "mean of %d sampled CG iterations" % (inner.upper(), inner.upper(), nr, info["hop_samples"]),
+                kernel="%s Schur operator: k_hop<%s, %d> (kernel A) + k_hop<%s, %d> (kernel B), %d RHS per "
+                       "launch, mean of %d sampled CG iterations" %
+                       (FORM_NAMES[form], inner.upper(), FORM_KINDS[form][0], inner.upper(), FORM_KINDS[form][1],
+                        nr, info["hop_samples"]),
                 achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                 traffic=None,
                 launches={n: dict(us=round(u, 1), algorithmic_bytes=int(b), GBps=round(b / (u * 1e-6) / 1e9, 1))
@@ -162,7 +168,9 @@ def roofline(info, inner, Vh):
 
 KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1701_07559_amd", "csrc", "dslash.hip")
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "schur_f16_24c64_L8_12rhs_counters.md")
+                            "schur_rp_f16_24c64_L8_12rhs_counters.md")
+# hop kinds (HopKind) of kernels A, B, A^+, B^+ of each CG operator
+FORM_KINDS = {"asym": (3, 4, 5, 6), "sym": (3, 9, 5, 6), "rp": (10, 11, 5, 12)}
 
 
 def kernel_sha():
@@ -171,15 +179,16 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def stored_traffic():
-    """Per-launch HBM traffic of the batched FP16 S launches (kernels A + B)
-    recorded by a counter run, if the hop source is unchanged since."""
+def stored_traffic(form):
+    """Per-launch HBM traffic of the batched FP16 CG-operator launches
+    (kernels A + B) recorded by a counter run, if the hop source is unchanged
+    since and the run used the same Schur form."""
     try:
         with open(TRAFFIC_FILE) as f:
             for line in f:
                 if line.startswith("traffic-record: "):
                     rec = json.loads(line[len("traffic-record: "):])
-                    if rec.get("dslash_sha256") == kernel_sha():
+                    if rec.get("dslash_sha256") == kernel_sha() and rec.get("form") == form:
                         return rec
     except OSError:
         pass
@@ -205,7 +214,11 @@ def summarize(args):
     grid12 = nblk * 12 * 256
     lines = []
     cmds = [c for c in args.summary_cmds.split("||") if c.strip()]
-    lines.append("# rocprofv3 summary: batched FP16 Schur operator in bench.py (24^3x64, L5=8, 12 RHS)")
+    form = args.schur_form
+    kinds = FORM_KINDS[form]
+    names = dict(zip(kinds, ("A", "B", "A_dag", "B_dag")))
+    lines.append("# rocprofv3 summary: batched FP16 %s Schur operator in bench.py (24^3x64, L5=8, 12 RHS)" %
+                 FORM_NAMES[form])
     lines.append("")
     lines.append("Commands (from the repository root on one MI355X, with `export TMPDIR=/tmp`):")
     lines.append("")
@@ -231,12 +244,11 @@ def summarize(args):
         if gx == grid12 and lab.startswith("mdwf::k_hop<F16"):
             kind = int(lab.split(",")[1])
             sel[kind].append(dur / 1e3)
-    names = {3: "A", 4: "B", 5: "A_dag", 6: "B_dag"}
     lines.append("12-RHS launches of the solve (grid %d threads):" % grid12)
     lines.append("")
     lines.append("| kernel | launches | average us |")
     lines.append("|---|---|---|")
-    for kind in (3, 4, 5, 6):
+    for kind in kinds:
         v = sel.get(kind, [])
         if v:
             lines.append("| %s (`k_hop<F16, %d, *>`) | %d | %.1f |" % (names[kind], kind, len(v), sum(v) / len(v)))
@@ -246,7 +258,8 @@ def summarize(args):
             bl = [json.loads(x) for x in f if x.startswith("{")]
         la = (bl[-1].get("roofline") or {}).get("launches") if bl else None
         if la:
-            tr = {k: sum(sel.get(kind, [0])) / max(1, len(sel.get(kind, []))) for k, kind in (("A", 3), ("B", 4))}
+            tr = {k: sum(sel.get(kind, [0])) / max(1, len(sel.get(kind, [])))
+                  for k, kind in (("A", kinds[0]), ("B", kinds[1]))}
             lines.append("Agreement: bench.py in the traced run timed the same launches with HIP events on the "
                          "solve stream (`mdwf_solve_info.hop_us`): A %.1f us, B %.1f us, against %.1f and %.1f us "
                          "in the trace (sum %+.1f %%)." % (la["A"]["us"], la["B"]["us"], tr["A"], tr["B"],
@@ -277,17 +290,17 @@ def summarize(args):
         lines.append("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |")
         lines.append("|---|---|---|---|")
         per = {}
-        for kind in (3, 4, 5, 6):
+        for kind in kinds:
             if fe.get(kind) and wr.get(kind):
                 fk = sum(fe[kind]) / len(fe[kind])
                 wk = sum(wr[kind]) / len(wr[kind])
                 per[kind] = fk * 1024 * f_r + wk * 1024 * f_w
                 lines.append("| %s | %.0f | %.0f | %.4g |" % (names[kind], fk, wk, per[kind]))
         lines.append("")
-        if 3 in per and 4 in per:
-            rec = dict(traffic_bytes_per_launch=per[3] + per[4], kernels="A+B, 12 RHS, FP16",
-                       fetch_scale=round(f_r, 4), write_scale=round(f_w, 4), dslash_sha256=kernel_sha())
-            lines.append("HBM traffic of one batched S application (kernels A + B): %.4g bytes." %
+        if kinds[0] in per and kinds[1] in per:
+            rec = dict(traffic_bytes_per_launch=per[kinds[0]] + per[kinds[1]], kernels="A+B, 12 RHS, FP16",
+                       form=form, fetch_scale=round(f_r, 4), write_scale=round(f_w, 4), dslash_sha256=kernel_sha())
+            lines.append("HBM traffic of one batched operator application (kernels A + B): %.4g bytes." %
                          rec["traffic_bytes_per_launch"])
             lines.append("")
             lines.append("traffic-record: " + json.dumps(rec))
@@ -440,7 +453,7 @@ def serve_main(args):
         st0 = srv.stats()
         log("server: budget %.1f GB after %d resident fields" % (st0["budget"] / 1e9, len(fids)))
         inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
-        opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1)
+        opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1, schur_form=FORMS[args.schur_form])
         cap = int(args.host_cap_gb * 1e9)
         for f, k, ms in burst:
             log("burst request: %s L5=%d nrhs=%d masses=%s" % (SERVE_FIELDS[f][0], SERVE_FIELDS[f][1], k, ms))
@@ -490,10 +503,11 @@ def serve_main(args):
         "data": "synthetic",
         "config": {
             "workload": "serving: %d resident exp(i0.25H) fields %s, M5=1.3 b5=1.5 c5=0.5, m_q per RHS from %s, "
-                        "point-source columns, %s inner, every solve to true residual 1e-10; a burst of %d "
+                        "point-source columns, %s inner, %s Schur form, every solve to true residual 1e-10; a burst of %d "
                         "requests (throughput) then %d Poisson arrivals offering %.2f x that throughput in RHS x 5D sites (latency)" %
                         (len(SERVE_FIELDS), ["%dx%dx%dx%d L5=%d" % (tuple(d) + (l5,)) for d, l5, _, _ in SERVE_FIELDS],
-                         list(SERVE_MASSES), args.inner, len(burst), len(stream), args.load),
+                         list(SERVE_MASSES), args.inner, FORM_NAMES[args.schur_form], len(burst), len(stream),
+                         args.load),
             "name": "serving", "max_active": args.max_active, "host_cap_gb": args.host_cap_gb,
             "request_seed": ARRIVAL_SEED,
         },
@@ -569,8 +583,10 @@ def main():
     ap.add_argument("--max-active", type=int, default=4, help="serving: worker streams")
     ap.add_argument("--host-cap-gb", type=float, default=160.0, help="serving: outstanding solution memory on the host")
     ap.add_argument("--no-serial", action="store_true", help="serving: skip the one-at-a-time pass")
-    ap.add_argument("--schur-form", choices=["asym", "sym"], default="asym",
-                    help="CG operator of the mixed solve: S or the symmetric K5^-1 S")
+    ap.add_argument("--schur-form", choices=["asym", "sym", "rp"], default="rp",
+                    help="CG operator of the mixed solve: S, the symmetric K5^-1 S, or S B^-1")
+    ap.add_argument("--fp64-form", choices=["asym", "sym", "rp"], default="asym",
+                    help="CG operator of the plain FP64 comparison solve")
     ap.add_argument("--shamir", action="store_true", help="b5 = 1, c5 = 0 instead of the Moebius b5, c5")
     args = ap.parse_args()
     if args.summarize:
@@ -665,7 +681,7 @@ def main():
     # profile_iters: the library times its batched hop launches of 10 CG
     # iterations with HIP events on the solve stream (the roofline figure)
     opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1, use_graph=args.graph,
-                profile_iters=0 if args.graph else 10, schur_form=1 if args.schur_form == "sym" else 0)
+                profile_iters=0 if args.graph else 10, schur_form=FORMS[args.schur_form])
     bptr = [b[rhs_col[k]].data_ptr() for k in range(nrhs)]
     xptr = [x[k].data_ptr() for k in range(per)]
 
@@ -705,7 +721,8 @@ def main():
     # plain FP64 CG on the same columns (solved one at a time)
     fp64 = None
     if args.fp64_cols > 0:
-        o64 = dict(tol=1e-10, inner=M.MDWF_F64, max_iter=50000, use_graph=args.graph)
+        o64 = dict(tol=1e-10, inner=M.MDWF_F64, max_iter=50000, use_graph=args.graph,
+                   schur_form=FORMS[args.fp64_form])
         t64 = []
         it64 = []
         for k in range(min(args.fp64_cols, nrhs)):
@@ -716,7 +733,7 @@ def main():
             it64.append(i64[0]["iters"])
             log("fp64 column %d: %.3f s iters %d resid %.2e" % (k, t64[-1], it64[-1], i64[0]["true_resid"]))
         per_col = float(np.mean(t64))
-        fp64 = dict(columns_solved=len(t64), seconds_per_column=per_col, iters=it64,
+        fp64 = dict(form=FORM_NAMES[args.fp64_form], columns_solved=len(t64), seconds_per_column=per_col, iters=it64,
                     seconds_all_columns=per_col * nrhs,
                     note="sum over %d columns = measured per-column time x %d" % (nrhs, nrhs)
                     if len(t64) < nrhs else "measured")
@@ -727,12 +744,12 @@ def main():
         cpu = cpu_baseline(U, DIMS, L5, ACTION)
         log("cpu oracle %.3f GB/s" % cpu["value"])
 
-    roof = roofline(infos[0], args.inner, V * L5 // 2)
-    rec = stored_traffic() if (roof and args.inner == "f16" and args.workload == "mixed" and nrhs == 12
-                               and args.schur_form == "asym" and not args.shamir) else None
+    roof = roofline(infos[0], args.inner, V * L5 // 2, args.schur_form)
+    rec = stored_traffic(args.schur_form) if (roof and args.inner == "f16" and args.workload == "mixed"
+                                              and nrhs == 12 and not args.shamir) else None
     if rec:
         roof["traffic"] = round(rec["traffic_bytes_per_launch"], 0)
-        roof["traffic_note"] = "HBM bytes per S application (kernels A + B) from rocprofv3 FETCH_SIZE / WRITE_SIZE, " \
+        roof["traffic_note"] = "HBM bytes per operator application (kernels A + B) from rocprofv3 FETCH_SIZE / WRITE_SIZE, " \
                                "scaled by the 1 GiB copy calibration; %s" % os.path.relpath(TRAFFIC_FILE)
 
     out = {
@@ -754,7 +771,7 @@ def main():
                         "%s Schur form, each to true residual 1e-10" %
                         (X, Y, Z, T, L5, ACTION["M5"], ACTION["b5"], ACTION["c5"],
                          "/".join(str(m) for m in MASSES), plaq, nrhs, ncol, len(MASSES),
-                         GROUPS, args.inner, per, "symmetric" if args.schur_form == "sym" else "asymmetric"),
+                         GROUPS, args.inner, per, FORM_NAMES[args.schur_form]),
             "name": args.workload,
             "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": args.inner,
             "schur_form": args.schur_form, "b5": ACTION["b5"], "c5": ACTION["c5"],

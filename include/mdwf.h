@@ -96,7 +96,11 @@ typedef enum {
     MDWF_OP_B_DAG = 13,      /* full -> full : B^+                                */
     MDWF_OP_SCHUR_SYM = 14,  /* even -> even : K5^-1 S (symmetric form, Sec. VII) */
     MDWF_OP_SCHUR_SYM_DAG = 15, /* even -> even : S^+ K5^-+                      */
-    MDWF_OP_COUNT = 16
+    MDWF_OP_SCHUR_RP = 16,   /* even -> even : S B^-1 (right preconditioning by B) */
+    MDWF_OP_SCHUR_RP_DAG = 17, /* even -> even : B^-+ S^+                        */
+    MDWF_OP_BINV = 18,       /* full -> full : B^-1                               */
+    MDWF_OP_BINV_DAG = 19,   /* full -> full : (B^+)^-1                           */
+    MDWF_OP_COUNT = 20
 } mdwf_op;
 
 typedef struct {
@@ -122,10 +126,12 @@ typedef struct {
                             iterations (from the third on) with HIP events on
                             the solve stream; 0 = off, at most 64, ignored
                             with use_graph                                   */
-    int schur_form;      /* 0: CG on the asymmetric S x_e = b'_e; 1: on the
-                            symmetric K5^-1 S x_e = K5^-1 b'_e (Sec. VII), the
-                            same kernels with other coefficients; the stop
-                            is the same true residual ||b - D5 x|| / ||b||   */
+    int schur_form;      /* CG operator: 0 the asymmetric S x_e = b'_e;
+                            1 the symmetric K5^-1 S x_e = K5^-1 b'_e (Sec.
+                            VII); 2 S B^-1 y = b'_e, x_e = B^-1 y (right
+                            preconditioning by B: no B before the first hop,
+                            none after the adjoint's second).  The stop is
+                            the same true residual ||b - D5 x|| / ||b||     */
 } mdwf_solver_opts;
 
 typedef struct {

@@ -81,6 +81,19 @@ RhsCoef make_coef(const mdwf_action& a, double mq) {
     }
     c.m[0] = a.b5 * c.kinv[0] - mq * a.c5 * c.kinv[L5 - 1];
     for (int k = 1; k < L5; ++k) c.m[k] = a.b5 * c.kinv[k] + a.c5 * c.kinv[k - 1];
+    // B = b5 + c5 C has the same closed-form inverse with (a, b) -> (b5, c5);
+    // K5 B^-1 is again reduced with C^L5 = -m_q
+    const double zb = -a.c5 / a.b5;
+    double zbl = 1.0;
+    for (int k = 0; k < L5; ++k) zbl *= zb;
+    const double nb = 1.0 / (a.b5 * (1.0 + mq * zbl));
+    double zbk = 1.0;
+    for (int k = 0; k < L5; ++k) {
+        c.binv[k] = zbk * nb;
+        zbk *= zb;
+    }
+    c.w[0] = ka * c.binv[0] - mq * kb * c.binv[L5 - 1];
+    for (int k = 1; k < L5; ++k) c.w[k] = ka * c.binv[k] + kb * c.binv[k - 1];
     return c;
 }
 
@@ -119,6 +132,10 @@ void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes) {
         case MDWF_OP_D5_DAG: f = 2 * (1320 + 72 + 72 + 48); b = 2 * (3 * bs + bl); break;
         case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: case MDWF_OP_SCHUR_SYM: case MDWF_OP_SCHUR_SYM_DAG:
             f = (1320 + 72 + 48 * L5) + (1320 + 72 + 48); b = (2 * bs + bl) + (3 * bs + bl); break;
+        case MDWF_OP_SCHUR_RP: case MDWF_OP_SCHUR_RP_DAG:
+            f = (1320 + 48 * L5) + (1320 + 48 * L5 + 48); b = (2 * bs + bl) + (3 * bs + bl); break;
+        case MDWF_OP_BINV: case MDWF_OP_BINV_DAG:
+            f = 2 * 48 * L5; b = 2 * 2 * bs; break;
         case MDWF_OP_K5: case MDWF_OP_K5_DAG: case MDWF_OP_B: case MDWF_OP_B_DAG:
             f = 2 * 72; b = 2 * 2 * bs; break;
         case MDWF_OP_K5INV: case MDWF_OP_K5INV_DAG:
@@ -172,14 +189,17 @@ size_t gauge_bytes(const mdwf_ctx* c) {
     return tot;
 }
 
-// S, S^+ (sym = false) or K5^-1 S, S^+ K5^-+ (sym = true) on nrhs fields
-// `stride` apart: kernel A into tmp, then kernel B into out with block norm
-// partials of out when `partials` is set.  cf: the action's tables; cfs: the
-// symmetric form's (make_coef_sym).  The symmetric adjoint first writes
-// K5^-+ in to tmp2.  evs: optional events around the two hop launches.
-void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, bool sym, bool dag, const void* in, void* out,
+// The even-odd operator of Schur form `form` or its adjoint on nrhs fields
+// `stride` apart: 0 = S, S^+; 1 = K5^-1 S, S^+ K5^-+ (symmetric); 2 = S B^-1,
+// B^-+ S^+ (right preconditioning by B).  Kernel A writes tmp, then kernel B
+// writes out with block norm partials of out when `partials` is set.  cf: the
+// action's tables; cfs: the symmetric form's (make_coef_sym).  The symmetric
+// adjoint first writes K5^-+ in to tmp2.  evs: optional events around the two
+// hop launches.
+void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, int form, bool dag, const void* in, void* out,
                   void* tmp, void* tmp2, size_t stride, int nrhs, const RhsCoef* cf, const RhsCoef* cfs,
                   const int* active, double* partials, hipStream_t st, hipEvent_t* evs) {
+    const bool sym = form == 1, rp = form == 2;
     HopLaunch L{};
     L.prec = p;
     L.stride = stride;
@@ -191,12 +211,13 @@ void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, bool sym, bool dag, 
         ain = tmp2;
     }
     if (evs) (void)hipEventRecord(evs[0], st);
-    L.kind = dag ? HOP_SCHUR_A_DAG : HOP_SCHUR_A;
+    L.kind = dag ? HOP_SCHUR_A_DAG : (rp ? HOP_SCHUR_A_RP : HOP_SCHUR_A);
     L.coef = cf;
     L.out_parity = 1; L.out = tmp; L.in = ain; L.centre = nullptr; L.partials = nullptr;
     launch_hop(g, gs, L, st);
     if (evs) (void)hipEventRecord(evs[1], st);
-    L.kind = dag ? HOP_SCHUR_B_DAG : (sym ? HOP_SCHUR_B_SYM : HOP_SCHUR_B);
+    L.kind = rp ? (dag ? HOP_SCHUR_B_DAG_RP : HOP_SCHUR_B_RP)
+                : (dag ? HOP_SCHUR_B_DAG : (sym ? HOP_SCHUR_B_SYM : HOP_SCHUR_B));
     L.coef = sym ? cfs : cf;
     L.out_parity = 0; L.out = out; L.in = tmp; L.centre = in; L.partials = partials;
     launch_hop(g, gs, L, st);
@@ -231,14 +252,17 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
         case MDWF_OP_SCHUR:
         case MDWF_OP_SCHUR_DAG:
         case MDWF_OP_SCHUR_SYM:
-        case MDWF_OP_SCHUR_SYM_DAG: {
+        case MDWF_OP_SCHUR_SYM_DAG:
+        case MDWF_OP_SCHUR_RP:
+        case MDWF_OP_SCHUR_RP_DAG: {
             void* tmp = buf(c, "apply_tmp", stride * nrhs, &s);
             if (!tmp) return s;
-            const bool dag = op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_SCHUR_SYM_DAG;
+            const bool dag = op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_SCHUR_SYM_DAG || op == MDWF_OP_SCHUR_RP_DAG;
             const bool sym = op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG;
+            const int form = sym ? 1 : (op == MDWF_OP_SCHUR_RP || op == MDWF_OP_SCHUR_RP_DAG) ? 2 : 0;
             void* tmp2 = sym && dag ? buf(c, "apply_tmp2", stride * nrhs, &s) : nullptr;
             if (sym && dag && !tmp2) return s;
-            schur_launch(g, c->gs, p, sym, dag, in, out, tmp, tmp2, stride, nrhs, d_coef,
+            schur_launch(g, c->gs, p, form, dag, in, out, tmp, tmp2, stride, nrhs, d_coef,
                          sym ? d_coef + nrhs : nullptr, d_active, nullptr, st);
             break;
         }
@@ -255,10 +279,12 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
             launch_hop(g, c->gs, L, st);
             break;
         case MDWF_OP_K5: case MDWF_OP_K5_DAG: case MDWF_OP_K5INV: case MDWF_OP_K5INV_DAG:
-        case MDWF_OP_B: case MDWF_OP_B_DAG: {
+        case MDWF_OP_B: case MDWF_OP_B_DAG: case MDWF_OP_BINV: case MDWF_OP_BINV_DAG: {
             const FifthKind k = (op == MDWF_OP_K5 || op == MDWF_OP_K5_DAG) ? FIFTH_K5
-                              : (op == MDWF_OP_B || op == MDWF_OP_B_DAG) ? FIFTH_B : FIFTH_K5INV;
-            const int dag = (op == MDWF_OP_K5_DAG || op == MDWF_OP_K5INV_DAG || op == MDWF_OP_B_DAG) ? 1 : 0;
+                              : (op == MDWF_OP_B || op == MDWF_OP_B_DAG) ? FIFTH_B
+                              : (op == MDWF_OP_BINV || op == MDWF_OP_BINV_DAG) ? FIFTH_BINV : FIFTH_K5INV;
+            const int dag = (op == MDWF_OP_K5_DAG || op == MDWF_OP_K5INV_DAG || op == MDWF_OP_B_DAG ||
+                             op == MDWF_OP_BINV_DAG) ? 1 : 0;
             launch_fifth(g, p, k, dag, ie, oe, stride, nrhs, d_coef, d_active, st);
             launch_fifth(g, p, k, dag, io, oo, stride, nrhs, d_coef, d_active, st);
             break;
@@ -272,24 +298,25 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
 }  // namespace mdwf
 
 // ------------------------------------------------------------------ helpers
-static bool op_sym(mdwf_op op) { return op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG; }
+static bool op_schur(mdwf_op op) {
+    return op == MDWF_OP_SCHUR || op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG ||
+           op == MDWF_OP_SCHUR_RP || op == MDWF_OP_SCHUR_RP_DAG;
+}
 static bool op_full(mdwf_op op) {
-    return !(op == MDWF_OP_SCHUR || op == MDWF_OP_SCHUR_DAG || op_sym(op) || op == MDWF_OP_HOP_EO ||
-             op == MDWF_OP_HOP_OE || op == MDWF_OP_HOP_EO_DAG || op == MDWF_OP_HOP_OE_DAG);
+    return !(op_schur(op) || op == MDWF_OP_HOP_EO || op == MDWF_OP_HOP_OE || op == MDWF_OP_HOP_EO_DAG ||
+             op == MDWF_OP_HOP_OE_DAG);
 }
 static int op_in_kind(mdwf_op op) {
+    if (op_schur(op)) return MDWF_HALF_EVEN;
     switch (op) {
-        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: case MDWF_OP_SCHUR_SYM: case MDWF_OP_SCHUR_SYM_DAG:
-            return MDWF_HALF_EVEN;
         case MDWF_OP_HOP_EO: case MDWF_OP_HOP_EO_DAG: return MDWF_HALF_ODD;
         case MDWF_OP_HOP_OE: case MDWF_OP_HOP_OE_DAG: return MDWF_HALF_EVEN;
         default: return MDWF_FULL;
     }
 }
 static int op_out_kind(mdwf_op op) {
+    if (op_schur(op)) return MDWF_HALF_EVEN;
     switch (op) {
-        case MDWF_OP_SCHUR: case MDWF_OP_SCHUR_DAG: case MDWF_OP_SCHUR_SYM: case MDWF_OP_SCHUR_SYM_DAG:
-            return MDWF_HALF_EVEN;
         case MDWF_OP_HOP_EO: case MDWF_OP_HOP_EO_DAG: return MDWF_HALF_EVEN;
         case MDWF_OP_HOP_OE: case MDWF_OP_HOP_OE_DAG: return MDWF_HALF_ODD;
         default: return MDWF_FULL;

@@ -50,7 +50,7 @@ void* pinned(mdwf_ctx* c, size_t n, mdwf_status* st);
 // Coefficients of the fifth-dimension polynomials for mass mq.
 RhsCoef make_coef(const mdwf_action& a, double mq);
 RhsCoef make_coef_sym(const mdwf_action& a, double mq);   // kernel B of K5^-1 S
-void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, bool sym, bool dag, const void* in, void* out,
+void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, int form, bool dag, const void* in, void* out,
                   void* tmp, void* tmp2, size_t stride, int nrhs, const RhsCoef* cf, const RhsCoef* cfs,
                   const int* active, double* partials, hipStream_t st, hipEvent_t* evs = nullptr);
 

@@ -209,20 +209,26 @@ struct HopDev {
 };
 
 template <int K> struct HopTraits {
-    static constexpr bool dag = (K == HOP_D5_DAG || K == HOP_SCHUR_A_DAG || K == HOP_SCHUR_B_DAG || K == HOP_BARE_DAG);
+    static constexpr bool dag = (K == HOP_D5_DAG || K == HOP_SCHUR_A_DAG || K == HOP_SCHUR_B_DAG || K == HOP_BARE_DAG ||
+                                 K == HOP_SCHUR_B_DAG_RP);
     static constexpr bool preB = (K == HOP_D5 || K == HOP_SCHUR_A || K == HOP_PREP);
     // epilogue on the hop result: 0 none, 1 sum_k m_k C^k (B K5^-1, or K5^-1
     // for the symmetric form's kernel B), 2 its adjoint, 3 B^+
-    static constexpr int epi = (K == HOP_SCHUR_A || K == HOP_SCHUR_B_SYM) ? 1 : (K == HOP_SCHUR_A_DAG) ? 2
+    static constexpr int epi = (K == HOP_SCHUR_A || K == HOP_SCHUR_B_SYM || K == HOP_SCHUR_A_RP) ? 1
+                             : (K == HOP_SCHUR_A_DAG) ? 2
                              : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 3 : 0;
-    // centre term: 0 none, 1 K5, 2 K5^+, 3 identity
+    // centre term: 0 none, 1 K5, 2 K5^+, 3 identity, 4 dense K5 B^-1 =
+    // sum_k w_k C^k, 5 its adjoint
     static constexpr int cen = (K == HOP_D5 || K == HOP_SCHUR_B) ? 1
                              : (K == HOP_D5_DAG || K == HOP_SCHUR_B_DAG) ? 2
-                             : (K == HOP_PREP || K == HOP_SCHUR_B_SYM) ? 3 : 0;
+                             : (K == HOP_PREP || K == HOP_SCHUR_B_SYM) ? 3
+                             : (K == HOP_SCHUR_B_RP) ? 4 : (K == HOP_SCHUR_B_DAG_RP) ? 5 : 0;
     // kernels B and B^+ also return block partial sums of |out|^2 (CG norms)
-    static constexpr bool norm = (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG || K == HOP_SCHUR_B_SYM);
+    static constexpr bool norm = (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG || K == HOP_SCHUR_B_SYM ||
+                                  K == HOP_SCHUR_B_RP || K == HOP_SCHUR_B_DAG_RP);
     static constexpr double coef = (K == HOP_D5 || K == HOP_D5_DAG) ? -0.5
-                                 : (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG || K == HOP_SCHUR_B_SYM) ? -0.25
+                                 : (K == HOP_SCHUR_B || K == HOP_SCHUR_B_DAG || K == HOP_SCHUR_B_SYM ||
+                                    K == HOP_SCHUR_B_RP || K == HOP_SCHUR_B_DAG_RP) ? -0.25
                                  : (K == HOP_PREP) ? 0.5 : 1.0;
 };
 
@@ -607,7 +613,8 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     constexpr int NP = LinkStage<P>::NP;
     constexpr int kDirBytes = kStageSites * NP * 16;
     constexpr int kLinkBytes = LM == 1 ? kWaves * 8 * kDirBytes : 0;
-    constexpr int kEpiBytes = (TR::epi == 1 || TR::epi == 2) ? 12 * kBlock * int(sizeof(cx<R>)) : 0;
+    constexpr int kEpiBytes = (TR::epi == 1 || TR::epi == 2 || TR::cen == 4 || TR::cen == 5)
+                                  ? 12 * kBlock * int(sizeof(cx<R>)) : 0;
     constexpr int kSmem = kLinkBytes > kEpiBytes ? kLinkBytes : kEpiBytes;
     __shared__ __align__(16) unsigned char smem[kSmem > 0 ? kSmem : 16];
     unsigned char* lslot = smem + size_t(wave) * 8 * kDirBytes + size_t(sw) * NP * 16;
@@ -688,11 +695,49 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
         }
     }
 
+    // dense centre term sum_k w_k C^k (or its adjoint) on the centre field:
+    // the L5 lanes of a site exchange their values through LDS
+    cx<R> cd[12];
+    if constexpr (TR::cen == 4 || TR::cen == 5) {
+        cx<R>* sh = reinterpret_cast<cx<R>*>(smem);
+        cx<R> cv[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) cv[c] = {R(0), R(0)};
+        if (valid) Field<P>::load(at_rhs(a.centre, a.stride, rhs), g.Vh, i * L5 + s, cv);
+        if constexpr (LM == 1) __syncthreads();   // every wave is past the link stage
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = cv[c];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 12; ++c) cd[c] = {R(0), R(0)};
+        if (valid) {
+            const int tbase = tid - s;
+            for (int k = 0; k < L5; ++k) {
+                const R wk = R(cf.w[k]);
+                // C^k on P+ reads slice s-k, on P- slice s+k (adjoint: swapped)
+                int su = (TR::cen == 4) ? s - k : s + k;
+                int sd = (TR::cen == 4) ? s + k : s - k;
+                R fu = wk, fd = wk;
+                if (su < 0) { su += L5; fu = -mq * wk; }
+                if (su >= L5) { su -= L5; fu = -mq * wk; }
+                if (sd < 0) { sd += L5; fd = -mq * wk; }
+                if (sd >= L5) { sd -= L5; fd = -mq * wk; }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) cd[c] = cd[c] + fu * sh[c * kBlock + tbase + su];
+#pragma unroll
+                for (int c = 6; c < 12; ++c) cd[c] = cd[c] + fd * sh[c * kBlock + tbase + sd];
+            }
+        }
+    }
+
     double n2 = 0.0;
     if (valid) {
         const int j = i * L5 + s;
         const R hc = R(TR::coef);
-        if constexpr (TR::cen != 0) {
+        if constexpr (TR::cen == 4 || TR::cen == 5) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) res[c] = cd[c] + hc * res[c];
+        } else if constexpr (TR::cen != 0) {
             cx<R> cv[12];
             Field<P>::load(at_rhs(a.centre, a.stride, rhs), g.Vh, j, cv);
             if constexpr (TR::cen == 1 || TR::cen == 2) {
@@ -784,6 +829,9 @@ static void launch_hop_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
         case HOP_SCHUR_B_DAG: launch_hop_t<P, HOP_SCHUR_B_DAG>(g, gs, L, st); break;
         case HOP_PREP: launch_hop_t<P, HOP_PREP>(g, gs, L, st); break;
         case HOP_SCHUR_B_SYM: launch_hop_t<P, HOP_SCHUR_B_SYM>(g, gs, L, st); break;
+        case HOP_SCHUR_A_RP: launch_hop_t<P, HOP_SCHUR_A_RP>(g, gs, L, st); break;
+        case HOP_SCHUR_B_RP: launch_hop_t<P, HOP_SCHUR_B_RP>(g, gs, L, st); break;
+        case HOP_SCHUR_B_DAG_RP: launch_hop_t<P, HOP_SCHUR_B_DAG_RP>(g, gs, L, st); break;
     }
 }
 
@@ -826,17 +874,19 @@ __global__ void __launch_bounds__(kBlock) k_fifth(const Geo g, int kind, int dag
     __syncthreads();
     if (!valid) return;
 
-    // K5 = k5[0] + k5[1] C, B = b5 + c5 C, K5^-1 = sum_k kinv[k] C^k
+    // K5 = k5[0] + k5[1] C, B = b5 + c5 C, K5^-1 = sum_k kinv[k] C^k,
+    // B^-1 = sum_k binv[k] C^k
     double two[2];
     const double* ck;
     if (kind == FIFTH_K5) { two[0] = cf.k5[0]; two[1] = cf.k5[1]; ck = two; }
     else if (kind == FIFTH_B) { two[0] = cf.b5; two[1] = cf.c5; ck = two; }
+    else if (kind == FIFTH_BINV) { ck = cf.binv; }
     else { ck = cf.kinv; }
     cx<R> o[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) o[c] = {R(0), R(0)};
     const int tbase = tid - s;
-    const int nterms = (kind == FIFTH_K5INV) ? L5 : 2;
+    const int nterms = (kind == FIFTH_K5INV || kind == FIFTH_BINV) ? L5 : 2;
     for (int k = 0; k < nterms; ++k) {
         const R mk = R(ck[k]);
         int su = dag ? s + k : s - k;

@@ -105,6 +105,8 @@ struct RhsCoef {
     double k5[2];         // K5 = k5[0] + k5[1] C
     double m[kMaxL5];     // B K5^-1   = sum_k m[k] C^k
     double kinv[kMaxL5];  // K5^-1     = sum_k kinv[k] C^k
+    double w[kMaxL5];     // K5 B^-1   = sum_k w[k] C^k
+    double binv[kMaxL5];  // B^-1      = sum_k binv[k] C^k
 };
 
 // Bytes of a native half field / link segment.
@@ -352,7 +354,11 @@ enum HopKind {
     HOP_SCHUR_B_DAG, // out = K5^+ c - 1/4 B^+ Dslash^+ in
     HOP_PREP,        // out = c + 1/2 Dslash B in
     HOP_BARE_DAG,    // out = Dslash^+ in
-    HOP_SCHUR_B_SYM  // out = c - 1/4 K5^-1 Dslash in (the table's m holds K5^-1)
+    HOP_SCHUR_B_SYM, // out = c - 1/4 K5^-1 Dslash in (the table's m holds K5^-1)
+    // S B^-1 (right preconditioning by B) and its adjoint B^-+ S^+:
+    HOP_SCHUR_A_RP,      // out = B K5^-1 Dslash in
+    HOP_SCHUR_B_RP,      // out = K5 B^-1 c - 1/4 Dslash in
+    HOP_SCHUR_B_DAG_RP   // out = (K5 B^-1)^+ c - 1/4 Dslash^+ in (A^+ is HOP_SCHUR_A_DAG)
 };
 
 struct HopLaunch {
@@ -370,7 +376,7 @@ struct HopLaunch {
     int nblocks_per_rhs;  // filled by the launcher
 };
 
-enum FifthKind { FIFTH_K5 = 0, FIFTH_K5INV, FIFTH_B };
+enum FifthKind { FIFTH_K5 = 0, FIFTH_K5INV, FIFTH_B, FIFTH_BINV };
 
 void launch_hop(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st);
 void launch_fifth(const Geo& g, Prec p, FifthKind kind, int dag, const void* in, void* out, size_t stride,

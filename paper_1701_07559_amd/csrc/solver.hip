@@ -15,6 +15,9 @@
 // The symmetric form (schur_form 1) runs the same recursion on
 // K5^-1 S x_e = K5^-1 b'_e with the symmetric coefficient table; its
 // residual is K5^-1 r, so the tracked target is divided by a bound on |K5|.
+// Right preconditioning by B (schur_form 2) runs it on S B^-1 y = b'_e: the
+// iterate is y = B x_e (x_hi, x_lo hold y) and the residual is unchanged;
+// x_e = B^-1 y is formed for the true residual and the output.
 //
 // Mixed precision: the inner vectors r, p, s, q and the hop temporary live in
 // FP32 or FP16 (per-site norm) and the inner solution x_lo in FP32;
@@ -67,7 +70,7 @@ struct Solver {
     char *be, *bo, *rh, *t64, *ye, *xo;   // FP64 scratch, one RHS each
     double* canon = nullptr;       // canonical staging of one field (host I/O)
     RhsCoef* coef;                 // [n] the action's, then [n] the symmetric form's
-    bool sym = false;              // CG on K5^-1 S
+    int form = 0;                  // CG operator: 0 S, 1 K5^-1 S, 2 S B^-1
     CGScal* sc;
     int* act;
     int* msk;
@@ -112,7 +115,7 @@ struct Solver {
     // stride.  k0: index of the first RHS in the coefficient tables.
     void schur(Prec pr, const char* in, char* out, char* tmp, char* tmp2, size_t stride, int nk, int k0,
                const int* mask, bool dag, double* partials, hipEvent_t* evs = nullptr) {
-        schur_launch(g, c->gs, pr, sym, dag, in, out, tmp, tmp2, stride, nk, coef + k0, coef + n + k0, mask,
+        schur_launch(g, c->gs, pr, form, dag, in, out, tmp, tmp2, stride, nk, coef + k0, coef + n + k0, mask,
                      partials, st, evs);
         hipok(hipGetLastError(), "schur launch");
     }
@@ -192,8 +195,8 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     mdwf_default_opts(&o);
     if (o_in) o = *o_in;
     if (!(o.tol > 0.0) || o.max_iter < 1 || (o.inner != MDWF_F64 && o.inner != MDWF_F32 && o.inner != MDWF_F16) ||
-        !(o.delta > 0.0 && o.delta < 1.0) || (o.schur_form != 0 && o.schur_form != 1))
-        return fail(c, MDWF_ERR_ARG, "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1, schur_form 0/1)");
+        !(o.delta > 0.0 && o.delta < 1.0) || o.schur_form < 0 || o.schur_form > 2)
+        return fail(c, MDWF_ERR_ARG, "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1, schur_form 0-2)");
     if (o.check_every < 1) o.check_every = 1;
     std::vector<double> masses(nrhs, c->act.mq);
     if (mq)
@@ -310,11 +313,11 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     S.hmask = reinterpret_cast<int*>(S.hsum + n);
     RhsCoef* hcoef = reinterpret_cast<RhsCoef*>((reinterpret_cast<uintptr_t>(S.hmask + n) + 7) & ~uintptr_t(7));
     const bool sym = o.schur_form == 1;
+    S.form = o.schur_form;
     for (int k = 0; k < n; ++k) {
         hcoef[k] = make_coef(c->act, masses[k]);
         hcoef[n + k] = make_coef_sym(c->act, masses[k]);
     }
-    S.sym = sym;
     if (!S.hipok(hipMemcpyAsync(S.coef, hcoef, 2 * sizeof(RhsCoef) * n, hipMemcpyHostToDevice, st), "coef upload"))
         return S.err;
     // |K5| <= |a| + |b| |C| with |C| = max(1, m_q) = 1: a tracked K5^-1 r
@@ -390,6 +393,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     auto verify = [&](int k, bool write_x) {
         S.load_b(k);
         const char* xk = S.xh + S.H64 * k;
+        if (S.form == 2) {   // x_e = B^-1 y
+            launch_fifth(g, P64, FIFTH_BINV, 0, xk, S.rh, S.H64, 1, S.coef + k, nullptr, st);
+            xk = S.rh;
+        }
         HopLaunch L{};
         L.prec = P64; L.stride = S.H64; L.nrhs = 1; L.coef = S.coef + k; L.active = nullptr;
         L.kind = HOP_PREP; L.out_parity = 1; L.out = S.t64; L.in = xk; L.centre = S.bo;

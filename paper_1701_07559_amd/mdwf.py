@@ -24,7 +24,8 @@ MDWF_F64, MDWF_F32, MDWF_F16 = 0, 1, 2
 MDWF_FULL, MDWF_HALF_EVEN, MDWF_HALF_ODD = 0, 1, 2
 (MDWF_OP_D5, MDWF_OP_D5_DAG, MDWF_OP_SCHUR, MDWF_OP_SCHUR_DAG, MDWF_OP_HOP_EO, MDWF_OP_HOP_OE,
  MDWF_OP_K5, MDWF_OP_K5INV, MDWF_OP_HOP_EO_DAG, MDWF_OP_HOP_OE_DAG, MDWF_OP_K5_DAG, MDWF_OP_K5INV_DAG,
- MDWF_OP_B, MDWF_OP_B_DAG, MDWF_OP_SCHUR_SYM, MDWF_OP_SCHUR_SYM_DAG) = range(16)
+ MDWF_OP_B, MDWF_OP_B_DAG, MDWF_OP_SCHUR_SYM, MDWF_OP_SCHUR_SYM_DAG, MDWF_OP_SCHUR_RP, MDWF_OP_SCHUR_RP_DAG,
+ MDWF_OP_BINV, MDWF_OP_BINV_DAG) = range(20)
 
 # field kinds (in, out) of each operator
 OP_KINDS = {
@@ -36,6 +37,8 @@ OP_KINDS = {
     MDWF_OP_K5_DAG: (MDWF_FULL, MDWF_FULL), MDWF_OP_K5INV_DAG: (MDWF_FULL, MDWF_FULL),
     MDWF_OP_B: (MDWF_FULL, MDWF_FULL), MDWF_OP_B_DAG: (MDWF_FULL, MDWF_FULL),
     MDWF_OP_SCHUR_SYM: (MDWF_HALF_EVEN, MDWF_HALF_EVEN), MDWF_OP_SCHUR_SYM_DAG: (MDWF_HALF_EVEN, MDWF_HALF_EVEN),
+    MDWF_OP_SCHUR_RP: (MDWF_HALF_EVEN, MDWF_HALF_EVEN), MDWF_OP_SCHUR_RP_DAG: (MDWF_HALF_EVEN, MDWF_HALF_EVEN),
+    MDWF_OP_BINV: (MDWF_FULL, MDWF_FULL), MDWF_OP_BINV_DAG: (MDWF_FULL, MDWF_FULL),
 }
 
 

@@ -72,14 +72,17 @@ def oracle_op(M, op, act, U, psi):
         return half(oracle.schur(act, U, psi, dag=(op == M.MDWF_OP_SCHUR_DAG)), d, 0)
     if op in (M.MDWF_OP_SCHUR_SYM, M.MDWF_OP_SCHUR_SYM_DAG):
         return half(oracle.schur_sym(act, U, psi, dag=(op == M.MDWF_OP_SCHUR_SYM_DAG)), d, 0)
+    if op in (M.MDWF_OP_SCHUR_RP, M.MDWF_OP_SCHUR_RP_DAG):
+        return half(oracle.schur_rp(act, U, psi, dag=(op == M.MDWF_OP_SCHUR_RP_DAG)), d, 0)
     if op in (M.MDWF_OP_HOP_EO, M.MDWF_OP_HOP_EO_DAG):
         return half(oracle.hop(act, U, psi, 0, dag=(op == M.MDWF_OP_HOP_EO_DAG)), d, 0)
     if op in (M.MDWF_OP_HOP_OE, M.MDWF_OP_HOP_OE_DAG):
         return half(oracle.hop(act, U, psi, 1, dag=(op == M.MDWF_OP_HOP_OE_DAG)), d, 1)
     f = {M.MDWF_OP_K5: oracle.apply_K5, M.MDWF_OP_K5_DAG: oracle.apply_K5,
          M.MDWF_OP_K5INV: oracle.apply_K5inv, M.MDWF_OP_K5INV_DAG: oracle.apply_K5inv,
-         M.MDWF_OP_B: oracle.apply_B, M.MDWF_OP_B_DAG: oracle.apply_B}[op]
-    dag = op in (M.MDWF_OP_K5_DAG, M.MDWF_OP_K5INV_DAG, M.MDWF_OP_B_DAG)
+         M.MDWF_OP_B: oracle.apply_B, M.MDWF_OP_B_DAG: oracle.apply_B,
+         M.MDWF_OP_BINV: oracle.apply_Binv, M.MDWF_OP_BINV_DAG: oracle.apply_Binv}[op]
+    dag = op in (M.MDWF_OP_K5_DAG, M.MDWF_OP_K5INV_DAG, M.MDWF_OP_B_DAG, M.MDWF_OP_BINV_DAG)
     return f(act, psi, dag=dag)
 
 
@@ -107,7 +110,7 @@ GEOMS = [
     ((4, 2, 4, 6), 1, False),
     ((2, 4, 2, 4), 5, True),
 ]
-ALL_OPS = list(range(16))
+ALL_OPS = list(range(20))
 
 
 @pytest.mark.parametrize("geom", GEOMS, ids=lambda g: "x".join(map(str, g[0])) + "_L%d" % g[1])
@@ -338,14 +341,16 @@ def test_solve_matches_oracle(M, cfg1, inner):
 
 
 @pytest.mark.parametrize("inner", [0, 1, 2], ids=["f64", "f32_inner", "f16_inner"])
-def test_symmetric_form_solve_matches_oracle(M, cfg1, inner):
-    """CG on K5^-1 S x_e = K5^-1 b'_e (Sec. VII's symmetric form) reaches the
-    same solution: true residual by the oracle's operator at most 1e-10."""
+@pytest.mark.parametrize("form", [1, 2], ids=["sym", "rp"])
+def test_other_schur_forms_solve_matches_oracle(M, cfg1, inner, form):
+    """CG on K5^-1 S x_e = K5^-1 b'_e (Sec. VII's symmetric form) or on
+    S B^-1 y = b'_e (right preconditioning by B) reaches the same solution:
+    true residual by the oracle's operator at most 1e-10."""
     act, U, b, x_ref = cfg1
     ctx = make_ctx(M, act, U)
     try:
         x = np.zeros_like(b)
-        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(tol=1e-10, inner=inner, max_iter=20000, schur_form=1))
+        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(tol=1e-10, inner=inner, max_iter=20000, schur_form=form))
         assert st == M.MDWF_OK, info
         tr = oracle.true_residual(act, U, b, x)
         assert tr <= 1e-10, (tr, info)
@@ -355,10 +360,10 @@ def test_symmetric_form_solve_matches_oracle(M, cfg1, inner):
         M.mdwf_destroy(ctx)
 
 
-def test_symmetric_form_with_graph_and_shamir_action(M):
+def test_schur_forms_with_graph_and_shamir_action(M):
     """Shamir action (b5 = 1, c5 = 0), where K5 is far from a multiple of 1:
-    the symmetric form solves to 1e-10 with the graph-replayed iteration and
-    its result matches the asymmetric solve's."""
+    every Schur form solves to 1e-10 with the graph-replayed iteration and
+    the results match the asymmetric solve's."""
     dims, L5 = (4, 4, 4, 8), 8
     act = oracle.Action(dims, L5, M5=1.5, b5=1.0, c5=0.0, mq=0.02)
     U = I.random_links(dims, 0.3, 48)
@@ -366,15 +371,15 @@ def test_symmetric_form_with_graph_and_shamir_action(M):
     ctx = make_ctx(M, act, U)
     try:
         xs = {}
-        for form in (0, 1):
+        for form in (0, 1, 2):
             x = np.zeros_like(b)
             st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(inner=2, use_graph=1, schur_form=form))
             assert st == M.MDWF_OK, info
             assert oracle.true_residual(act, U, b, x) <= 1e-10
             xs[form] = x
-        assert rel(xs[1], xs[0]) <= 1e-7
+        assert rel(xs[1], xs[0]) <= 1e-7 and rel(xs[2], xs[0]) <= 1e-7
         with pytest.raises(M.MdwfError):
-            M.mdwf_solve(ctx, [b], [np.zeros_like(b)], opts=dict(schur_form=2))
+            M.mdwf_solve(ctx, [b], [np.zeros_like(b)], opts=dict(schur_form=3))
     finally:
         M.mdwf_destroy(ctx)
 
@@ -418,7 +423,7 @@ def test_solve_launch_timing_changes_nothing(M, cfg1):
         M.mdwf_destroy(ctx)
 
 
-@pytest.mark.parametrize("form", [0, 1], ids=["asym", "sym"])
+@pytest.mark.parametrize("form", [0, 1, 2], ids=["asym", "sym", "rp"])
 def test_multi_rhs_multi_mass_equals_single(M, form):
     """Point-source columns at three masses in one launch; each equals its solo solve."""
     dims, L5 = (4, 4, 4, 8), 8
