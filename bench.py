@@ -684,6 +684,14 @@ def main():
                 profile_iters=0 if args.graph else 10, schur_form=FORMS[args.schur_form])
     bptr = [b[rhs_col[k]].data_ptr() for k in range(nrhs)]
     xptr = [x[k].data_ptr() for k in range(per)]
+    # launch shapes for the solve itself: the inner precision on its CG
+    # operator with `per` RHS per launch, FP64 on it with one RHS
+    solve_tune = None
+    if not args.no_tune:
+        solve_tune = M.mdwf_autotune_solve(ctx, per, opts)
+        for pn, t in zip(("f64", "f32", "f16"), solve_tune):
+            log("solve autotune %s: tile %s xcd_remap %d nt_store %d link_mode %d rhs_group %d  %.1f us" %
+                (pn, t["tile"], t["xcd_remap"], t["nt_store"], t["link_mode"], t["rhs_group"], t["us"]))
 
     def step():
         """The whole step: every launch group solved to 1e-10 (status, infos)."""
@@ -776,6 +784,7 @@ def main():
             "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": args.inner,
             "schur_form": args.schur_form, "b5": ACTION["b5"], "c5": ACTION["c5"],
             "launch_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), tune)} if tune else None),
+            "solve_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), solve_tune)} if solve_tune else None),
         },
         "solve": {
             "seconds": round(ms_per_step / 1e3, 4),

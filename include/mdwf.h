@@ -237,6 +237,17 @@ typedef struct {
  * of each precision). */
 mdwf_status mdwf_autotune(mdwf_ctx *ctx, mdwf_launch_tune *out);
 
+/* Autotuner for the launches of one solve shape: the inner precision
+ * opts->inner is tuned on the CG operator of opts->schur_form and its
+ * adjoint with nrhs RHS per launch (as one CG iteration launches them;
+ * candidates also include the RHS grouping), and, for a mixed inner
+ * precision, FP64 on that operator with one RHS (the reliable updates).
+ * Other precisions keep their shapes.  out[3] (may be NULL) receives every
+ * precision's shape.  opts NULL = defaults.  Scratch: four (symmetric
+ * form: five) inner-precision half fields per RHS.  ERR_ARG on nrhs < 1 or
+ * bad options. */
+mdwf_status mdwf_autotune_solve(mdwf_ctx *ctx, const mdwf_solver_opts *opts, int nrhs, mdwf_launch_tune *out);
+
 /* Current launch shape of precision `prec` (defaults before autotuning). */
 mdwf_status mdwf_get_tune(const mdwf_ctx *ctx, mdwf_prec prec, mdwf_launch_tune *out);
 

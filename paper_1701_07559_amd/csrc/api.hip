@@ -583,13 +583,20 @@ mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* o
     return MDWF_OK;
 }
 
-mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
-    mdwf_status s = ready(c);
-    if (s) return s;
+}  // extern "C"
+
+namespace {
+
+// Coordinate-descent tuning of precision p's launch shape on the CG operator
+// of Schur form `form` with nrhs RHS per launch (its adjoint too when
+// `with_dag`): traversal tile (z-blocks and compact 4D tiles), link mode,
+// non-temporal stores and workgroup numbering, then (nrhs > 1) the RHS
+// grouping.  Each candidate: 2 warm-up applications, the mean of 5 timed.
+mdwf_status tune_precision(mdwf_ctx* c, Prec p, int form, int nrhs, bool with_dag, const double* cin,
+                           hipEvent_t e0, hipEvent_t e1, mdwf_launch_tune* out) {
     Geo& g = c->geo;
     hipStream_t st = c->stream;
-    // traversal tiles: z-blocks (full x-y planes, t inside) of small
-    // power-of-two depth and of Z, and compact 4D tiles of 384..6912 sites
+    mdwf_status s = MDWF_OK;
     std::vector<std::array<int, 4>> tiles;
     auto add_tile = [&](int bx, int by, int bz, int bt) {
         const int b4[4] = {bx, by, bz, bt};
@@ -607,76 +614,143 @@ mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
                     const long vol = long(bx) * by * bz * bt;
                     if (vol >= 384 && vol <= 6912 && (by < g.Y || bt > 1)) add_tile(bx, by, bz, bt);
                 }
-    const size_t canon = size_t(g.Vh) * 24 * sizeof(double);
+    const size_t hb = half_field_bytes(p, g.Vh);
+    // scratch: nrhs even inputs (packed from the canonical pattern), outputs
+    // of the operator and of its adjoint (the input is never overwritten, so
+    // repeated applications do not grow it), odd temporaries and, for the
+    // symmetric adjoint, one more even set
+    char* a = static_cast<char*>(buf(c, "tune_a", hb * nrhs, &s));
+    char* b = a ? static_cast<char*>(buf(c, "tune_b", hb * nrhs, &s)) : nullptr;
+    char* d = (b && with_dag) ? static_cast<char*>(buf(c, "tune_d", hb * nrhs, &s)) : b;
+    char* t = d ? static_cast<char*>(buf(c, "tune_t", hb * nrhs, &s)) : nullptr;
+    char* t2 = (t && form == 1 && with_dag) ? static_cast<char*>(buf(c, "tune_t2", hb * nrhs, &s)) : t;
+    RhsCoef* cf = t2 ? static_cast<RhsCoef*>(buf(c, "tune_coef", 2 * sizeof(RhsCoef) * nrhs, &s)) : nullptr;
+    if (!cf) return s;
+    std::vector<RhsCoef> hc(2 * size_t(nrhs));
+    for (int k = 0; k < nrhs; ++k) {
+        hc[k] = make_coef(c->act, c->act.mq);
+        hc[nrhs + k] = make_coef_sym(c->act, c->act.mq);
+    }
+    if ((s = hip_check(c, hipMemcpyAsync(cf, hc.data(), hc.size() * sizeof(RhsCoef), hipMemcpyHostToDevice, st),
+                       "tune coefficients")))
+        return s;
+    for (int k = 0; k < nrhs; ++k) launch_pack_parity(g, p, 0, 0, cin, a + hb * k, st);
+    auto apply = [&]() {
+        schur_launch(g, c->gs, p, form, false, a, b, t, t2, hb, nrhs, cf, cf + nrhs, nullptr, nullptr, st);
+        if (with_dag)
+            schur_launch(g, c->gs, p, form, true, b, d, t, t2, hb, nrhs, cf, cf + nrhs, nullptr, nullptr, st);
+    };
+    auto timed = [&](mdwf_launch_tune tn) -> mdwf_launch_tune {
+        set_tune(g, p, tn);
+        const int warm = 2, reps = 5;
+        for (int r = 0; r < warm; ++r) apply();
+        if ((s = hip_check(c, hipGetLastError(), "autotune launch"))) return tn;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps; ++r) apply();
+        (void)hipEventRecord(e1, st);
+        if ((s = hip_check(c, hipEventSynchronize(e1), "autotune"))) return tn;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        tn.us = 1e3 * ms / reps;
+        return tn;
+    };
+    mdwf_launch_tune best{};
+    for (int k = 0; k < 4; ++k) best.tile[k] = g.trav[p].b[k];
+    best.xcd_remap = 1;
+    best.rhs_group = g.rhs_group[p];
+    best.us = 1e30;
+    for (const auto& tl : tiles) {
+        mdwf_launch_tune tn = best;
+        for (int k = 0; k < 4; ++k) tn.tile[k] = tl[k];
+        tn = timed(tn);
+        if (s) return s;
+        if (tn.us < best.us) best = tn;
+    }
+    for (int lm : {1, 2}) {
+        if (lm == 1 && 64 / g.L5 > 8) continue;
+        if (lm == 2 && (p == P64 || g.L5 < (p == P32 ? 4 : 2))) continue;
+        mdwf_launch_tune tn = best;
+        tn.link_mode = lm;
+        tn = timed(tn);
+        if (s) return s;
+        if (tn.us < best.us) best = tn;
+    }
+    for (int v = 0; v < 2; ++v) {
+        mdwf_launch_tune tn = best;
+        if (v == 0) tn.nt_store = 1 - tn.nt_store;
+        else tn.xcd_remap = 1 - tn.xcd_remap;
+        tn = timed(tn);
+        if (s) return s;
+        if (tn.us < best.us) best = tn;
+    }
+    if (nrhs > 1)
+        for (int rg : {0, 1, 2, 3, 4, 6}) {
+            if (rg >= nrhs || rg == best.rhs_group) continue;
+            mdwf_launch_tune tn = best;
+            tn.rhs_group = rg;
+            tn = timed(tn);
+            if (s) return s;
+            if (tn.us < best.us) best = tn;
+        }
+    set_tune(g, p, best);
+    c->tuned_us[p] = best.us;
+    if (out) *out = best;
+    return MDWF_OK;
+}
+
+// shared set-up of both tuning entry points: a canonical scratch field with
+// a finite pattern (timing does not depend on the values) and two events
+template <typename F>
+mdwf_status with_tune_scratch(mdwf_ctx* c, F body) {
+    mdwf_status s = MDWF_OK;
+    const size_t canon = size_t(c->geo.Vh) * 24 * sizeof(double);
     void* cin = buf(c, "tune_canon", canon, &s);
     if (!cin) return s;
-    // any finite, normal pattern: timing does not depend on the values
-    if ((s = hip_check(c, hipMemsetAsync(cin, 0x3f, canon, st), "memset"))) return s;
+    if ((s = hip_check(c, hipMemsetAsync(cin, 0x3f, canon, c->stream), "memset"))) return s;
     hipEvent_t e0, e1;
     if ((s = hip_check(c, hipEventCreate(&e0), "event"))) return s;
-    if ((s = hip_check(c, hipEventCreate(&e1), "event"))) return s;
-    for (int pi = 0; pi < 3 && !s; ++pi) {
-        const Prec p = Prec(pi);
-        const size_t hb = half_field_bytes(p, g.Vh);
-        void* a = buf(c, "tune_a", 2 * half_field_bytes(P64, g.Vh), &s);
-        void* b = a ? buf(c, "tune_b", 2 * half_field_bytes(P64, g.Vh), &s) : nullptr;
-        if (!a || !b) break;
-        launch_pack_parity(g, p, 0, 0, static_cast<const double*>(cin), a, st);
-        // time one Schur application (2 warm-up, mean of 5) with shape t
-        auto timed = [&](mdwf_launch_tune t) -> mdwf_launch_tune {
-            set_tune(g, p, t);
-            const int warm = 2, reps = 5;
-            for (int r = 0; r < warm && !s; ++r)
-                s = apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st);
-            if (s) return t;
-            (void)hipEventRecord(e0, st);
-            for (int r = 0; r < reps; ++r) apply_native(c, MDWF_OP_SCHUR, p, a, b, hb, 1, c->d_coef1, nullptr, st);
-            (void)hipEventRecord(e1, st);
-            if ((s = hip_check(c, hipEventSynchronize(e1), "autotune"))) return t;
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            t.us = 1e3 * ms / reps;
-            return t;
-        };
-        mdwf_launch_tune best{};
-        for (int k = 0; k < 4; ++k) best.tile[k] = g.trav[p].b[k];
-        best.xcd_remap = 1;
-        best.rhs_group = g.rhs_group[p];
-        best.us = 1e30;
-        // coordinate descent: traversal tile, then link mode, then stores and
-        // workgroup numbering
-        for (const auto& tl : tiles) {
-            mdwf_launch_tune t = best;
-            for (int k = 0; k < 4; ++k) t.tile[k] = tl[k];
-            t = timed(t);
-            if (s) break;
-            if (t.us < best.us) best = t;
-        }
-        std::vector<int> modes{1, 2};
-        for (int lm : modes) {
-            if (s) break;
-            if (lm == 1 && 64 / g.L5 > 8) continue;
-            if (lm == 2 && (p == P64 || g.L5 < (p == P32 ? 4 : 2))) continue;
-            mdwf_launch_tune t = best;
-            t.link_mode = lm;
-            t = timed(t);
-            if (!s && t.us < best.us) best = t;
-        }
-        for (int v = 0; v < 2 && !s; ++v) {
-            mdwf_launch_tune t = best;
-            if (v == 0) t.nt_store = 1 - t.nt_store;
-            else t.xcd_remap = 1 - t.xcd_remap;
-            t = timed(t);
-            if (!s && t.us < best.us) best = t;
-        }
-        if (s) break;
-        set_tune(g, p, best);
-        c->tuned_us[pi] = best.us;
-        if (out) out[pi] = best;
+    if ((s = hip_check(c, hipEventCreate(&e1), "event"))) {
+        (void)hipEventDestroy(e0);
+        return s;
     }
+    s = body(static_cast<const double*>(cin), e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdwf_status mdwf_autotune(mdwf_ctx* c, mdwf_launch_tune* out) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    return with_tune_scratch(c, [&](const double* cin, hipEvent_t e0, hipEvent_t e1) {
+        for (int pi = 0; pi < 3; ++pi) {
+            const mdwf_status r = tune_precision(c, Prec(pi), 0, 1, false, cin, e0, e1, out ? out + pi : nullptr);
+            if (r) return r;
+        }
+        return MDWF_OK;
+    });
+}
+
+mdwf_status mdwf_autotune_solve(mdwf_ctx* c, const mdwf_solver_opts* opts, int nrhs, mdwf_launch_tune* out) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    mdwf_solver_opts o;
+    mdwf_default_opts(&o);
+    if (opts) o = *opts;
+    if (nrhs < 1 || !valid_prec(o.inner) || o.schur_form < 0 || o.schur_form > 2)
+        return fail(c, MDWF_ERR_ARG, "need nrhs >= 1, a valid inner precision and schur_form 0-2");
+    for (int pi = 0; pi < 3 && out; ++pi) (void)mdwf_get_tune(c, mdwf_prec(pi), out + pi);
+    return with_tune_scratch(c, [&](const double* cin, hipEvent_t e0, hipEvent_t e1) {
+        const Prec pi = Prec(o.inner);
+        mdwf_status r = tune_precision(c, pi, o.schur_form, nrhs, true, cin, e0, e1, out ? out + pi : nullptr);
+        if (!r && pi != P64)   // reliable updates: the FP64 operator, one RHS at a time
+            r = tune_precision(c, P64, o.schur_form, 1, false, cin, e0, e1, out ? out + P64 : nullptr);
+        return r;
+    });
 }
 
 mdwf_status mdwf_solve_dev(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, const double* mq,

@@ -125,6 +125,7 @@ def _load():
         "mdwf_default_opts": ([C.POINTER(mdwf_solver_opts)], None),
         "mdwf_op_model": ([vp, ip, ip, C.POINTER(dp), C.POINTER(dp)], ip),
         "mdwf_autotune": ([vp, C.POINTER(mdwf_launch_tune)], ip),
+        "mdwf_autotune_solve": ([vp, C.POINTER(mdwf_solver_opts), ip, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_get_tune": ([vp, ip, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_server_create": ([ip, C.c_size_t, ip, C.POINTER(vp)], ip),
         "mdwf_server_destroy": ([vp], None),
@@ -271,6 +272,15 @@ def mdwf_autotune(ctx):
     return [o.as_dict() for o in out]
 
 
+def mdwf_autotune_solve(ctx, nrhs, opts=None):
+    """Autotune for one solve shape (inner precision and Schur form of opts,
+    nrhs RHS per launch); returns 3 dicts."""
+    out = (mdwf_launch_tune * 3)()
+    o = _opts(opts)
+    _check(ctx, lib.mdwf_autotune_solve(ctx, C.byref(o), int(nrhs), out))
+    return [t.as_dict() for t in out]
+
+
 def mdwf_get_tune(ctx, prec):
     t = mdwf_launch_tune()
     _check(ctx, lib.mdwf_get_tune(ctx, int(prec), C.byref(t)))
@@ -349,6 +359,6 @@ def exported_symbols():
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
             "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
-            "mdwf_autotune", "mdwf_get_tune", "mdwf_server_create", "mdwf_server_destroy",
+            "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_server_create", "mdwf_server_destroy",
             "mdwf_server_last_error", "mdwf_server_add_field", "mdwf_server_submit", "mdwf_server_wait",
             "mdwf_server_stats"]

@@ -202,6 +202,39 @@ def test_autotune_keeps_parity(M):
         M.mdwf_destroy(ctx)
 
 
+@pytest.mark.parametrize("form", [0, 1, 2], ids=["asym", "sym", "rp"])
+def test_solve_shaped_autotune_keeps_parity_and_solves(M, form):
+    """mdwf_autotune_solve tunes the FP16 CG operator of the form with 5 RHS
+    per launch (RHS grouping among the candidates) and FP64 with one; every
+    operator still matches the oracle and a 5-RHS solve still converges."""
+    dims, L5 = (6, 4, 2, 6), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 53)
+    psi = I.gaussian_source(dims, L5, 54)
+    ctx = make_ctx(M, act, U)
+    try:
+        before = M.mdwf_get_tune(ctx, 1)
+        opts = dict(inner=2, schur_form=form)
+        tunes = M.mdwf_autotune_solve(ctx, 5, opts)
+        assert len(tunes) == 3 and tunes[2]["us"] > 0 and tunes[0]["us"] > 0
+        assert M.mdwf_get_tune(ctx, 2)["tile"] == tunes[2]["tile"]
+        assert M.mdwf_get_tune(ctx, 2)["rhs_group"] == tunes[2]["rhs_group"]
+        assert M.mdwf_get_tune(ctx, 1) == before     # FP32 is not used by this solve
+        for prec in (0, 2):
+            for op in ALL_OPS:
+                assert rel(gpu_op(M, ctx, op, prec, act, psi), oracle_op(M, op, act, U, psi)) <= TOL[prec]
+        bs = [I.gaussian_source(dims, L5, 60 + k) for k in range(5)]
+        xs = [np.zeros_like(b) for b in bs]
+        st, info = M.mdwf_solve(ctx, bs, xs, opts=opts)
+        assert st == M.MDWF_OK
+        for b, x in zip(bs, xs):
+            assert oracle.true_residual(act, U, b, x) <= 1e-10
+        with pytest.raises(M.MdwfError):
+            M.mdwf_autotune_solve(ctx, 0, opts)
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 def test_operator_parity_other_action(M):
     """Shamir-like and heavy-mass corner: b5 = 1, c5 = 0, m_q = 1, M5 = 1.8."""
     dims, L5 = (4, 4, 2, 2), 6
