@@ -417,6 +417,57 @@ def test_schur_forms_with_graph_and_shamir_action(M):
         M.mdwf_destroy(ctx)
 
 
+def _free_d5(p, L5, M5, b5, c5, mq):
+    """D5(p) = D_W(p)(b5 + c5 C) + 1 - C on C^{4 L5} for unit links, with
+    D_W(p) = 4 - M5 - sum cos p_mu + i sum gamma_mu sin p_mu (colour trivial)."""
+    import kron_ref as KR
+    g = KR.gammas()
+    dw = (4 - M5 - np.cos(p).sum()) * np.eye(4) + 1j * sum(g[mu] * np.sin(p[mu]) for mu in range(4))
+    Sp, Sm = KR.c5_matrix(L5, mq)
+    Cm = np.kron(Sp, KR.PPLUS) + np.kron(Sm, KR.PMINUS)
+    Id = np.eye(4 * L5)
+    return np.kron(np.eye(L5), dw) @ (b5 * Id + c5 * Cm) + Id - Cm
+
+
+@pytest.mark.parametrize("form", [0, 1, 2], ids=["asym", "sym", "rp"])
+def test_free_field_plane_wave_solve_closed_form(M, form):
+    """Unit links, b = e^{ipx} chi on 8^3 x 16, L5 = 8, m = 0.0102, FP16
+    inner: the solution equals e^{ipx} D5(p)^-1 chi to within the condition
+    number of D5 (exact over every momentum of the lattice) times 1e-10."""
+    dims, L5 = (8, 8, 8, 16), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.0102)
+    X, Y, Z, T = dims
+    n = (1, 3, 0, 2)
+    p = np.array([2 * np.pi * n[0] / X, 2 * np.pi * n[1] / Y, 2 * np.pi * n[2] / Z, (2 * n[3] + 1) * np.pi / T])
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    ph = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    rng = np.random.default_rng(17)
+    chi = rng.standard_normal((L5, 4, 3)) + 1j * rng.standard_normal((L5, 4, 3))
+    b = np.ascontiguousarray(ph[None, ..., None, None] * chi[:, None, None, None, None])
+    Dp = _free_d5(p, L5, 1.3, 1.5, 0.5, 0.0102)
+    xc = np.linalg.solve(Dp, chi.reshape(L5 * 4, 3)).reshape(L5, 4, 3)
+    ref = ph[None, ..., None, None] * xc[:, None, None, None, None]
+    # condition number of D5 on this lattice: extreme singular values over all momenta
+    smax, smin = 0.0, np.inf
+    for nt in range(T):
+        for nz in range(Z):
+            for ny in range(Y):
+                ps = np.stack(np.meshgrid(2 * np.pi * np.arange(X) / X, [2 * np.pi * ny / Y], [2 * np.pi * nz / Z],
+                                          [(2 * nt + 1) * np.pi / T], indexing="ij"), -1).reshape(-1, 4)
+                sv = np.linalg.svd(np.array([_free_d5(q, L5, 1.3, 1.5, 0.5, 0.0102) for q in ps]), compute_uv=False)
+                smax, smin = max(smax, sv.max()), min(smin, sv.min())
+    kappa = smax / smin
+    ctx = make_ctx(M, act, I.unit_links(dims))
+    try:
+        xg = np.zeros_like(b)
+        st, info = M.mdwf_solve(ctx, [b], [xg], opts=dict(inner=2, schur_form=form))
+        assert st == M.MDWF_OK, info
+        assert oracle.true_residual(act, I.unit_links(dims), b, xg) <= 1e-10
+        assert rel(xg, ref) <= kappa * 1e-10, (rel(xg, ref), kappa)
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 def test_solve_graph_replay_matches_eager(M, cfg1):
     act, U, b, _ = cfg1
     ctx = make_ctx(M, act, U)
