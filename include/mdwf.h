@@ -132,6 +132,9 @@ typedef struct {
                             preconditioning by B: no B before the first hop,
                             none after the adjoint's second).  The stop is
                             the same true residual ||b - D5 x|| / ||b||     */
+    double max_seconds;  /* > 0: a time limit for the call; once it has run
+                            this long every unconverged RHS stops as at
+                            max_iter (ERR_NOCONV, best x written); 0 = none */
 } mdwf_solver_opts;
 
 typedef struct {
@@ -208,7 +211,7 @@ mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, 
                            void *stream);
 
 /* Fill opts with defaults: tol 1e-10, max_iter 100000, inner F64, delta 0.1,
- * check_every 1, use_graph 0, profile_iters 0, schur_form 0. */
+ * check_every 1, use_graph 0, profile_iters 0, schur_form 0, max_seconds 0. */
 void mdwf_default_opts(mdwf_solver_opts *opts);
 
 /* Launch shape of the hop kernels for one storage precision. */
@@ -285,7 +288,8 @@ mdwf_status mdwf_server_add_field(mdwf_server *srv, const mdwf_geometry *geom, c
 
 /* Queue a solve of nrhs RHS on field_id with action act (mq: per-RHS masses
  * or NULL for act->mq; opts NULL = defaults; use_graph and profile_iters are
- * ignored).  Returns at once with *req_id.  A request whose footprint exceeds
+ * ignored; max_seconds > 0 is the request's time limit from the moment it
+ * starts running, across its sub-batches).  Returns at once with *req_id.  A request whose footprint exceeds
  * the budget is split into sub-batches of the most RHS that fit, solved one
  * after another (bitwise the same results).  ERR_ARG on bad arguments,
  * ERR_OOM if not even one RHS fits the budget. */

@@ -427,6 +427,7 @@ void mdwf_default_opts(mdwf_solver_opts* o) {
     o->use_graph = 0;
     o->profile_iters = 0;
     o->schur_form = 0;
+    o->max_seconds = 0.0;
 }
 
 static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_device) {

@@ -126,8 +126,10 @@ void worker_loop(mdwf_server* s) {
         for (int k0 = 0; st == MDWF_OK || st == MDWF_ERR_NOCONV || st == MDWF_ERR_NUMERIC; k0 += r->batch) {
             if (k0 >= n) break;
             const int k = std::min(r->batch, n - k0);
-            const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0,
-                                              &r->opts, r->info.data() + k0);
+            mdwf_solver_opts ok = r->opts;   // the time limit covers the whole request
+            if (r->opts.max_seconds > 0.0) ok.max_seconds = std::max(1e-9, r->opts.max_seconds - (wall() - r->t_start));
+            const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0, &ok,
+                                              r->info.data() + k0);
             if (sk == MDWF_OK) continue;
             const bool hard = sk != MDWF_ERR_NOCONV && sk != MDWF_ERR_NUMERIC;
             if (st == MDWF_OK || hard) {

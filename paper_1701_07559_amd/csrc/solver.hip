@@ -195,8 +195,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     mdwf_default_opts(&o);
     if (o_in) o = *o_in;
     if (!(o.tol > 0.0) || o.max_iter < 1 || (o.inner != MDWF_F64 && o.inner != MDWF_F32 && o.inner != MDWF_F16) ||
-        !(o.delta > 0.0 && o.delta < 1.0) || o.schur_form < 0 || o.schur_form > 2)
-        return fail(c, MDWF_ERR_ARG, "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1, schur_form 0-2)");
+        !(o.delta > 0.0 && o.delta < 1.0) || o.schur_form < 0 || o.schur_form > 2 || !(o.max_seconds >= 0.0))
+        return fail(c, MDWF_ERR_ARG,
+                    "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1, schur_form 0-2, max_seconds >= 0)");
     if (o.check_every < 1) o.check_every = 1;
     std::vector<double> masses(nrhs, c->act.mq);
     if (mq)
@@ -248,8 +249,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             mdwf_status worst = MDWF_OK;
             for (int k0 = 0; k0 < n; k0 += nb) {
                 const int nk = std::min(nb, n - k0);
+                mdwf_solver_opts ok = o;   // the time limit covers the whole call
+                if (o.max_seconds > 0.0) ok.max_seconds = std::max(1e-9, o.max_seconds - (now() - t_start));
                 const mdwf_status r = mdwf_solve_impl(c, nk, b_in + k0, x_out + k0, host_io, mq ? mq + k0 : nullptr,
-                                                      &o, info ? info + k0 : nullptr, st);
+                                                      &ok, info ? info + k0 : nullptr, st);
                 if (r != MDWF_OK && r != MDWF_ERR_NOCONV && r != MDWF_ERR_NUMERIC) return r;
                 if (r != MDWF_OK && worst == MDWF_OK) worst = r;
             }
@@ -488,6 +491,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         pend_slot = slot;
         std::vector<int> upd(n, 0), rp(n, 0);
         bool any = false;
+        // past max_seconds every active RHS stops as if at max_iter
+        const bool late = o.max_seconds > 0.0 && now() - t_start > o.max_seconds;
+        auto limit = [&](int k) { return iters[k] >= o.max_iter || late; };
         for (int k = 0; k < n; ++k) {
             if (!active[k] || skip[k]) {
                 skip[k] = 0;
@@ -500,7 +506,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
                 continue;
             }
             const double rn = std::sqrt(h[k].rr);
-            if (rn <= tgt * bnorm[k] || iters[k] >= o.max_iter) { upd[k] = 1; any = true; }
+            if (rn <= tgt * bnorm[k] || limit(k)) { upd[k] = 1; any = true; }
             else if (S.mixed && rn < o.delta * rmax[k]) { upd[k] = 1; any = true; }
         }
         if (!any) continue;
@@ -514,11 +520,11 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         for (int k = 0; k < n; ++k) {
             if (!upd[k]) continue;
             if (S.mixed) ++updates[k];
-            if (std::sqrt(rr[k]) <= tgt * bnorm[k] || iters[k] >= o.max_iter || stopped[k] == 2) {
+            if (std::sqrt(rr[k]) <= tgt * bnorm[k] || limit(k) || stopped[k] == 2) {
                 const double tr = verify(k, false);
                 true_res[k] = tr;
                 if (tr <= o.tol) { done[k] = 1; active[k] = 0; any_stop = true; }
-                else if (iters[k] >= o.max_iter || stopped[k] == 2) {
+                else if (limit(k) || stopped[k] == 2) {
                     active[k] = 0;
                     any_stop = true;
                     if (!stopped[k]) stopped[k] = 1;

@@ -53,7 +53,7 @@ def test_null_context_calls_return_arg_errors():
     assert mdwf.lib.mdwf_autotune_solve(None, None, 1, None) == mdwf.MDWF_ERR_ARG
     o = mdwf.mdwf_default_opts()
     assert o.tol == 1e-10 and o.inner == mdwf.MDWF_F64 and abs(o.delta - 0.1) < 1e-15
-    assert o.schur_form == 0 and o.profile_iters == 0 and o.use_graph == 0
+    assert o.schur_form == 0 and o.profile_iters == 0 and o.use_graph == 0 and o.max_seconds == 0.0
     mdwf.lib.mdwf_destroy(None)   # ignored
 
 

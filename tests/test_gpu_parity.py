@@ -610,6 +610,46 @@ def test_solve_dev_with_torch_buffers(M, cfg1):
         M.mdwf_destroy(ctx)
 
 
+def test_solve_is_deterministic(M, cfg1):
+    """The same solve twice (and the same operator twice) gives bitwise the
+    same result: every reduction runs in a fixed order."""
+    act, U, b, _ = cfg1
+    ctx = make_ctx(M, act, U)
+    try:
+        xs = []
+        for _ in range(2):
+            x = np.zeros_like(b)
+            st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(inner=2, schur_form=2))
+            assert st == M.MDWF_OK
+            xs.append((x, info[0]["iters"], info[0]["true_resid"]))
+        assert np.array_equal(xs[0][0], xs[1][0]) and xs[0][1:] == xs[1][1:]
+        for prec in (0, 1, 2):
+            outs = [gpu_op(M, ctx, M.MDWF_OP_SCHUR_RP, prec, act, b) for _ in range(2)]
+            assert np.array_equal(outs[0], outs[1])
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_solve_time_limit(M, cfg1):
+    """max_seconds stops an unconverged solve as max_iter does: ERR_NOCONV,
+    the best x written, its true residual reported."""
+    act, U, b, _ = cfg1
+    ctx = make_ctx(M, act, U)
+    try:
+        x = np.zeros_like(b)
+        st, info = M.mdwf_solve(ctx, [b, b], [x, np.zeros_like(b)], opts=dict(inner=2, max_seconds=1e-4))
+        assert st == M.MDWF_ERR_NOCONV
+        assert info[0]["true_resid"] > 1e-10 and np.all(np.isfinite(x)) and np.any(x != 0)
+        assert abs(oracle.true_residual(act, U, b, x) - info[0]["true_resid"]) <= 1e-9
+        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(inner=2, max_seconds=60.0))
+        assert st == M.MDWF_OK and info[0]["true_resid"] <= 1e-10
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_solve(ctx, [b], [x], opts=dict(max_seconds=-1.0))
+        assert e.value.status == M.MDWF_ERR_ARG
+    finally:
+        M.mdwf_destroy(ctx)
+
+
 def test_solver_failure_paths(M, cfg1):
     act, U, b, _ = cfg1
     ctx = M.mdwf_create(act.dims)

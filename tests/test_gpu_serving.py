@@ -114,6 +114,28 @@ def test_server_rejects_bad_requests(M):
         tiny.close()
 
 
+def test_request_time_limit(M):
+    """A request with a time limit far below its solve time stops with
+    ERR_NOCONV and its best x; a request beside it is unaffected."""
+    dims, L5 = (4, 4, 4, 8), 8
+    U = I.random_links(dims, 0.3, 66)
+    b = I.gaussian_source(dims, L5, 67)
+    srv = M.Server(mem_budget=0, max_active=2)
+    try:
+        fid = srv.add_field(dims, U)
+        xs = [np.zeros_like(b), np.zeros_like(b)]
+        r1 = srv.submit(fid, 1.3, 1.5, 0.5, 0.02, L5, [b], [xs[0]], opts=dict(inner=2, max_seconds=1e-4))
+        r2 = srv.submit(fid, 1.3, 1.5, 0.5, 0.02, L5, [b], [xs[1]], opts=dict(inner=2))
+        st1, info1, _ = srv.wait(r1)
+        st2, info2, _ = srv.wait(r2)
+        assert st1 == M.MDWF_ERR_NOCONV and info1[0]["true_resid"] > 1e-10 and np.all(np.isfinite(xs[0]))
+        assert st2 == M.MDWF_OK and info2[0]["true_resid"] <= 1e-10
+    finally:
+        srv.close()
+    ref, _ = alone(M, dims, U, L5, [0.02], 2, [b])
+    assert np.array_equal(xs[1], ref[0])
+
+
 def test_request_larger_than_the_budget_runs_in_sub_batches(M):
     # 24 RHS need more than the budget; the server splits them into
     # sub-batches that fit, and the results equal one solve of all 24
