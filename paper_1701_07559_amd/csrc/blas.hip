@@ -349,6 +349,113 @@ void launch_cg_xp(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* p, c
     }
 }
 
+// even iteration of the two-iteration update: pn = s + beta p
+template <Prec PI>
+__global__ void __launch_bounds__(kBlas) k_cg_p(const Geo g, void* pn, const void* p, const void* s, size_t si,
+                                                const int* active, const CGScal* sc) {
+    const int rhs = blockIdx.y;
+    if (active && !active[rhs]) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.Vh) return;
+    const double beta = sc[rhs].beta;
+    cx<double> vp[12], vs[12];
+    Ld<PI>::load(at_rhs(p, si, rhs), g.Vh, j, vp);
+    Ld<PI>::load(at_rhs(s, si, rhs), g.Vh, j, vs);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vp[c] = vs[c] + beta * vp[c];
+    Ld<PI>::store(at_rhs(pn, si, rhs), g.Vh, j, vp);
+}
+
+// odd iteration: x += alpha_prev pp + alpha p, then pp = s + beta p
+template <Prec PX, Prec PI>
+__global__ void __launch_bounds__(kBlas) k_cg_xp2(const Geo g, void* x, size_t sx, void* pp, const void* p,
+                                                  const void* s, size_t si, const int* active, const CGScal* sc) {
+    const int rhs = blockIdx.y;
+    if (active && !active[rhs]) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.Vh) return;
+    const double a0 = sc[rhs].alpha_prev, a1 = sc[rhs].alpha, beta = sc[rhs].beta;
+    cx<double> vx[12], vq[12], vp[12], vs[12];
+    Ld<PX>::load(at_rhs(x, sx, rhs), g.Vh, j, vx);
+    Ld<PI>::load(at_rhs(pp, si, rhs), g.Vh, j, vq);
+    Ld<PI>::load(at_rhs(p, si, rhs), g.Vh, j, vp);
+    Ld<PI>::load(at_rhs(s, si, rhs), g.Vh, j, vs);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        vx[c] = vx[c] + a0 * vq[c] + a1 * vp[c];
+        vq[c] = vs[c] + beta * vp[c];
+    }
+    Ld<PX>::store(at_rhs(x, sx, rhs), g.Vh, j, vx);
+    Ld<PI>::store(at_rhs(pp, si, rhs), g.Vh, j, vq);
+}
+
+// x += alpha_prev p
+template <Prec PX, Prec PI>
+__global__ void __launch_bounds__(kBlas) k_cg_xpend(const Geo g, void* x, size_t sx, const void* p, size_t si,
+                                                    const int* active, const CGScal* sc) {
+    const int rhs = blockIdx.y;
+    if (active && !active[rhs]) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.Vh) return;
+    const double a0 = sc[rhs].alpha_prev;
+    cx<double> vx[12], vp[12];
+    Ld<PX>::load(at_rhs(x, sx, rhs), g.Vh, j, vx);
+    Ld<PI>::load(at_rhs(p, si, rhs), g.Vh, j, vp);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vx[c] = vx[c] + a0 * vp[c];
+    Ld<PX>::store(at_rhs(x, sx, rhs), g.Vh, j, vx);
+}
+
+void launch_cg_p(const Geo& g, Prec pi, void* pn, const void* p, const void* s, size_t si, int nrhs,
+                 const int* active, const CGScal* sc, hipStream_t st) {
+    const dim3 grid(blas_blocks_per_rhs(g), nrhs), blk(kBlas);
+    switch (pi) {
+        case P64: hipLaunchKernelGGL(k_cg_p<P64>, grid, blk, 0, st, g, pn, p, s, si, active, sc); break;
+        case P32: hipLaunchKernelGGL(k_cg_p<P32>, grid, blk, 0, st, g, pn, p, s, si, active, sc); break;
+        case P16: hipLaunchKernelGGL(k_cg_p<P16>, grid, blk, 0, st, g, pn, p, s, si, active, sc); break;
+    }
+}
+
+template <Prec PX>
+static void cg_xp2_px(const Geo& g, Prec pi, void* x, size_t sx, void* pp, const void* p, const void* s, size_t si,
+                      int nrhs, const int* active, const CGScal* sc, hipStream_t st) {
+    const dim3 grid(blas_blocks_per_rhs(g), nrhs), blk(kBlas);
+    switch (pi) {
+        case P64: hipLaunchKernelGGL((k_cg_xp2<PX, P64>), grid, blk, 0, st, g, x, sx, pp, p, s, si, active, sc); break;
+        case P32: hipLaunchKernelGGL((k_cg_xp2<PX, P32>), grid, blk, 0, st, g, x, sx, pp, p, s, si, active, sc); break;
+        case P16: hipLaunchKernelGGL((k_cg_xp2<PX, P16>), grid, blk, 0, st, g, x, sx, pp, p, s, si, active, sc); break;
+    }
+}
+
+void launch_cg_xp2(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* pp, const void* p, const void* s,
+                   size_t si, int nrhs, const int* active, const CGScal* sc, hipStream_t st) {
+    switch (px) {
+        case P64: cg_xp2_px<P64>(g, pi, x, sx, pp, p, s, si, nrhs, active, sc, st); break;
+        case P32: cg_xp2_px<P32>(g, pi, x, sx, pp, p, s, si, nrhs, active, sc, st); break;
+        case P16: cg_xp2_px<P16>(g, pi, x, sx, pp, p, s, si, nrhs, active, sc, st); break;
+    }
+}
+
+template <Prec PX>
+static void cg_xpend_px(const Geo& g, Prec pi, void* x, size_t sx, const void* p, size_t si, int nrhs,
+                        const int* active, const CGScal* sc, hipStream_t st) {
+    const dim3 grid(blas_blocks_per_rhs(g), nrhs), blk(kBlas);
+    switch (pi) {
+        case P64: hipLaunchKernelGGL((k_cg_xpend<PX, P64>), grid, blk, 0, st, g, x, sx, p, si, active, sc); break;
+        case P32: hipLaunchKernelGGL((k_cg_xpend<PX, P32>), grid, blk, 0, st, g, x, sx, p, si, active, sc); break;
+        case P16: hipLaunchKernelGGL((k_cg_xpend<PX, P16>), grid, blk, 0, st, g, x, sx, p, si, active, sc); break;
+    }
+}
+
+void launch_cg_xpend(const Geo& g, Prec px, Prec pi, void* x, size_t sx, const void* p, size_t si, int nrhs,
+                     const int* active, const CGScal* sc, hipStream_t st) {
+    switch (px) {
+        case P64: cg_xpend_px<P64>(g, pi, x, sx, p, si, nrhs, active, sc, st); break;
+        case P32: cg_xpend_px<P32>(g, pi, x, sx, p, si, nrhs, active, sc, st); break;
+        case P16: cg_xpend_px<P16>(g, pi, x, sx, p, si, nrhs, active, sc, st); break;
+    }
+}
+
 // x_hi += x_lo ; x_lo = 0
 template <Prec PX>
 __global__ void __launch_bounds__(kBlas) k_flush(const Geo g, void* xhi, size_t shi, void* xlo, size_t slo,
@@ -416,6 +523,15 @@ __global__ void __launch_bounds__(256) k_scalars(int op, const double* partials,
         case SC_RR:
             c.rr = tot;
             if (!ok) c.bad = 1;
+            break;
+        case SC_ALPHA_KEEP:
+            c.delta = tot;
+            if (ok && tot > 0.0) c.alpha = c.gamma / tot;
+            else { c.alpha = 0.0; c.bad = 1; }
+            c.alpha_prev = c.alpha;
+            break;
+        case SC_CLEAR_PREV:
+            c.alpha_prev = 0.0;
             break;
         default: break;
     }

@@ -404,6 +404,16 @@ void launch_cg_r(const Geo& g, Prec pi, void* r, const void* q, size_t si, int n
 // x(px) += alpha[r] * p(pi); then p = s + beta[r] p
 void launch_cg_xp(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
                   const int* active, const CGScal* sc, hipStream_t st);
+// Two-iteration solution update.  Even iteration: pn = s + beta p (x waits).
+// Odd iteration: x += alpha_prev pp + alpha p, then pp = s + beta p (pp holds
+// the even iteration's direction on entry, the next direction on exit).
+void launch_cg_p(const Geo& g, Prec pi, void* pn, const void* p, const void* s, size_t si, int nrhs,
+                 const int* active, const CGScal* sc, hipStream_t st);
+void launch_cg_xp2(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* pp, const void* p, const void* s,
+                   size_t si, int nrhs, const int* active, const CGScal* sc, hipStream_t st);
+// x += alpha_prev p: the pending half of a two-iteration update
+void launch_cg_xpend(const Geo& g, Prec px, Prec pi, void* x, size_t sx, const void* p, size_t si, int nrhs,
+                     const int* active, const CGScal* sc, hipStream_t st);
 // x_hi(P64) += x_lo(px); x_lo = 0
 void launch_flush(const Geo& g, Prec px, void* xhi, size_t shi, void* xlo, size_t slo, int nrhs,
                   const int* active, hipStream_t st);
@@ -417,8 +427,11 @@ struct CGScal {
     double rr;      // ||r||^2 (iterated)
     int bad;        // NaN/Inf or breakdown seen
     int pad;
+    double alpha_prev;   // alpha of the last even iteration, its x update pending
 };
-enum ScalOp { SC_ALPHA = 0, SC_BETA, SC_SET_GAMMA, SC_RR, SC_SUM };
+// SC_ALPHA_KEEP: SC_ALPHA and alpha_prev = alpha (even iterations);
+// SC_CLEAR_PREV: alpha_prev = 0 (its update applied)
+enum ScalOp { SC_ALPHA = 0, SC_BETA, SC_SET_GAMMA, SC_RR, SC_SUM, SC_ALPHA_KEEP, SC_CLEAR_PREV };
 // Reduce partials per RHS in a fixed order and update the scalars.
 void launch_scalars(ScalOp op, const double* partials, int nblk, int nrhs, const int* active, CGScal* sc,
                     double* out_sum, hipStream_t st);

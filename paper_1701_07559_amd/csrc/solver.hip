@@ -6,8 +6,12 @@
 //   CG on the normal equations of S x_e = b'_e in least-squares form:
 //     q = S p, alpha = |s|^2/|q|^2, x += alpha p, r -= alpha q,
 //     s = S^+ r, beta = |s_new|^2/|s|^2, p = s + beta p
-// (x += alpha p runs in the same pass as the update of p, which reads p
-// anyway; alpha and the old p are what they were right after q = S p).
+// The solution update is applied every second iteration, in the pass that
+// writes the next direction: p alternates between two buffers, an even
+// iteration writes p_next = s + beta p beside p (x waits), the odd one adds
+// alpha_prev p_prev + alpha p to x and writes its p_next over p_prev.  x is
+// read and written once per two iterations.  A reliable update first adds
+// a pending alpha_prev p_prev.
 //   x_o = K5^-1 (b_o + 1/2 D_oe B x_e)
 // The recursion tracks r = b' - S x_e, whose norm equals the full residual
 // |b - D5 x| after reconstruction, so it stops on the quantity that matters;
@@ -64,7 +68,8 @@ struct Solver {
     int chunk;   // RHS per Schur launch pair (they share the hop temporary)
     // per RHS
     char *xh, *bp;                 // FP64, stride H64
-    char *r, *p, *s, *q, *xl;      // inner precision (x_lo: px), strides Hi / Hx
+    char *r, *p, *p2, *s, *q, *xl; // inner precision (x_lo: px), strides Hi / Hx; p / p2
+                                   // hold the direction of even / odd iterations
     // shared
     char* t;                       // inner hop temporary, `chunk` RHS at stride Hi
     char *be, *bo, *rh, *t64, *ye, *xo;   // FP64 scratch, one RHS each
@@ -84,8 +89,8 @@ struct Solver {
     // kernels A, B of S and of S^+ (first chunk); prof = the current six
     std::vector<hipEvent_t> pev;
     hipEvent_t* prof = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // even, odd iteration
+    hipGraph_t graph[2] = {nullptr, nullptr};
     mdwf_status err = MDWF_OK;
     const double* const* b;
     double* const* x;
@@ -154,16 +159,22 @@ struct Solver {
         launch_pack_parity(g, P64, 1, 1, src, bo, st);
     }
 
-    void one_iteration() {
-        void* xcur = mixed ? static_cast<void*>(xl) : static_cast<void*>(xh);
-        const size_t sxc = mixed ? Hx : H64;
-        schur_inner(p, q, act, false, part, prof);
-        launch_scalars(SC_ALPHA, part, nbh, n, act, sc, nullptr, st);
+    void* xcur() const { return mixed ? static_cast<void*>(xl) : static_cast<void*>(xh); }
+    size_t sxc() const { return mixed ? Hx : H64; }
+
+    // iteration j (odd: the second of a pair) with direction p_j in
+    // (odd ? p2 : p)
+    void one_iteration(bool odd) {
+        char* pc = odd ? p2 : p;
+        char* po = odd ? p : p2;
+        schur_inner(pc, q, act, false, part, prof);
+        launch_scalars(odd ? SC_ALPHA : SC_ALPHA_KEEP, part, nbh, n, act, sc, nullptr, st);
         launch_cg_r(g, pi, r, q, Hi, n, act, sc, part, st);
         launch_scalars(SC_RR, part, nbb, n, act, sc, nullptr, st);
         schur_inner(r, s, act, true, part, prof ? prof + 3 : nullptr);
         launch_scalars(SC_BETA, part, nbh, n, act, sc, nullptr, st);
-        launch_cg_xp(g, mixed ? px : P64, pi, xcur, sxc, p, s, Hi, n, act, sc, st);
+        if (odd) launch_cg_xp2(g, mixed ? px : P64, pi, xcur(), sxc(), po, pc, s, Hi, n, act, sc, st);
+        else launch_cg_p(g, pi, po, pc, s, Hi, n, act, sc, st);
     }
 };
 
@@ -178,7 +189,7 @@ size_t solve_footprint(const Geo& g, Prec inner, int n, bool host_io) {
     const bool mixed = inner != P64;
     const size_t H64 = half_field_bytes(P64, g.Vh), Hi = half_field_bytes(inner, g.Vh);
     const size_t Hx = half_field_bytes(P32, g.Vh);
-    const size_t per_rhs = 2 * H64 + (mixed ? 4 * Hi + Hx : 4 * H64);
+    const size_t per_rhs = 2 * H64 + (mixed ? 5 * Hi + Hx : 5 * H64);
     const size_t shared = 6 * H64 + (host_io ? size_t(2) * g.Vh * 24 * sizeof(double) : 0);
     const size_t tmp = size_t(n) * (mixed ? Hi : H64);   // hop temporary for every RHS at once
     return per_rhs * n + shared + tmp + (size_t(64) << 20);
@@ -279,6 +290,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     if (S.mixed) {
         ALLOC(r, "sv_r", S.Hi * n);
         ALLOC(p, "sv_p", S.Hi * n);
+        ALLOC(p2, "sv_p2", S.Hi * n);
         ALLOC(s, "sv_s", S.Hi * n);
         ALLOC(q, "sv_q", S.Hi * n);
         ALLOC(xl, "sv_xl", S.Hx * n);
@@ -286,6 +298,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     } else {
         ALLOC(r, "sv_r64", S.H64 * n);
         ALLOC(p, "sv_p64", S.H64 * n);
+        ALLOC(p2, "sv_p2_64", S.H64 * n);
         ALLOC(s, "sv_s64", S.H64 * n);
         ALLOC(q, "sv_q64", S.H64 * n);
         ALLOC(t, "sv_t64c", S.H64 * S.chunk);
@@ -358,6 +371,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     }
     S.hipok(hipMemsetAsync(S.xh, 0, S.H64 * n, st), "memset");
     if (S.mixed) S.hipok(hipMemsetAsync(S.xl, 0, S.Hx * n, st), "memset");
+    // the odd-iteration buffer is read (times alpha_prev = 0) before a
+    // restart has written it: start it finite
+    S.hipok(hipMemsetAsync(S.p2, 0, S.Hi * n, st), "memset");
+    int it = 0;   // CG iterations done; odd: an update alpha_prev p is pending
     S.upload_mask(S.act, active);
     if (S.err) return S.err;
 
@@ -366,6 +383,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     // precision, s = S^+ r, gamma = |s|^2, and p = s where `restart_p`.
     auto refresh = [&](const std::vector<int>& upd, const std::vector<int>& restart_p) {
         S.upload_mask(S.msk, upd);
+        if (it & 1) {   // the pending half of a two-iteration update (direction in p)
+            launch_cg_xpend(g, S.mixed ? S.px : P64, S.pi, S.xcur(), S.sxc(), S.p, S.Hi, n, S.msk, S.sc, st);
+            launch_scalars(SC_CLEAR_PREV, S.part, 0, n, S.msk, S.sc, nullptr, st);
+        }
         if (S.mixed) launch_flush(g, S.px, S.xh, S.H64, S.xl, S.Hx, n, S.msk, st);
         std::vector<double> rr(n, 0.0);
         for (int k = 0; k < n; ++k) {
@@ -384,9 +405,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             rmax[k] = std::sqrt(rr[k]);
             if (restart_p[k]) { rp[k] = 1; any_rp = true; }
         }
-        if (any_rp) {
+        if (any_rp) {   // into the buffer the next iteration reads
             S.upload_mask(S.msk, rp);
-            launch_convert(g, S.pi, S.pi, S.s, S.p, S.Hi, S.Hi, n, S.msk, st);
+            launch_convert(g, S.pi, S.pi, S.s, (it & 1) ? S.p2 : S.p, S.Hi, S.Hi, n, S.msk, st);
         }
         return rr;
     };
@@ -431,14 +452,15 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     }
     if (S.err) return S.err;
 
-    // optional graph of one iteration
+    // optional graphs of an even and an odd iteration
     bool use_graph = o.use_graph != 0;
-    if (use_graph) {
+    for (int odd = 0; odd < 2 && use_graph; ++odd) {
         if (!S.hipok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "capture")) return S.err;
-        S.one_iteration();
-        hipError_t e = hipStreamEndCapture(st, &S.graph);
+        S.one_iteration(odd == 1);
+        hipError_t e = hipStreamEndCapture(st, &S.graph[odd]);
         if (!S.hipok(e, "capture end")) return S.err;
-        if (!S.hipok(hipGraphInstantiate(&S.gexec, S.graph, nullptr, nullptr, 0), "graph instantiate")) return S.err;
+        if (!S.hipok(hipGraphInstantiate(&S.gexec[odd], S.graph[odd], nullptr, nullptr, 0), "graph instantiate"))
+            return S.err;
     }
 
     // launch timing: sampled iterations from the third on (not with a graph)
@@ -451,7 +473,6 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     }
 
     const double tgt = 0.5 * o.tol / knorm;
-    int it = 0;
     bool pending = false;
     int pend_slot = 0;
     // Each RHS's update schedule must depend on its own residuals only, so a
@@ -465,10 +486,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     };
     while (any_active() && S.err == MDWF_OK) {
         if (use_graph) {
-            S.hipok(hipGraphLaunch(S.gexec, st), "graph launch");
+            S.hipok(hipGraphLaunch(S.gexec[it & 1], st), "graph launch");
         } else {
             S.prof = (it >= 2 && prof_done < nprof) ? &S.pev[6 * prof_done++] : nullptr;
-            S.one_iteration();
+            S.one_iteration((it & 1) != 0);
             S.prof = nullptr;
         }
         ++it;
@@ -550,8 +571,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
 
     // reconstruct every RHS, verify and write x
     for (int k = 0; k < n && !S.err; ++k) true_res[k] = verify(k, true);
-    if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
-    if (S.graph) (void)hipGraphDestroy(S.graph);
+    for (int odd = 0; odd < 2; ++odd) {
+        if (S.gexec[odd]) (void)hipGraphExecDestroy(S.gexec[odd]);
+        if (S.graph[odd]) (void)hipGraphDestroy(S.graph[odd]);
+    }
     for (int e = 0; e < 2; ++e) (void)hipEventDestroy(S.ev[e]);
     if (S.err) return S.err;
 
@@ -560,9 +583,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     // model counts per RHS
     const double bsI = spinor_site_bytes(S.pi), bsX = spinor_site_bytes(S.px), bs64 = spinor_site_bytes(P64);
     const double blI = link_site_bytes(S.pi, g.L5), bl64 = link_site_bytes(P64, g.L5);
-    // A, B, A^+, B^+ (10 inner fields), r -= alpha q (3), x += alpha p with
-    // p = s + beta p (3 inner + x_lo read and written)
-    const double it_bytes = g.Vh * (16 * bsI + 2 * bsX + 4 * blI);
+    // A, B, A^+, B^+ (10 inner fields), r -= alpha q (3), the direction update
+    // (3 inner fields) and, every second iteration, x read and written with
+    // one more inner read: 16.5 inner fields and one x field per iteration
+    const double it_bytes = g.Vh * (16.5 * bsI + bsX + 4 * blI);
     const double it_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 5 * 48.0);
     const double up_bytes = g.Vh * (5 * bs64 + 2 * bl64 + 3 * bs64 + bs64 + bsI + 5 * bsI + 2 * blI + 2 * bs64 + 2 * bsX);
     const double up_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 3 * 48.0);
