@@ -311,6 +311,57 @@ def summarize(args):
     print(text)
 
 
+def pmc_summary(args):
+    """Markdown summary of a rocprofv3 counter database with SQ_ACTIVE_INST_VALU,
+    SQ_ACTIVE_INST_LDS and GRBM_GUI_ACTIVE: per kernel and grid, the share of
+    the dispatch time the vector ALUs (and LDS) were busy, rocprofv3's
+    VALUBusy = 100 sum(SQ_ACTIVE_INST_VALU) / CU_NUM / max(GRBM_GUI_ACTIVE).
+    The database holds each counter summed over its dimensions, so the
+    per-XCD maximum of GRBM_GUI_ACTIVE is taken as that sum / 8 XCDs (the
+    XCDs run the dispatch side by side)."""
+    import collections
+    import sqlite3
+    cu_num, n_xcd = 256, 8
+    db = sqlite3.connect(args.pmc_summary)
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    meta = {}
+    for did, kn, gs, cn, v in db.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
+                                         "from counters_collection"):
+        per[did][cn].append(v)
+        meta[did] = (_kernel_label(kn), gs)
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for did, cs in per.items():
+        if "GRBM_GUI_ACTIVE" not in cs or "SQ_ACTIVE_INST_VALU" not in cs:
+            continue
+        g = sum(cs["GRBM_GUI_ACTIVE"]) / n_xcd
+        if g <= 0:
+            continue
+        key = meta[did]
+        agg[key]["valu"].append(100.0 * sum(cs["SQ_ACTIVE_INST_VALU"]) / cu_num / g)
+        if "SQ_ACTIVE_INST_LDS" in cs:
+            agg[key]["lds"].append(100.0 * sum(cs["SQ_ACTIVE_INST_LDS"]) / cu_num / g)
+    lines = ["# rocprofv3 counters: vector ALU and LDS busy share of the hop and CG kernels", "",
+             "Commands (from the repository root on one MI355X, with `export TMPDIR=/tmp`):", ""]
+    lines += ["    " + c.strip() for c in args.summary_cmds.split("||") if c.strip()]
+    lines += ["", "VALU busy = 100 sum(SQ_ACTIVE_INST_VALU) / 256 CUs / GRBM_GUI_ACTIVE per XCD, per dispatch "
+              "(rocprofv3's VALUBusy; the database sums GRBM_GUI_ACTIVE over the 8 XCDs, divided back "
+              "here), LDS busy likewise from SQ_ACTIVE_INST_LDS; means over the dispatches of each "
+              "kernel and grid.", "",
+              "| kernel | grid (threads) | dispatches | VALU busy % | LDS busy % |", "|---|---|---|---|---|"]
+    rows = sorted(agg.items(), key=lambda kv: -len(kv[1]["valu"]))
+    for (name, gs), d in rows:
+        if not (name.startswith("mdwf::k_hop") or name.startswith("mdwf::k_cg")):
+            continue
+        lds = "%.1f" % (sum(d["lds"]) / len(d["lds"])) if d["lds"] else "-"
+        lines.append("| `%s` | %d | %d | %.1f | %s |" % (name, gs, len(d["valu"]),
+                                                          sum(d["valu"]) / len(d["valu"]), lds))
+    text = "\n".join(lines) + "\n"
+    if args.summary_out:
+        with open(args.summary_out, "w") as f:
+            f.write(text)
+    print(text)
+
+
 def serve_requests(n, rng):
     """n requests of the serving mix: (field index, RHS count, mass per RHS)."""
     out = []
@@ -574,6 +625,8 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DB", "FETCH_DB", "WRITE_DB"),
                     help="write the rocprofv3 summary of the dominant kernels (no GPU use); "
                          "FETCH_DB / WRITE_DB may be '-'")
+    ap.add_argument("--pmc-summary", default=None, metavar="DB",
+                    help="write the VALU / LDS busy summary of a rocprofv3 counter database (no GPU use)")
     ap.add_argument("--summary-out", default=None)
     ap.add_argument("--summary-cmds", default="", help="commands that produced the databases ('||'-separated)")
     ap.add_argument("--summary-bench", default=None, help="the JSON line bench.py printed in the traced run")
@@ -591,6 +644,9 @@ def main():
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
+        return
+    if args.pmc_summary:
+        pmc_summary(args)
         return
 
     if args.gpus != 1:

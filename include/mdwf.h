@@ -16,9 +16,11 @@
  *   -1/2 Dslash B.  The solver works on the asymmetric even-odd Schur
  *   complement the paper names (Sec. VII):
  *     S = K5 - 1/4 D_eo B K5^-1 D_oe B   on the even 4D sites,
- *   and solves D5 x = b by CG on the normal equations of S (least-squares
- *   form), optionally with an FP32 or FP16 inner solve and FP64 reliable
- *   updates (the paper's "double-half" mixed-precision solver, Sec. VII).
+ *   and solves D5 x = b by CG on the normal equations (least-squares form) of
+ *   S, of the symmetric form K5^-1 S (Sec. VII) or of S B^-1 (right
+ *   preconditioning by B), optionally with an FP32 or FP16 inner solve and
+ *   FP64 reliable updates (the paper's "double-half" mixed-precision solver,
+ *   Sec. VII).
  *
  * Conventions:
  *   Euclidean chiral gamma basis, g5 = diag(1, 1, -1, -1); P+ = spins 0,1.
@@ -66,7 +68,7 @@ typedef enum {
     MDWF_ERR_STATE = 2,    /* call out of order (no gauge field / action yet)   */
     MDWF_ERR_OOM = 3,      /* device allocation failed                          */
     MDWF_ERR_HIP = 4,      /* HIP runtime error                                 */
-    MDWF_ERR_NOCONV = 5,   /* solver stopped at max_iter; best x written        */
+    MDWF_ERR_NOCONV = 5,   /* solver stopped at max_iter or max_seconds; best x written */
     MDWF_ERR_NUMERIC = 6   /* NaN/Inf or breakdown in a reduction               */
 } mdwf_status;
 
@@ -146,8 +148,9 @@ typedef struct {
     double model_flops;   /* flops of the model counted for this right-hand side  */
     double model_bytes;   /* algorithmic HBM bytes of the model for this RHS       */
     double hop_us[4];     /* profile_iters > 0: mean duration (us) of one launch of
-                             kernel A, B, A^+, B^+ (inner precision, first chunk
-                             of right-hand sides, all its RHS together); else 0 */
+                             kernel A, B, A^+, B^+ of the CG operator (inner
+                             precision, first chunk of right-hand sides, all its
+                             RHS together); else 0 */
     int hop_rhs;          /* right-hand sides in those launches                   */
     int hop_samples;      /* iterations sampled                                   */
 } mdwf_solve_info;
@@ -200,7 +203,8 @@ mdwf_status mdwf_apply_dev(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const void
  * parameters are shared.  info: array of nrhs records (may be NULL).
  * All RHS share every operator launch; when their vectors do not fit in
  * free device memory together, consecutive sub-batches are solved in turn.
- * Returns ERR_NOCONV if any RHS hit max_iter (its best x is still written). */
+ * Returns ERR_NOCONV if any RHS hit max_iter or the time limit (its best x is
+ * still written). */
 mdwf_status mdwf_solve(mdwf_ctx *ctx, int nrhs, const double *const *b, double *const *x,
                        const double *mq, const mdwf_solver_opts *opts, mdwf_solve_info *info);
 

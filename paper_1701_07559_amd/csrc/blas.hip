@@ -305,50 +305,6 @@ void launch_cg_r(const Geo& g, Prec pi, void* r, const void* q, size_t si, int n
     }
 }
 
-// x += alpha p, then p = s + beta p: the solution update of this iteration,
-// deferred to the pass that reads p anyway (alpha of this iteration, p before
-// its update), so p is read once per iteration
-template <Prec PX, Prec PI>
-__global__ void __launch_bounds__(kBlas) k_cg_xp(const Geo g, void* x, size_t sx, void* p, const void* s, size_t si,
-                                                 const int* active, const CGScal* sc) {
-    const int rhs = blockIdx.y;
-    if (active && !active[rhs]) return;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= g.Vh) return;
-    const double alpha = sc[rhs].alpha, beta = sc[rhs].beta;
-    cx<double> vx[12], vp[12], vs[12];
-    Ld<PX>::load(at_rhs(x, sx, rhs), g.Vh, j, vx);
-    Ld<PI>::load(at_rhs(p, si, rhs), g.Vh, j, vp);
-    Ld<PI>::load(at_rhs(s, si, rhs), g.Vh, j, vs);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        vx[c] = vx[c] + alpha * vp[c];
-        vp[c] = vs[c] + beta * vp[c];
-    }
-    Ld<PX>::store(at_rhs(x, sx, rhs), g.Vh, j, vx);
-    Ld<PI>::store(at_rhs(p, si, rhs), g.Vh, j, vp);
-}
-
-template <Prec PX>
-static void cg_xp_px(const Geo& g, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
-                     const int* active, const CGScal* sc, hipStream_t st) {
-    const dim3 grid(blas_blocks_per_rhs(g), nrhs), blk(kBlas);
-    switch (pi) {
-        case P64: hipLaunchKernelGGL((k_cg_xp<PX, P64>), grid, blk, 0, st, g, x, sx, p, s, si, active, sc); break;
-        case P32: hipLaunchKernelGGL((k_cg_xp<PX, P32>), grid, blk, 0, st, g, x, sx, p, s, si, active, sc); break;
-        case P16: hipLaunchKernelGGL((k_cg_xp<PX, P16>), grid, blk, 0, st, g, x, sx, p, s, si, active, sc); break;
-    }
-}
-
-void launch_cg_xp(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
-                  const int* active, const CGScal* sc, hipStream_t st) {
-    switch (px) {
-        case P64: cg_xp_px<P64>(g, pi, x, sx, p, s, si, nrhs, active, sc, st); break;
-        case P32: cg_xp_px<P32>(g, pi, x, sx, p, s, si, nrhs, active, sc, st); break;
-        case P16: cg_xp_px<P16>(g, pi, x, sx, p, s, si, nrhs, active, sc, st); break;
-    }
-}
-
 // even iteration of the two-iteration update: pn = s + beta p
 template <Prec PI>
 __global__ void __launch_bounds__(kBlas) k_cg_p(const Geo g, void* pn, const void* p, const void* s, size_t si,

@@ -401,9 +401,6 @@ void launch_norm2(const Geo& g, Prec p, const void* x, size_t stride, int nrhs, 
 struct CGScal;
 void launch_cg_r(const Geo& g, Prec pi, void* r, const void* q, size_t si, int nrhs, const int* active,
                  const CGScal* sc, double* partials, hipStream_t st);
-// x(px) += alpha[r] * p(pi); then p = s + beta[r] p
-void launch_cg_xp(const Geo& g, Prec px, Prec pi, void* x, size_t sx, void* p, const void* s, size_t si, int nrhs,
-                  const int* active, const CGScal* sc, hipStream_t st);
 // Two-iteration solution update.  Even iteration: pn = s + beta p (x waits).
 // Odd iteration: x += alpha_prev pp + alpha p, then pp = s + beta p (pp holds
 // the even iteration's direction on entry, the next direction on exit).
