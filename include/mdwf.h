@@ -261,6 +261,26 @@ mdwf_status mdwf_get_tune(const mdwf_ctx *ctx, mdwf_prec prec, mdwf_launch_tune 
 /* Model flop and byte counts for one application of an operator (per call). */
 mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, double *flops, double *bytes);
 
+/* ------------------------------------------------------- gradient flow
+ * Wilson gradient flow of a gauge field, the smearing the paper applies to
+ * its ensembles before the valence solves (Sec. III; flow time t_gf = 1):
+ *   dV/dt = Z(V) V,  Z_mu(x) = -1/2 (O - O^+) + 1/6 tr(O - O^+),
+ *   O_mu(x) = U_mu(x) * (sum of the six staples of the link),
+ * integrated in FP64 with Luscher's third-order Runge-Kutta scheme, nsteps
+ * steps of size eps (flow time nsteps * eps).  U is a canonical gauge field
+ * (layout of mdwf_load_gauge), flowed in place; all directions periodic (the
+ * fermion boundary condition plays no part).  plaq (may be NULL) receives
+ * the average plaquette before and after.  Extents >= 2; ERR_ARG on eps <= 0
+ * or nsteps < 0.  Synchronous; allocates two link fields of scratch. */
+mdwf_status mdwf_wilson_flow(const mdwf_geometry *geom, int hip_device, double *U, double eps, int nsteps,
+                             double *plaq);
+/* Same on a device field, on `stream` (NULL = the null stream). */
+mdwf_status mdwf_wilson_flow_dev(const mdwf_geometry *geom, double *U_dev, double eps, int nsteps, void *stream,
+                                 double *plaq);
+/* Average plaquette (1/3) Re tr U(p) over sites and the six planes of a
+ * device gauge field (fixed-order reduction).  Synchronous on `stream`. */
+mdwf_status mdwf_plaquette_dev(const mdwf_geometry *geom, const double *U_dev, void *stream, double *plaq);
+
 /* ------------------------------------------------------------ serving
  * A request server for many solves of D5 x = b (the paper computes
  * propagators for several ensembles, masses and sources, Sec. III): gauge

@@ -127,6 +127,9 @@ def _load():
         "mdwf_autotune": ([vp, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_autotune_solve": ([vp, C.POINTER(mdwf_solver_opts), ip, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_get_tune": ([vp, ip, C.POINTER(mdwf_launch_tune)], ip),
+        "mdwf_wilson_flow": ([C.POINTER(mdwf_geometry), ip, vp, dp, ip, C.POINTER(dp)], ip),
+        "mdwf_wilson_flow_dev": ([C.POINTER(mdwf_geometry), vp, dp, ip, vp, C.POINTER(dp)], ip),
+        "mdwf_plaquette_dev": ([C.POINTER(mdwf_geometry), vp, vp, C.POINTER(dp)], ip),
         "mdwf_server_create": ([ip, C.c_size_t, ip, C.POINTER(vp)], ip),
         "mdwf_server_destroy": ([vp], None),
         "mdwf_server_last_error": ([vp], C.c_char_p),
@@ -287,6 +290,37 @@ def mdwf_get_tune(ctx, prec):
     return t.as_dict()
 
 
+def mdwf_wilson_flow(dims, U, eps, nsteps, hip_device=0):
+    """Wilson gradient flow of a host canonical gauge field (a flowed copy is
+    returned); returns (U_flowed, (plaquette before, after))."""
+    g = mdwf_geometry(*[int(d) for d in dims], 0)
+    V = np.array(U, dtype=np.complex128, order="C", copy=True)
+    plaq = (C.c_double * 2)()
+    st = lib.mdwf_wilson_flow(C.byref(g), int(hip_device), V.ctypes.data, float(eps), int(nsteps), plaq)
+    if st != MDWF_OK:
+        raise MdwfError(st, mdwf_last_error(None))
+    return V, (plaq[0], plaq[1])
+
+
+def mdwf_wilson_flow_dev(dims, U_ptr, eps, nsteps, stream=None):
+    """Flow a device canonical gauge field in place; returns (plaquette before, after)."""
+    g = mdwf_geometry(*[int(d) for d in dims], 0)
+    plaq = (C.c_double * 2)()
+    st = lib.mdwf_wilson_flow_dev(C.byref(g), int(U_ptr), float(eps), int(nsteps), stream, plaq)
+    if st != MDWF_OK:
+        raise MdwfError(st, mdwf_last_error(None))
+    return plaq[0], plaq[1]
+
+
+def mdwf_plaquette_dev(dims, U_ptr, stream=None):
+    g = mdwf_geometry(*[int(d) for d in dims], 0)
+    p = C.c_double()
+    st = lib.mdwf_plaquette_dev(C.byref(g), int(U_ptr), stream, C.byref(p))
+    if st != MDWF_OK:
+        raise MdwfError(st, mdwf_last_error(None))
+    return p.value
+
+
 class Server:
     """Request server (mdwf_server_*): resident gauge fields, solves admitted
     by device footprint and run concurrently on worker streams.  Host arrays
@@ -359,6 +393,7 @@ def exported_symbols():
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
             "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
-            "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_server_create", "mdwf_server_destroy",
+            "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
+            "mdwf_plaquette_dev", "mdwf_server_create", "mdwf_server_destroy",
             "mdwf_server_last_error", "mdwf_server_add_field", "mdwf_server_submit", "mdwf_server_wait",
             "mdwf_server_stats"]
