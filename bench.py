@@ -55,6 +55,7 @@ WORKLOADS = {
     "batched": dict(DIMS=(32, 32, 32, 64), L5=10, MASSES=[0.0074, 0.02, 0.04], GAUGE_SEED=104, SITE_SEED=404,
                     GROUPS=3),
     "serving": None,   # its own driver, serve_main
+    "flow": None,      # its own driver, flow_main
 }
 
 # Serving: four resident gauge fields shaped like the paper's ensembles
@@ -362,6 +363,102 @@ def pmc_summary(args):
     print(text)
 
 
+# Gradient flow model per link and Runge-Kutta stage: 26 products of 3x3
+# complex matrices (12 for the six staples, one for the link times their sum,
+# 12 for the degree-12 Taylor exponential, one for the update; 216 flops each)
+# and, in FP64, the input link and the output link read / written once and
+# the exponent accumulator read and written (written only by the first stage).
+FLOW_FLOPS_PER_LINK = 26 * 216
+FLOW_BYTES_PER_LINK = (144 * 3 + 144 * 4 + 144 * 4) / 3.0
+
+
+def flow_main(args):
+    """Flow workload: the 24^3 x 64 exp(i 0.25 H) field flowed to t_gf = 1
+    (the paper's flow time) in steps of 0.01, on the device."""
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_1701_07559_amd import inputs as I
+    from paper_1701_07559_amd import mdwf as M
+    dims, eps, nsteps = (24, 24, 24, 64), 0.01, 100
+    log("generating links", dims)
+    U = I.random_links(dims, EPS, GAUGE_SEED)
+    dev = torch.device("cuda:0")
+    work = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(work)
+    U0 = torch.from_numpy(U.view(np.float64).copy()).to(dev)
+    Ud = torch.empty_like(U0)
+    stream = work.cuda_stream
+    nlinks = 4 * int(np.prod(dims))
+    for w in range(args.warmup):
+        Ud.copy_(U0)
+        M.mdwf_wilson_flow_dev(dims, Ud.data_ptr(), eps, 2, stream, plaquette=False)
+    times, kern = [], []
+    plaq = None
+    for k in range(args.steps):
+        Ud.copy_(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(work)
+        M.mdwf_wilson_flow_dev(dims, Ud.data_ptr(), eps, nsteps, stream, plaquette=False)   # stage kernels only
+        e1.record(work)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        kern.append(e0.elapsed_time(e1) * 1e3 / (3 * nsteps))
+        log("flow to t=%.2f: %.3f s, %.1f us per stage" % (eps * nsteps, times[-1], kern[-1]))
+    p0 = M.mdwf_plaquette_dev(dims, U0.data_ptr(), stream)
+    p1 = M.mdwf_plaquette_dev(dims, Ud.data_ptr(), stream)
+    ms = 1e3 * float(np.mean(times))
+    stage_us = float(np.mean(kern))
+    bytes_step = FLOW_BYTES_PER_LINK * nlinks * 3 * nsteps
+    flops_stage = FLOW_FLOPS_PER_LINK * nlinks
+    value = bytes_step / (ms * 1e-3) / 1e9
+    achieved = flops_stage / (stage_us * 1e-6) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        from oracle import flow as F
+        small = (8, 8, 8, 16)
+        Us = I.random_links(small, EPS, GAUGE_SEED)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            Us = F.flow_step(Us, eps)
+            n += 1
+            if time.perf_counter() - t0 > 12.0 or n >= 4:
+                break
+        dt = (time.perf_counter() - t0) / n
+        nl = 4 * int(np.prod(small))
+        cpu = dict(value=round(FLOW_BYTES_PER_LINK * nl * 3 / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                   sample="%d FP64 Runge-Kutta flow steps of the numpy oracle on 8^3x16 (%.2f s each), the same "
+                          "per-link byte model" % (n, dt))
+    out = {
+        "metric": "Moebius DWF dslash GB/s (% HBM peak); time to r=1e-10 solve, mixed vs FP64",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Wilson gradient flow of the 24x24x24x64 exp(i0.25H) gauge field to t_gf = 1 "
+                               "(%d Runge-Kutta steps of %g), FP64" % (nsteps, eps),
+                   "name": "flow", "lattice": list(dims), "eps": eps, "nsteps": nsteps},
+        "flow": {"plaquette_before": p0, "plaquette_after": p1, "seconds": round(ms / 1e3, 4),
+                 "stage_us": round(stage_us, 1)},
+        "roofline": {"bound": "alu", "kernel": "k_flow_stage (one Runge-Kutta stage, FP64)",
+                     "achieved": round(achieved, 2), "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": round(achieved / 78.6, 4), "traffic": None,
+                     "model": "26 complex 3x3 products per link and stage (216 flops each)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def serve_requests(n, rng):
     """n requests of the serving mix: (field index, RHS count, mass per RHS)."""
     out = []
@@ -655,6 +752,9 @@ def main():
         sys.exit(2)
     if args.workload == "serving":
         serve_main(args)
+        return
+    if args.workload == "flow":
+        flow_main(args)
         return
     global DIMS, L5, MASSES, GAUGE_SEED, SITE_SEED, GROUPS
     wl = WORKLOADS[args.workload]

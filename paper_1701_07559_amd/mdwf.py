@@ -302,14 +302,15 @@ def mdwf_wilson_flow(dims, U, eps, nsteps, hip_device=0):
     return V, (plaq[0], plaq[1])
 
 
-def mdwf_wilson_flow_dev(dims, U_ptr, eps, nsteps, stream=None):
-    """Flow a device canonical gauge field in place; returns (plaquette before, after)."""
+def mdwf_wilson_flow_dev(dims, U_ptr, eps, nsteps, stream=None, plaquette=True):
+    """Flow a device canonical gauge field in place; returns (plaquette
+    before, after), or None with plaquette=False (no reductions launched)."""
     g = mdwf_geometry(*[int(d) for d in dims], 0)
-    plaq = (C.c_double * 2)()
+    plaq = (C.c_double * 2)() if plaquette else None
     st = lib.mdwf_wilson_flow_dev(C.byref(g), int(U_ptr), float(eps), int(nsteps), stream, plaq)
     if st != MDWF_OK:
         raise MdwfError(st, mdwf_last_error(None))
-    return plaq[0], plaq[1]
+    return (plaq[0], plaq[1]) if plaquette else None
 
 
 def mdwf_plaquette_dev(dims, U_ptr, stream=None):
