@@ -1,0 +1,133 @@
+"""Pins of the source/sink oracle (oracle/sources.py) against facts fixed by
+the definitions, not against itself:
+
+* Gaussian smearing: in the free field every spatial plane wave is an
+  eigenvector with eigenvalue (1 - sigma^2/(4N) sum_i 4 sin^2(p_i/2))^N; on
+  any field it is gauge covariant, Hermitian and keeps time slices apart.
+* The wall source and the wall projection give the 4D propagator of the
+  5D operator's effective 4D operator, (D_eff^-1 - 1) / (1 - m_q), where
+  D_eff is built densely from D5 and the Pauli-Villars D5(m = 1) and is
+  itself pinned to the paper's Moebius kernel in test_oracle_pins.py.
+* The midpoint and wall correlators obey the integrated axial Ward identity
+  of the 5D action: a global axial rotation (-1 on the first L5/2 slices, +1
+  on the rest) changes D5 only at the midpoint and at the mass term, so
+      sum_x [C_mp(x) + m_q C_PP(x)] = Re sum_cols <eta_col, q_col(source)>,
+  exactly, for point and smeared sources, Shamir and Moebius actions.  A
+  wrong midpoint slice or projector, a wrong wall or a missing (1 - c5 D_W)
+  factor breaks it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sources as SRC
+from paper_1701_07559_amd import inputs as I
+from test_oracle_pins import _eff_operator, dense_of
+
+
+def _sites(dims):
+    X, Y, Z, T = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    return x, y, z, t
+
+
+@pytest.mark.parametrize("n", [(1, 0, 0), (1, 2, 3), (2, 1, 0)])
+def test_smearing_free_field_plane_wave(n):
+    dims = (4, 6, 8, 3)
+    U = I.unit_links(dims)
+    x, y, z, t = _sites(dims)
+    p = [2 * np.pi * n[i] / dims[i] for i in range(3)]
+    rng = np.random.default_rng(1)
+    chi = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    ft = rng.standard_normal(dims[3])                    # arbitrary time profile
+    wave = (np.exp(1j * (p[0] * x + p[1] * y + p[2] * z)) * ft[t])[..., None, None] * chi
+    sigma, N = 2.5, 7
+    lam = 1 - sigma ** 2 / (4 * N) * sum(4 * np.sin(pi / 2) ** 2 for pi in p)
+    out = SRC.gauss_smear(U, wave, sigma, N)
+    assert np.abs(out - lam ** N * wave).max() < 1e-13
+
+
+def test_smearing_is_gauge_covariant():
+    dims = (4, 2, 4, 2)
+    U = I.random_links(dims, 0.4, 81)
+    g = I.random_gauge_transform(dims, 82)
+    psi = I.gaussian_source(dims, 1, 83)[0]
+    a = I.gauge_transform_spinor(SRC.gauss_smear(U, psi, 2.0, 4), g)
+    b = SRC.gauss_smear(I.gauge_transform_links(U, g), I.gauge_transform_spinor(psi, g), 2.0, 4)
+    assert np.abs(a - b).max() < 1e-12
+
+
+def test_smearing_is_hermitian_and_keeps_time_slices():
+    dims = (4, 4, 2, 4)
+    U = I.random_links(dims, 0.4, 84)
+    a = I.gaussian_source(dims, 1, 85)[0]
+    b = I.gaussian_source(dims, 1, 86)[0]
+    Ka, Kb = SRC.gauss_smear(U, a, 3.0, 5), SRC.gauss_smear(U, b, 3.0, 5)
+    assert abs(np.vdot(a, Kb) - np.vdot(Ka, b)) < 1e-11 * abs(np.vdot(a, Kb))
+    one = np.zeros_like(a)
+    one[2] = a[2]
+    K1 = SRC.gauss_smear(U, one, 3.0, 5)
+    assert np.abs(K1[[0, 1, 3]]).max() == 0.0 and np.abs(K1[2]).max() > 0
+    # zero steps and zero width are the identity
+    assert np.array_equal(SRC.gauss_smear(U, a, 3.0, 0), a)
+    assert np.abs(SRC.gauss_smear(U, a, 0.0, 3) - a).max() == 0.0
+
+
+def _dense_D5(act, U):
+    n5 = 12 * int(np.prod(act.dims)) * act.L5
+    return dense_of(lambda v: oracle.D5(act, U, v), n5, act.shape5)
+
+
+@pytest.mark.parametrize("b5,c5", [(1.5, 0.5), (1.0, 0.0)])
+def test_wall_source_gives_the_effective_operator_propagator(b5, c5):
+    dims, L5 = (2, 2, 2, 4), 4
+    U = I.random_links(dims, 0.3, 87)
+    act = oracle.Action(dims, L5, M5=1.3, b5=b5, c5=c5, mq=0.05)
+    Deff, _ = _eff_operator(act, U)
+    n4 = Deff.shape[0]
+    S4 = (np.linalg.inv(Deff) - np.eye(n4)) / (1 - act.mq)
+    D = _dense_D5(act, U)
+    etas = [SRC.point_source(dims, (1, 0, 1, 1), j // 3, j % 3) for j in range(12)]
+    etas.append(I.gaussian_source(dims, 1, 88)[0])
+    for eta in etas:
+        x = np.linalg.solve(D, SRC.wall_source(act, U, eta).ravel()).reshape(act.shape5)
+        ref = (S4 @ eta.ravel()).reshape(eta.shape)
+        assert np.abs(SRC.project_wall(x) - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("b5,c5,L5,smear", [(1.0, 0.0, 4, None), (1.5, 0.5, 4, None),
+                                            (1.5, 0.5, 6, (1.5, 5)), (1.25, 0.25, 6, (2.0, 3))])
+def test_integrated_axial_ward_identity(b5, c5, L5, smear):
+    dims = (2, 2, 2, 4)
+    U = I.random_links(dims, 0.3, 89)
+    act = oracle.Action(dims, L5, M5=1.2, b5=b5, c5=c5, mq=0.04)
+    D = _dense_D5(act, U)
+    cols, rhs = [], 0.0
+    for j in range(12):
+        eta = SRC.point_source(dims, (2, 1, 0, 1), j // 3, j % 3)
+        if smear:
+            eta = SRC.gauss_smear(U, eta, *smear)
+        x = np.linalg.solve(D, SRC.wall_source(act, U, eta).ravel()).reshape(act.shape5)
+        cols.append(x)
+        rhs += np.vdot(eta, SRC.project_wall(x)).real
+    cpp, cmp_, mres = SRC.correlators(cols)
+    lhs = float(np.sum(cmp_ + act.mq * cpp))
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+    assert np.all(cpp > 0) and np.all(cmp_ > 0) and np.allclose(mres, cmp_ / cpp)
+
+
+def test_residual_mass_falls_with_L5_on_a_smooth_field():
+    """Chiral symmetry breaking shrinks as the fifth dimension grows."""
+    dims = (2, 2, 2, 4)
+    U = I.random_links(dims, 0.1, 90)
+    means = []
+    for L5 in (4, 8, 12):
+        act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.02)
+        cols = []
+        for j in range(12):
+            eta = SRC.point_source(dims, (0, 0, 0, 0), j // 3, j % 3)
+            x, info = oracle.solve(act, U, SRC.wall_source(act, U, eta), tol=1e-12)
+            assert info["status"] == 0
+            cols.append(x)
+        means.append(float(np.mean(SRC.correlators(cols)[2][1:])))
+    assert means[0] > 3 * means[1] > 9 * means[2] > 0, means
