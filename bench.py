@@ -24,6 +24,9 @@ on the launch stream), and the FP64 CPU oracle timed on a bounded sample.
 
 --workload batched: the a12m220 volume, 32^3 x 64 at L5 = 10, 36 RHS (the
 12 columns at m_q = 0.0074, 0.02, 0.04) as three multi-mass launches of 12.
+--workload flow: the Wilson gradient flow of the 24^3 x 64 field to t = 1.
+--workload mres: the source and sink side around the headline solve
+(Gaussian-smeared point source, Moebius wall sources, m_res correlators).
 --summarize: write the rocprofv3 summary of the dominant kernels (no GPU).
 """
 from __future__ import annotations
@@ -56,6 +59,7 @@ WORKLOADS = {
                     GROUPS=3),
     "serving": None,   # its own driver, serve_main
     "flow": None,      # its own driver, flow_main
+    "mres": None,      # its own driver, mres_main
 }
 
 # Serving: four resident gauge fields shaped like the paper's ensembles
@@ -698,6 +702,170 @@ def serve_cpu_baseline(U16, burst, recs, budget_s=25.0):
                        "iteration, time proportional to 5D volume)" % (n, dt, len(burst)))
 
 
+# Source/sink model per 4D site: a Gaussian smearing step reads and writes
+# every vector once (192 B each way) and the three spatial links once
+# (432 B); the wall source reads a vector and the four links and writes L5
+# slices of its 5D field; the correlators read the four slices they use.
+SMEAR_SIGMA, SMEAR_ITERS = 4.0, 30
+
+
+def smear_bytes(V, nvec):
+    return V * (nvec * 384.0 + 432.0)
+
+
+def wall_bytes(V, nvec, L5_):
+    return V * (nvec * (192.0 + 192.0 * L5_) + 576.0)
+
+
+def corr_bytes(V, nvec):
+    return V * nvec * 4 * 96.0
+
+
+def mres_main(args):
+    """Source/sink workload: the 12 spin-colour columns of a point source on
+    the 24^3 x 64 field, Gaussian-smeared, turned into 5D Moebius sources,
+    solved (the headline mixed solve) and contracted into the pseudoscalar
+    and midpoint correlators and m_res(t)."""
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_1701_07559_amd import inputs as I
+    from paper_1701_07559_amd import mdwf as M
+    dims, L5_ = DIMS, L5
+    X, Y, Z, T = dims
+    V = X * Y * Z * T
+    act_t = (ACTION["M5"], ACTION["b5"], ACTION["c5"], ACTION["mq"], L5_)
+    dev = torch.device("cuda:0")
+    work = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(work)
+    stream = work.cuda_stream
+    log("generating links", dims)
+    U = I.random_links(dims, EPS, GAUGE_SEED, workers=8)
+    Ud = torch.from_numpy(U.view(np.float64).copy()).to(dev)
+    del U
+    xs, ys, zs, ts = I.random_point_site(dims, SITE_SEED)
+    eta = torch.zeros((12, V * 24), dtype=torch.float64, device=dev)
+    for j in range(12):
+        eta[j, 2 * ((((ts * Z + zs) * Y + ys) * X + xs) * 12 + j)] = 1.0
+    sm = torch.empty_like(eta)
+    n5 = L5_ * V * 24
+    b = torch.empty((12, n5), dtype=torch.float64, device=dev)
+    x = torch.zeros((12, n5), dtype=torch.float64, device=dev)
+    ctx = M.mdwf_create(dims, antiperiodic_t=True, hip_device=0, hip_stream=stream)
+    M.mdwf_set_action(ctx, *act_t)
+    M.mdwf_load_gauge_dev(ctx, Ud.data_ptr())
+    opts = dict(tol=1e-10, inner=M.MDWF_F16, max_iter=args.max_iter, delta=0.1,
+                schur_form=FORMS[args.schur_form])
+    if not args.no_tune:
+        M.mdwf_autotune_solve(ctx, 12, opts)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step():
+        e = [ev() for _ in range(4)]
+        e[0].record(work)
+        M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), 12, eta.data_ptr(), sm.data_ptr(), SMEAR_SIGMA, SMEAR_ITERS,
+                               stream)
+        e[1].record(work)
+        M.mdwf_wall_source_dev(dims, act_t, Ud.data_ptr(), 12, sm.data_ptr(), b.data_ptr(), True, stream)
+        e[2].record(work)
+        st, infos = M.mdwf_solve_dev(ctx, [b[k].data_ptr() for k in range(12)], [x[k].data_ptr() for k in range(12)],
+                                     opts=opts, stream=stream)
+        e[3].record(work)
+        c0 = time.perf_counter()
+        corr = M.mdwf_mres_correlators_dev(dims, L5_, 12, x.data_ptr(), stream)
+        corr_s = time.perf_counter() - c0
+        torch.cuda.synchronize()
+        return st, infos, corr, dict(smear_ms=e[0].elapsed_time(e[1]), wall_ms=e[1].elapsed_time(e[2]),
+                                     solve_ms=e[2].elapsed_time(e[3]), corr_ms=1e3 * corr_s)
+
+    for w in range(args.warmup):
+        st, infos, _, kt = step()
+        log("warmup %d: status %d, %s" % (w, st, kt))
+    times, kts = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos, corr, kt = step()
+        times.append(time.perf_counter() - t0)
+        kts.append(kt)
+        log("step %d: %.3f s status %d max true resid %.2e  %s" % (k, times[-1], st,
+                                                                  max(i["true_resid"] for i in infos), kt))
+    cpp, cmp_, mres = corr
+    # integrated axial Ward identity: sum_t [C_mp + m C_PP] = Re sum_cols <source, q(source)>
+    q = torch.empty_like(sm)
+    M.mdwf_project_4d_dev(dims, L5_, 12, x.data_ptr(), q.data_ptr(), None, stream)
+    torch.cuda.synchronize()
+    ward_rhs = float(torch.sum(sm * q).item())      # Re <a, b> = sum of re*re + im*im
+    ward_lhs = float(np.sum(cmp_ + act_t[3] * cpp))
+    ms = 1e3 * float(np.mean(times))
+    kmean = {k: float(np.mean([d[k] for d in kts])) for k in kts[0]}
+    sb, wb, cb = smear_bytes(V, 12), wall_bytes(V, 12, L5_), corr_bytes(V, 12)
+    solve_bytes = sum(i["model_bytes"] for i in infos)
+    step_bytes = SMEAR_ITERS * sb + wb + solve_bytes + cb
+    value = step_bytes / (ms * 1e-3) / 1e9
+    smear_us = 1e3 * kmean["smear_ms"] / SMEAR_ITERS
+    achieved = sb / (smear_us * 1e-6) / 1e9
+    far = [t for t in range(T) if min((t - ts) % T, (ts - t) % T) >= 6]
+    cpu = None
+    if not args.no_cpu:
+        from oracle import sources as SRC
+        import oracle
+        small = (8, 8, 8, 16)
+        Us = I.random_links(small, EPS, GAUGE_SEED)
+        acts = oracle.Action(small, L5_, *act_t[:4])
+        Vs = int(np.prod(small))
+        t0 = time.perf_counter()
+        cols = []
+        for j in range(12):
+            e_ = SRC.gauss_smear(Us, SRC.point_source(small, (0, 0, 0, 0), j // 3, j % 3), SMEAR_SIGMA, SMEAR_ITERS)
+            cols.append(SRC.wall_source(acts, Us, e_))      # stands in for the solution: same size, same reads
+        with np.errstate(all="ignore"):                    # slices the stand-in leaves empty give 0/0
+            SRC.correlators(cols)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=round((SMEAR_ITERS * smear_bytes(Vs, 12) + wall_bytes(Vs, 12, L5_) + corr_bytes(Vs, 12))
+                               / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                   sample="the numpy oracle's source and sink side (12 columns smeared by %d steps, wall sources, "
+                          "correlators) on 8^3x16, L5=%d, %.2f s; the solve's CPU baseline is the mixed workload's"
+                          % (SMEAR_ITERS, L5_, dt))
+    out = {
+        "metric": "Moebius DWF dslash GB/s (% HBM peak); time to r=1e-10 solve, mixed vs FP64",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f16",
+        "data": "synthetic",
+        "config": {"workload": "m_res chain on %dx%dx%dx%d L5=%d M5=%g b5=%g c5=%g m_q=%g, exp(i0.25H) links: 12 "
+                               "point-source columns Gaussian-smeared (sigma=%g, %d steps), Moebius wall sources, "
+                               "mixed FP16 solve to 1e-10 (%s form), midpoint and wall correlators"
+                               % (X, Y, Z, T, L5_, act_t[0], act_t[1], act_t[2], act_t[3], SMEAR_SIGMA, SMEAR_ITERS,
+                                  FORM_NAMES[args.schur_form]),
+                   "name": "mres", "lattice": list(dims), "L5": L5_, "source_site": [xs, ys, zs, ts]},
+        "kernels": {"smear_us_per_step": round(smear_us, 1), "smear_GBps": round(achieved, 1),
+                    "wall_source_us": round(1e3 * kmean["wall_ms"], 1),
+                    "wall_source_GBps": round(wb / (kmean["wall_ms"] * 1e-3) / 1e9, 1),
+                    "correlators_us_incl_copy": round(1e3 * kmean["corr_ms"], 1),
+                    "solve_s": round(kmean["solve_ms"] / 1e3, 3),
+                    "solve_iters": max(i["iters"] for i in infos)},
+        "mres": {"mres_t": [float("%.6g" % v) for v in mres], "mres_far_mean": float(np.mean(mres[far])),
+                 "far_slices": "|t - t_src| >= 6", "ward_lhs": ward_lhs, "ward_rhs": ward_rhs,
+                 "ward_rel": abs(ward_lhs - ward_rhs) / abs(ward_rhs),
+                 "max_true_resid": max(i["true_resid"] for i in infos)},
+        "roofline": {"bound": "hbm", "kernel": "k_gauss_step (one smearing step, 12 vectors, FP64)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "model": "per site: 12 x (192 B read + 192 B written) + 3 spatial links (432 B)"},
+        "cpu_baseline": cpu,
+    }
+    M.mdwf_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -755,6 +923,9 @@ def main():
         return
     if args.workload == "flow":
         flow_main(args)
+        return
+    if args.workload == "mres":
+        mres_main(args)
         return
     global DIMS, L5, MASSES, GAUGE_SEED, SITE_SEED, GROUPS
     wl = WORKLOADS[args.workload]

@@ -281,6 +281,55 @@ mdwf_status mdwf_wilson_flow_dev(const mdwf_geometry *geom, double *U_dev, doubl
  * device gauge field (fixed-order reduction).  Synchronous on `stream`. */
 mdwf_status mdwf_plaquette_dev(const mdwf_geometry *geom, const double *U_dev, void *stream, double *plaq);
 
+/* ------------------------------------------------ sources and sinks
+ * The steps around the solves of a propagator (paper Sec. V: MDWF
+ * propagators from gauge-covariant Gaussian-smeared sources; Sec. III: the
+ * residual mass m_res from the midpoint and wall pseudoscalar correlators,
+ * with the Shamir midpoint density).  All fields are canonical FP64 device
+ * arrays, nvec of them back to back:
+ *   4D spinor  psi[t][z][y][x][spin][col]   (12 complex per site)
+ *   5D spinor  psi[s][t][z][y][x][spin][col]
+ * U_dev is a canonical gauge field (layout of mdwf_load_gauge).  Extents
+ * only need to be >= 1 here (no even-odd split).  Each call is asynchronous
+ * on `stream` (NULL = the null stream) unless stated; errors: ERR_ARG on a
+ * null pointer, a bad count or parameter, ERR_HIP / ERR_OOM from the runtime.
+ *
+ * mdwf_gauss_smear_dev: out = (1 + sigma^2/(4 niter) Delta)^niter in, with
+ *   the covariant spatial Laplacian
+ *   (Delta psi)(x) = sum_{i=x,y,z} U_i(x) psi(x+i) + U_i(x-i)^+ psi(x-i) - 2 psi(x),
+ *   periodic in space, each time slice on its own.  in and out must not
+ *   overlap; niter = 0 copies.  For niter >= 2 it allocates one scratch
+ *   field set and returns after the stream has finished it. */
+mdwf_status mdwf_gauss_smear_dev(const mdwf_geometry *geom, const double *U_dev, int nvec, const double *in_dev,
+                                 double *out_dev, double sigma, int niter, void *stream);
+
+/* mdwf_wall_source_dev: the 5D right-hand side whose solution of D5 x = b
+ *   carries the 4D quark propagator of the 4D source eta:
+ *     b = (1 - c5 D_W) Pbar eta,  (Pbar eta)_{L5-1} = P- eta, (Pbar eta)_0 = P+ eta,
+ *   all other slices zero (c5 = 0 gives the Shamir source).  The wall field
+ *   q = P- x_0 + P+ x_{L5-1} of the solution is then (D_eff^-1 - 1)/(1 - m_q) eta
+ *   with D_eff the 4D effective operator of D5.  Uses M5, c5 and L5 of act
+ *   (L5 >= 1) and the fermion time boundary of geom; b holds nvec 5D fields. */
+mdwf_status mdwf_wall_source_dev(const mdwf_geometry *geom, const mdwf_action *act, const double *U_dev, int nvec,
+                                 const double *eta_dev, double *b_dev, void *stream);
+
+/* mdwf_project_4d_dev: from nvec 5D fields x, the wall fields
+ *   q = P- x_0 + P+ x_{L5-1} into q_dev and, if mid_dev is not NULL (L5 even),
+ *   the midpoint fields Q = P- x_{L5/2} + P+ x_{L5/2-1} into mid_dev (4D). */
+mdwf_status mdwf_project_4d_dev(const mdwf_geometry *geom, int L5, int nvec, const double *x_dev, double *q_dev,
+                                double *mid_dev, void *stream);
+
+/* mdwf_mres_correlators_dev: for each time slice t (host arrays of T):
+ *   c_pp[t] = sum over the slice's sites, spins, colours and the nvec
+ *             solutions of |q|^2 (the pseudoscalar correlator of a source's
+ *             spin-colour columns),
+ *   c_mp[t] = the same of |Q|^2 (the midpoint correlator),
+ *   mres[t] = c_mp[t] / c_pp[t]   (NaN or inf where c_pp[t] = 0).
+ *   L5 even >= 2.  Fixed-order reductions (deterministic).  Synchronous;
+ *   allocates a small partial-sum buffer. */
+mdwf_status mdwf_mres_correlators_dev(const mdwf_geometry *geom, int L5, int nvec, const double *x_dev, void *stream,
+                                      double *c_pp, double *c_mp, double *mres);
+
 /* ------------------------------------------------------------ serving
  * A request server for many solves of D5 x = b (the paper computes
  * propagators for several ensembles, masses and sources, Sec. III): gauge

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdwf.so")
-SOURCES = ["api.hip", "dslash.hip", "blas.hip", "solver.hip", "serve.hip", "flow.hip"]
+SOURCES = ["api.hip", "dslash.hip", "blas.hip", "solver.hip", "serve.hip", "flow.hip", "source.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

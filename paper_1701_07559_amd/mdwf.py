@@ -130,6 +130,11 @@ def _load():
         "mdwf_wilson_flow": ([C.POINTER(mdwf_geometry), ip, vp, dp, ip, C.POINTER(dp)], ip),
         "mdwf_wilson_flow_dev": ([C.POINTER(mdwf_geometry), vp, dp, ip, vp, C.POINTER(dp)], ip),
         "mdwf_plaquette_dev": ([C.POINTER(mdwf_geometry), vp, vp, C.POINTER(dp)], ip),
+        "mdwf_gauss_smear_dev": ([C.POINTER(mdwf_geometry), vp, ip, vp, vp, dp, ip, vp], ip),
+        "mdwf_wall_source_dev": ([C.POINTER(mdwf_geometry), C.POINTER(mdwf_action), vp, ip, vp, vp, vp], ip),
+        "mdwf_project_4d_dev": ([C.POINTER(mdwf_geometry), ip, ip, vp, vp, vp, vp], ip),
+        "mdwf_mres_correlators_dev": ([C.POINTER(mdwf_geometry), ip, ip, vp, vp, C.POINTER(dp), C.POINTER(dp),
+                                       C.POINTER(dp)], ip),
         "mdwf_server_create": ([ip, C.c_size_t, ip, C.POINTER(vp)], ip),
         "mdwf_server_destroy": ([vp], None),
         "mdwf_server_last_error": ([vp], C.c_char_p),
@@ -322,6 +327,45 @@ def mdwf_plaquette_dev(dims, U_ptr, stream=None):
     return p.value
 
 
+def _geom(dims, antiperiodic_t=True):
+    return mdwf_geometry(*[int(d) for d in dims], int(bool(antiperiodic_t)))
+
+
+def _raise(st):
+    if st != MDWF_OK:
+        raise MdwfError(st, mdwf_last_error(None))
+
+
+def mdwf_gauss_smear_dev(dims, U_ptr, nvec, in_ptr, out_ptr, sigma, niter, stream=None):
+    """Gaussian-smear nvec consecutive device canonical 4D spinor fields."""
+    _raise(lib.mdwf_gauss_smear_dev(C.byref(_geom(dims)), int(U_ptr), int(nvec), int(in_ptr), int(out_ptr),
+                                    float(sigma), int(niter), stream))
+
+
+def mdwf_wall_source_dev(dims, action, U_ptr, nvec, eta_ptr, b_ptr, antiperiodic_t=True, stream=None):
+    """5D right-hand sides (1 - c5 D_W) Pbar eta of nvec device 4D sources;
+    action = (M5, b5, c5, mq, L5)."""
+    M5, b5, c5, mq, L5 = action
+    a = mdwf_action(float(M5), float(b5), float(c5), float(mq), int(L5))
+    _raise(lib.mdwf_wall_source_dev(C.byref(_geom(dims, antiperiodic_t)), C.byref(a), int(U_ptr), int(nvec),
+                                    int(eta_ptr), int(b_ptr), stream))
+
+
+def mdwf_project_4d_dev(dims, L5, nvec, x_ptr, q_ptr, mid_ptr=None, stream=None):
+    """Wall (and optionally midpoint) 4D fields of nvec device 5D fields."""
+    _raise(lib.mdwf_project_4d_dev(C.byref(_geom(dims)), int(L5), int(nvec), int(x_ptr), int(q_ptr),
+                                   int(mid_ptr) if mid_ptr else None, stream))
+
+
+def mdwf_mres_correlators_dev(dims, L5, nvec, x_ptr, stream=None):
+    """(C_PP, C_mp, m_res) per time slice, summed over nvec device 5D solutions."""
+    T = int(dims[3])
+    cpp, cmp_, mres = (C.c_double * T)(), (C.c_double * T)(), (C.c_double * T)()
+    _raise(lib.mdwf_mres_correlators_dev(C.byref(_geom(dims)), int(L5), int(nvec), int(x_ptr), stream, cpp, cmp_,
+                                         mres))
+    return np.array(cpp[:]), np.array(cmp_[:]), np.array(mres[:])
+
+
 class Server:
     """Request server (mdwf_server_*): resident gauge fields, solves admitted
     by device footprint and run concurrently on worker streams.  Host arrays
@@ -395,6 +439,7 @@ def exported_symbols():
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
             "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
             "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
-            "mdwf_plaquette_dev", "mdwf_server_create", "mdwf_server_destroy",
+            "mdwf_plaquette_dev", "mdwf_gauss_smear_dev", "mdwf_wall_source_dev", "mdwf_project_4d_dev",
+            "mdwf_mres_correlators_dev", "mdwf_server_create", "mdwf_server_destroy",
             "mdwf_server_last_error", "mdwf_server_add_field", "mdwf_server_submit", "mdwf_server_wait",
             "mdwf_server_stats"]

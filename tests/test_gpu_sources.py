@@ -1,0 +1,219 @@
+"""Source and sink kernels on the GPU (mdwf_gauss_smear_dev,
+mdwf_wall_source_dev, mdwf_project_4d_dev, mdwf_mres_correlators_dev)
+against the FP64 oracle (oracle/sources.py): every element on small and
+ragged lattices; the chain smeared source -> wall source -> solve ->
+correlators against the oracle's chain; and at the 24^3 x 64, L5 = 8
+benchmark size the properties that hold at any size (the smearing is
+Hermitian and keeps time slices apart, the integrated axial Ward identity
+holds to the solve's tolerance)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sources as SRC
+from paper_1701_07559_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1701_07559_amd import mdwf
+    try:
+        ctx = mdwf.mdwf_create((2, 2, 2, 2))
+    except mdwf.MdwfError as e:
+        pytest.skip("no HIP device: %s" % e)
+    mdwf.mdwf_destroy(ctx)
+    return mdwf
+
+
+def dev(a):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128).view(np.float64).copy()).to("cuda:0")
+    torch.cuda.synchronize()
+    return t
+
+
+def host(t, shape):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.complex128).reshape(shape)
+
+
+def empty(shape):
+    import torch
+    return torch.zeros(int(np.prod(shape)) * 2, dtype=torch.float64, device="cuda:0")
+
+
+def spinors(dims, n, seed):
+    return np.stack([I.gaussian_source(dims, 1, seed + k)[0] for k in range(n)])
+
+
+@pytest.mark.parametrize("dims,nvec,sigma,niter", [((4, 4, 4, 8), 2, 2.5, 5), ((5, 3, 4, 6), 3, 1.7, 2),
+                                                   ((6, 4, 2, 2), 1, 3.0, 1), ((3, 5, 7, 3), 2, 4.0, 12)])
+def test_gauss_smear_matches_oracle(M, dims, nvec, sigma, niter):
+    U = I.random_links(dims, 0.3, 101)
+    psi = spinors(dims, nvec, 102)
+    Ud, ind, outd = dev(U), dev(psi), empty(psi.shape)
+    outd.fill_(7.0)
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), nvec, ind.data_ptr(), outd.data_ptr(), sigma, niter)
+    out = host(outd, psi.shape)
+    for k in range(nvec):
+        ref = SRC.gauss_smear(U, psi[k], sigma, niter)
+        assert np.abs(out[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.array_equal(host(ind, psi.shape), psi)
+
+
+def test_gauss_smear_copy_and_errors(M):
+    dims = (4, 2, 2, 4)
+    U = I.random_links(dims, 0.3, 103)
+    psi = spinors(dims, 2, 104)
+    Ud, ind, outd = dev(U), dev(psi), empty(psi.shape)
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), 2, ind.data_ptr(), outd.data_ptr(), 2.0, 0)
+    assert np.array_equal(host(outd, psi.shape), psi)
+    for bad in [dict(nvec=0), dict(niter=-1), dict(sigma=-1.0), dict(sigma=float("nan")), dict(overlap=True)]:
+        with pytest.raises(M.MdwfError) as e:
+            out_ptr = ind.data_ptr() + 16 if bad.get("overlap") else outd.data_ptr()
+            M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), bad.get("nvec", 2), ind.data_ptr(), out_ptr,
+                                   bad.get("sigma", 2.0), bad.get("niter", 3))
+        assert e.value.status == M.MDWF_ERR_ARG
+
+
+@pytest.mark.parametrize("dims,L5,b5,c5,ap", [((4, 4, 4, 8), 8, 1.5, 0.5, True), ((5, 3, 4, 6), 4, 1.25, 0.25, True),
+                                              ((4, 2, 6, 4), 6, 1.0, 0.0, False), ((3, 3, 3, 1), 1, 2.0, 1.0, True),
+                                              ((4, 4, 2, 2), 2, 1.5, 0.5, True)])
+def test_wall_source_matches_oracle(M, dims, L5, b5, c5, ap):
+    U = I.random_links(dims, 0.3, 105)
+    eta = spinors(dims, 3, 106)
+    act = oracle.Action(dims, L5, M5=1.3, b5=b5, c5=c5, mq=0.03, antiperiodic_t=ap)
+    Ud, ed, bd = dev(U), dev(eta), empty((3,) + act.shape5)
+    bd.fill_(7.0)                            # every element must be written
+    M.mdwf_wall_source_dev(dims, (1.3, b5, c5, 0.03, L5), Ud.data_ptr(), 3, ed.data_ptr(), bd.data_ptr(),
+                           antiperiodic_t=ap)
+    out = host(bd, (3,) + act.shape5)
+    for k in range(3):
+        ref = SRC.wall_source(act, U, eta[k])
+        assert np.abs(out[k] - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_projections_and_correlators_match_oracle(M):
+    dims, L5, n = (5, 3, 4, 6), 6, 3
+    x5 = np.stack([I.gaussian_source(dims, L5, 107 + k) for k in range(n)])
+    xd = dev(x5)
+    q, mid = empty((n, 6, 4, 3, 5, 4, 3)), empty((n, 6, 4, 3, 5, 4, 3))
+    M.mdwf_project_4d_dev(dims, L5, n, xd.data_ptr(), q.data_ptr(), mid.data_ptr())
+    qh, mh = host(q, (n, 6, 4, 3, 5, 4, 3)), host(mid, (n, 6, 4, 3, 5, 4, 3))
+    for k in range(n):
+        assert np.array_equal(qh[k], SRC.project_wall(x5[k]))
+        assert np.array_equal(mh[k], SRC.project_mid(x5[k]))
+    cpp, cmp_, mres = M.mdwf_mres_correlators_dev(dims, L5, n, xd.data_ptr())
+    rpp, rmp, rres = SRC.correlators(list(x5))
+    for a, b in ((cpp, rpp), (cmp_, rmp), (mres, rres)):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    # deterministic, and the wall projection alone works for odd L5
+    assert all(np.array_equal(a, b) for a, b in zip((cpp, cmp_, mres),
+                                                     M.mdwf_mres_correlators_dev(dims, L5, n, xd.data_ptr())))
+    M.mdwf_project_4d_dev(dims, 5, 1, xd.data_ptr(), q.data_ptr())
+    with pytest.raises(M.MdwfError):
+        M.mdwf_project_4d_dev(dims, 5, 1, xd.data_ptr(), q.data_ptr(), mid.data_ptr())
+    with pytest.raises(M.MdwfError):
+        M.mdwf_mres_correlators_dev(dims, 5, 1, xd.data_ptr())
+
+
+def _chain_gpu(M, dims, U, act_t, site, smear, opts):
+    """12 columns: smear the point source, build the 5D sources, solve,
+    return the correlators, the wall fields and the smeared sources."""
+    import torch
+    M5, b5, c5, mq, L5 = act_t
+    X, Y, Z, T = dims
+    shape4 = (T, Z, Y, X, 4, 3)
+    eta = np.stack([SRC.point_source(dims, site, j // 3, j % 3) for j in range(12)])
+    Ud, ed = dev(U), dev(eta)
+    sd = empty(eta.shape)
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), 12, ed.data_ptr(), sd.data_ptr(), *smear)
+    n5 = L5 * int(np.prod(shape4))
+    bd, xd = empty((12, n5)), empty((12, n5))
+    M.mdwf_wall_source_dev(dims, act_t, Ud.data_ptr(), 12, sd.data_ptr(), bd.data_ptr())
+    torch.cuda.synchronize()                 # the solve runs on the context's own stream
+    ctx = M.mdwf_create(dims)
+    try:
+        M.mdwf_set_action(ctx, *act_t)
+        M.mdwf_load_gauge_dev(ctx, Ud.data_ptr())
+        st, infos = M.mdwf_solve_dev(ctx, [bd.data_ptr() + 16 * n5 * k for k in range(12)],
+                                     [xd.data_ptr() + 16 * n5 * k for k in range(12)], opts=opts)
+        assert st == M.MDWF_OK and max(i["true_resid"] for i in infos) <= opts["tol"]
+    finally:
+        M.mdwf_destroy(ctx)
+    cpp, cmp_, mres = M.mdwf_mres_correlators_dev(dims, L5, 12, xd.data_ptr())
+    qd = empty(eta.shape)
+    M.mdwf_project_4d_dev(dims, L5, 12, xd.data_ptr(), qd.data_ptr())
+    return (cpp, cmp_, mres), host(qd, eta.shape), host(sd, eta.shape), xd, sd
+
+
+def _ward(corr, mq, q, src):
+    cpp, cmp_, _ = corr
+    lhs = float(np.sum(cmp_ + mq * cpp))
+    rhs = float(sum(np.vdot(src[j], q[j]).real for j in range(len(q))))
+    return lhs, rhs
+
+
+CHAIN = dict(dims=(4, 4, 4, 4), act=(1.3, 1.5, 0.5, 0.05, 8), site=(3, 1, 2, 0), smear=(2.0, 6), seed=108)
+
+
+@pytest.fixture(scope="module")
+def oracle_chain():
+    """The oracle's 12-column chain (smear, wall source, FP64 CGLS to 1e-12,
+    correlators) for CHAIN, computed once (about 10 s on one core)."""
+    dims, act_t = CHAIN["dims"], CHAIN["act"]
+    U = I.random_links(dims, 0.3, CHAIN["seed"])
+    act = oracle.Action(dims, act_t[4], *act_t[:4])
+    cols, srcs = [], []
+    for j in range(12):
+        e = SRC.gauss_smear(U, SRC.point_source(dims, CHAIN["site"], j // 3, j % 3), *CHAIN["smear"])
+        x, info = oracle.solve(act, U, SRC.wall_source(act, U, e), tol=1e-12)
+        assert info["status"] == 0
+        cols.append(x)
+        srcs.append(e)
+    return U, srcs, SRC.correlators(cols)
+
+
+@pytest.mark.parametrize("inner", ["f64", "f16"])
+def test_source_solve_correlator_chain_matches_oracle(M, oracle_chain, inner):
+    U, srcs, ref = oracle_chain
+    act_t = CHAIN["act"]
+    opts = dict(tol=1e-11, inner=M.MDWF_F64 if inner == "f64" else M.MDWF_F16, schur_form=2 if inner == "f16" else 0)
+    corr, q, src, _, _ = _chain_gpu(M, CHAIN["dims"], U, act_t, CHAIN["site"], CHAIN["smear"], opts)
+    for j in range(12):
+        assert np.abs(srcs[j] - src[j]).max() <= 1e-13 * np.abs(srcs[j]).max()
+    for a, b in zip(corr, ref):
+        assert np.abs(a - b).max() <= 1e-7 * np.abs(b).max()
+    lhs, rhs = _ward(corr, act_t[3], q, src)
+    assert abs(lhs - rhs) <= 1e-8 * abs(rhs)
+
+
+def test_benchmark_size_properties(M):
+    """24^3 x 64, L5 = 8, the benchmark's field and action: smearing is
+    Hermitian and keeps a source's time slice, and the 12-column chain with
+    the mixed FP16 solve satisfies the integrated axial Ward identity."""
+    import torch
+    dims, L5 = (24, 24, 24, 64), 8
+    X, Y, Z, T = dims
+    U = I.random_links(dims, 0.25, 103, workers=8)
+    Ud = dev(U)
+    a, b = spinors(dims, 2, 109)
+    a[:5] = 0.0
+    a[6:] = 0.0                              # a lives on time slice 5 only
+    ad, bd, Ka, Kb = dev(a), dev(b), empty(a.shape), empty(b.shape)
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), 1, ad.data_ptr(), Ka.data_ptr(), 4.0, 30)
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), 1, bd.data_ptr(), Kb.data_ptr(), 4.0, 30)
+    Kah, Kbh = host(Ka, a.shape), host(Kb, b.shape)
+    assert np.abs(Kah[:5]).max() == 0.0 and np.abs(Kah[6:]).max() == 0.0
+    assert abs(np.vdot(a, Kbh) - np.vdot(Kah, b)) <= 1e-12 * abs(np.vdot(a, Kbh))
+    del Ka, Kb, ad, bd
+    torch.cuda.empty_cache()
+    act_t = (1.3, 1.5, 0.5, 0.0102, L5)
+    corr, q, src, _, _ = _chain_gpu(M, dims, U, act_t, (17, 3, 11, 5), (4.0, 30),
+                                    dict(tol=1e-11, inner=M.MDWF_F16, schur_form=2))
+    lhs, rhs = _ward(corr, act_t[3], q, src)
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (lhs, rhs)
+    assert np.all(corr[0] > 0) and np.all(corr[1] > 0)

@@ -16,7 +16,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_1701_07559_amd", "csrc")
-SOURCES = ["api.hip", "dslash.hip", "blas.hip", "solver.hip", "serve.hip", "flow.hip"]
+SOURCES = ["api.hip", "dslash.hip", "blas.hip", "solver.hip", "serve.hip", "flow.hip", "source.hip"]
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
 
 
