@@ -128,6 +128,14 @@ __device__ __forceinline__ h2 splat_h2(float f) {
 }
 // a.x b.x + a.y b.y + c
 __device__ __forceinline__ float dot2(h2 a, h2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+// a.x b.x + a.y b.y: the first term of a chain, in the three-operand encoding
+// with an inline zero (the builtin with c = 0 becomes a register clear plus
+// the accumulating form, one more VALU instruction per chain)
+__device__ __forceinline__ float dot2_first(h2 a, h2 b) {
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // From z = u + SGN X d (X = i for TI, else 1) the two packed operands that
 // make U z (FWD) or U^+ z a sum of dot2 products with the link element:
@@ -180,9 +188,10 @@ __device__ __forceinline__ void su3_mul_h(const h2 U[9], const h2 z1[6], const h
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            float re = 0.f, im = 0.f;
+            const h2 u0 = FWD ? U[a * 3] : U[a];
+            float re = dot2_first(u0, z1[sp * 3]), im = dot2_first(u0, z2[sp * 3]);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
+            for (int b = 1; b < 3; ++b) {
                 const h2 u = FWD ? U[a * 3 + b] : U[b * 3 + a];
                 re = dot2(u, z1[sp * 3 + b], re);
                 im = dot2(u, z2[sp * 3 + b], im);
@@ -575,9 +584,11 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     nb.fp1 = (s == L5 - 1) ? -mq : R(1);
 
     const void* in = at_rhs(a.in, a.stride, rhs);
+    // -0 is an exact additive identity, so the first direction's sums into
+    // res compile to plain moves (+0 would need its own register clears)
     cx<R> res[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) res[c] = {R(0), R(0)};
+    for (int c = 0; c < 12; ++c) res[c] = {R(-0.0), R(-0.0)};
 
     // neighbours of the output site (used only by valid lanes)
     const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
@@ -664,11 +675,13 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
         for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = res[c];
         __syncthreads();
         if (valid) {
-            cx<R> o[12];
-#pragma unroll
-            for (int c = 0; c < 12; ++c) o[c] = {R(0), R(0)};
             const int tbase = tid - s;
-            for (int k = 0; k < L5; ++k) {
+            // k = 0 (C^0 = 1) starts the sums
+            cx<R> o[12];
+            const R m0 = R(cf.m[0]);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) o[c] = m0 * sh[c * kBlock + tid];
+            for (int k = 1; k < L5; ++k) {
                 const R mk = R(cf.m[k]);
                 // C^k on P+ reads slice s-k, on P- slice s+k (adjoint: swapped)
                 int su = (TR::epi == 1) ? s - k : s + k;
@@ -701,18 +714,18 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     if constexpr (TR::cen == 4 || TR::cen == 5) {
         cx<R>* sh = reinterpret_cast<cx<R>*>(smem);
         cx<R> cv[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) cv[c] = {R(0), R(0)};
-        if (valid) Field<P>::load(at_rhs(a.centre, a.stride, rhs), g.Vh, i * L5 + s, cv);
+        // lanes past the lattice load site 0 (in bounds; no valid lane reads them)
+        Field<P>::load(at_rhs(a.centre, a.stride, rhs), g.Vh, valid ? i * L5 + s : 0, cv);
         if constexpr (LM == 1) __syncthreads();   // every wave is past the link stage
 #pragma unroll
         for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = cv[c];
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 12; ++c) cd[c] = {R(0), R(0)};
         if (valid) {
             const int tbase = tid - s;
-            for (int k = 0; k < L5; ++k) {
+            const R w0 = R(cf.w[0]);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) cd[c] = w0 * cv[c];   // k = 0 starts the sums
+            for (int k = 1; k < L5; ++k) {
                 const R wk = R(cf.w[k]);
                 // C^k on P+ reads slice s-k, on P- slice s+k (adjoint: swapped)
                 int su = (TR::cen == 4) ? s - k : s + k;
