@@ -325,7 +325,7 @@ mdwf_status mdwf_project_4d_dev(const mdwf_geometry *geom, int L5, int nvec, con
  *             spin-colour columns),
  *   c_mp[t] = the same of |Q|^2 (the midpoint correlator),
  *   mres[t] = c_mp[t] / c_pp[t]   (NaN or inf where c_pp[t] = 0).
- *   L5 even >= 2.  Fixed-order reductions (deterministic).  Synchronous;
+ *   L5 even >= 2, T <= 65535.  Fixed-order reductions (deterministic).  Synchronous;
  *   allocates a small partial-sum buffer. */
 mdwf_status mdwf_mres_correlators_dev(const mdwf_geometry *geom, int L5, int nvec, const double *x_dev, void *stream,
                                       double *c_pp, double *c_mp, double *mres);

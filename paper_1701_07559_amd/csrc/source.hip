@@ -364,16 +364,14 @@ mdwf_status mdwf_gauss_smear_dev(const mdwf_geometry* geom, const double* U_dev,
     const char* lo_in = reinterpret_cast<const char*>(in_dev);
     const char* lo_out = reinterpret_cast<const char*>(out_dev);
     if (lo_in < lo_out + bytes && lo_out < lo_in + bytes) return fail(nullptr, MDWF_ERR_ARG, "in and out overlap");
+    if (double(ntot) * 4.0 >= double(1u << 31))
+        return fail(nullptr, MDWF_ERR_ARG, "nvec x sites too large for one smearing launch");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (niter == 0)
         return hip_check(nullptr, hipMemcpyAsync(out_dev, in_dev, bytes, hipMemcpyDeviceToDevice, st), "smear copy");
     double2* tmp = nullptr;
     if (niter > 1 && (s = hip_check(nullptr, hipMalloc(&tmp, bytes), "smearing buffer"))) return s;
     const double kappa = sigma * sigma / (4.0 * niter);
-    if (double(ntot) * 4.0 >= double(1u << 31)) {
-        if (tmp) (void)hipFree(tmp);
-        return fail(nullptr, MDWF_ERR_ARG, "nvec x sites too large for one smearing launch");
-    }
     SmearIdx ix;
     ix.G = uint32_t(4 * nvec);
     ix.fG = FastDiv(ix.G);
@@ -454,6 +452,7 @@ mdwf_status mdwf_mres_correlators_dev(const mdwf_geometry* geom, int L5, int nve
     if (s) return s;
     if (!x_dev || !c_pp || !c_mp || !mres) return fail(nullptr, MDWF_ERR_ARG, "null pointer");
     if (nvec < 1 || L5 < 2 || L5 % 2) return fail(nullptr, MDWF_ERR_ARG, "need nvec >= 1 and an even L5 >= 2");
+    if (geom->T > 65535) return fail(nullptr, MDWF_ERR_ARG, "T > 65535");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int T = geom->T;
     const long nspat = long(geom->X) * geom->Y * geom->Z, nsites = nspat * T;

@@ -79,3 +79,45 @@ def test_server_null_and_argument_errors_without_device():
     assert mdwf.lib.mdwf_server_wait(None, 1, None, None) == mdwf.MDWF_ERR_ARG
     assert mdwf.lib.mdwf_server_add_field(None, None, None, None) == mdwf.MDWF_ERR_ARG
     mdwf.lib.mdwf_server_destroy(None)   # ignored
+
+
+def test_source_flow_entry_points_reject_bad_arguments_without_device():
+    """The source/sink and flow entry points validate every argument before
+    any HIP call, so these run without a GPU."""
+    from paper_1701_07559_amd import mdwf
+    L = mdwf.lib
+    ARG = mdwf.MDWF_ERR_ARG
+    g = mdwf.mdwf_geometry(4, 4, 4, 8, 1)
+    bad = mdwf.mdwf_geometry(4, 0, 4, 8, 1)
+    buf = (C.c_double * 64)()
+    p = C.cast(buf, C.c_void_p)
+    q = C.c_void_p(C.addressof(buf) + (1 << 20))   # a distinct address, never dereferenced
+    a = mdwf.mdwf_action(1.3, 1.5, 0.5, 0.05, 8)
+    # smearing: geometry, nulls, counts, width, overlap
+    assert L.mdwf_gauss_smear_dev(None, p, 1, p, q, 2.0, 3, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(bad), p, 1, p, q, 2.0, 3, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(g), None, 1, p, q, 2.0, 3, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(g), p, 0, p, q, 2.0, 3, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(g), p, 1, p, q, -1.0, 3, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(g), p, 1, p, q, float("inf"), 3, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(g), p, 1, p, q, 2.0, -1, None) == ARG
+    assert L.mdwf_gauss_smear_dev(C.byref(g), p, 1, p, p, 2.0, 3, None) == ARG
+    assert "overlap" in mdwf.mdwf_last_error(None)
+    # wall source
+    assert L.mdwf_wall_source_dev(C.byref(g), None, p, 1, p, q, None) == ARG
+    assert L.mdwf_wall_source_dev(C.byref(g), C.byref(a), p, 0, p, q, None) == ARG
+    a0 = mdwf.mdwf_action(1.3, 1.5, 0.5, 0.05, 0)
+    assert L.mdwf_wall_source_dev(C.byref(g), C.byref(a0), p, 1, p, q, None) == ARG
+    # projections and correlators: odd L5 has no midpoint
+    assert L.mdwf_project_4d_dev(C.byref(g), 5, 1, p, q, q, None) == ARG
+    assert L.mdwf_project_4d_dev(C.byref(g), 8, 0, p, q, None, None) == ARG
+    d = (C.c_double * 8)()
+    assert L.mdwf_mres_correlators_dev(C.byref(g), 5, 1, p, None, d, d, d) == ARG
+    assert L.mdwf_mres_correlators_dev(C.byref(g), 8, 1, p, None, None, d, d) == ARG
+    big_t = mdwf.mdwf_geometry(1, 1, 1, 70000, 1)
+    assert L.mdwf_mres_correlators_dev(C.byref(big_t), 8, 1, p, None, d, d, d) == ARG
+    # flow
+    assert L.mdwf_wilson_flow_dev(C.byref(g), p, 0.0, 3, None, None) == ARG
+    assert L.mdwf_wilson_flow_dev(C.byref(g), p, 0.01, -1, None, None) == ARG
+    assert L.mdwf_wilson_flow_dev(C.byref(mdwf.mdwf_geometry(4, 1, 4, 4, 0)), p, 0.01, 1, None, None) == ARG
+    assert L.mdwf_plaquette_dev(C.byref(g), None, None, d) == ARG
