@@ -52,6 +52,24 @@ int main() {
     EXPECT(mdwf_get_tune(nullptr, MDWF_F16, tune) == MDWF_ERR_ARG);
     EXPECT(mdwf_op_model(nullptr, MDWF_OP_SCHUR, MDWF_F32, &d, &f) == MDWF_ERR_ARG);
 
+    // sources, sinks and flow: argument errors are found before any HIP call
+    double buf[16] = {0}, cpp[8], cmp[8], mres[8], plaq[2];
+    mdwf_geometry flat{4, 4, 0, 8, 1}, tall{1, 1, 1, 70000, 1};
+    EXPECT(mdwf_gauss_smear_dev(nullptr, buf, 1, buf, buf + 8, 2.0, 3, nullptr) == MDWF_ERR_ARG);
+    EXPECT(mdwf_gauss_smear_dev(&flat, buf, 1, buf, buf + 8, 2.0, 3, nullptr) == MDWF_ERR_ARG);
+    EXPECT(mdwf_gauss_smear_dev(&good, buf, 1, buf, buf + 1, 2.0, 3, nullptr) == MDWF_ERR_ARG);   // overlap
+    EXPECT(mdwf_gauss_smear_dev(&good, buf, 0, buf, buf + 8, 2.0, 3, nullptr) == MDWF_ERR_ARG);
+    EXPECT(mdwf_wall_source_dev(&good, nullptr, buf, 1, buf, buf + 8, nullptr) == MDWF_ERR_ARG);
+    mdwf_action l0 = act;
+    l0.L5 = 0;
+    EXPECT(mdwf_wall_source_dev(&good, &l0, buf, 1, buf, buf + 8, nullptr) == MDWF_ERR_ARG);
+    EXPECT(mdwf_project_4d_dev(&good, 5, 1, buf, buf + 8, buf + 4, nullptr) == MDWF_ERR_ARG);
+    EXPECT(mdwf_mres_correlators_dev(&good, 7, 1, buf, nullptr, cpp, cmp, mres) == MDWF_ERR_ARG);
+    EXPECT(mdwf_mres_correlators_dev(&tall, 8, 1, buf, nullptr, cpp, cmp, mres) == MDWF_ERR_ARG);
+    EXPECT(mdwf_wilson_flow_dev(&good, buf, -1.0, 2, nullptr, plaq) == MDWF_ERR_ARG);
+    EXPECT(mdwf_wilson_flow(&flat, 0, buf, 0.01, 2, plaq) == MDWF_ERR_ARG);
+    EXPECT(mdwf_plaquette_dev(&good, nullptr, nullptr, plaq) == MDWF_ERR_ARG);
+
     // a context: on a host with a device the state and argument errors
     // follow; without one, creation reports the HIP error
     const mdwf_status cs = mdwf_create(&good, 0, nullptr, &c);
