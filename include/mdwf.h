@@ -111,7 +111,8 @@ typedef struct {
 } mdwf_geometry;
 
 /* Action parameters (paper Sec. II / III.A): requires b5 > c5 >= 0,
- * 0 <= mq <= 1, 1 <= L5 <= 32, 0 < M5 < 2. */
+ * 0 <= mq <= 1, 1 <= L5 <= 32, 0 < M5 < 2, and L5 x V/2 < 268435456 (the
+ * kernels address a field block with 32-bit byte offsets). */
 typedef struct {
     double M5, b5, c5, mq;
     int L5;

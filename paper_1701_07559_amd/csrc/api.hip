@@ -476,6 +476,10 @@ mdwf_status mdwf_set_action(mdwf_ctx* c, const mdwf_action* a) {
     if (!c) return fail(nullptr, MDWF_ERR_ARG, "null context");
     if (!a) return fail(c, MDWF_ERR_ARG, "action is null");
     if (a->L5 < 1 || a->L5 > kMaxL5) return fail(c, MDWF_ERR_ARG, "L5 must be in [1, 32]");
+    // the kernels address a 16-byte element of a field block with a 32-bit
+    // byte offset (16 Vh bytes per block)
+    if (double(c->geo.Vh4) * a->L5 * 16.0 >= 4294967296.0)
+        return fail(c, MDWF_ERR_ARG, "V/2 x L5 too large for 32-bit field offsets (V/2 x L5 < 268435456)");
     if (!(a->c5 >= 0.0) || !(a->b5 > a->c5)) return fail(c, MDWF_ERR_ARG, "need b5 > c5 >= 0");
     if (!(a->mq >= 0.0 && a->mq <= 1.0)) return fail(c, MDWF_ERR_ARG, "need 0 <= mq <= 1");
     if (!(a->M5 > 0.0 && a->M5 < 2.0)) return fail(c, MDWF_ERR_ARG, "need 0 < M5 < 2");

@@ -681,3 +681,17 @@ def test_solver_failure_paths(M, cfg1):
         assert e.value.status == M.MDWF_ERR_ARG
     finally:
         M.mdwf_destroy(ctx)
+
+
+def test_action_rejects_fields_beyond_32bit_offsets(M):
+    """The kernels address a field block with 32-bit byte offsets, so an
+    action whose L5 x V/2 reaches 2^28 is refused (48^3 x 160 holds
+    V/2 = 8847360 sites: L5 = 32 is over, L5 = 30 under)."""
+    ctx = M.mdwf_create((48, 48, 48, 160))
+    try:
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_set_action(ctx, 1.3, 1.5, 0.5, 0.05, 32)
+        assert e.value.status == M.MDWF_ERR_ARG and "32-bit" in str(e.value)
+        M.mdwf_set_action(ctx, 1.3, 1.5, 0.5, 0.05, 30)
+    finally:
+        M.mdwf_destroy(ctx)
