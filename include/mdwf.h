@@ -331,6 +331,16 @@ mdwf_status mdwf_project_4d_dev(const mdwf_geometry *geom, int L5, int nvec, con
 mdwf_status mdwf_mres_correlators_dev(const mdwf_geometry *geom, int L5, int nvec, const double *x_dev, void *stream,
                                       double *c_pp, double *c_mp, double *mres);
 
+/* mdwf_pion_correlator_dev: c[t] (host, T values) = sum over the slice's
+ *   sites, spins, colours and the nvec 4D fields q of |q|^2: the
+ *   pseudoscalar correlator of a source's columns with any sink, e.g. the
+ *   wall fields of mdwf_project_4d_dev as they are (then c equals c_pp
+ *   above, bit for bit) or after mdwf_gauss_smear_dev (a smeared sink).
+ *   T <= 65535.  Fixed-order reductions.  Synchronous; allocates a small
+ *   partial-sum buffer. */
+mdwf_status mdwf_pion_correlator_dev(const mdwf_geometry *geom, int nvec, const double *q_dev, void *stream,
+                                     double *c);
+
 /* ------------------------------------------------------------ serving
  * A request server for many solves of D5 x = b (the paper computes
  * propagators for several ensembles, masses and sources, Sec. III): gauge

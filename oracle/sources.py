@@ -29,7 +29,9 @@ What is computed:
       C_PP(t) = sum_{x in t} sum_cols |q|^2,   C_mp(t) = sum_{x in t} sum_cols |Q|^2,
       m_res(t) = C_mp(t) / C_PP(t).
   Both are products of a propagator with its gamma5-adjoint, so they are
-  sums of squared moduli.
+  sums of squared moduli.  The same sum over any 4D fields (a propagator's
+  columns with the sink smeared, say) is the pseudoscalar correlator of
+  those fields.
 
 Chiral basis, g5 = diag(1, 1, -1, -1): P+ keeps spins 0, 1 and P- spins 2, 3.
 Layouts: links U[t, z, y, x, mu, a, b], 4D spinors [t, z, y, x, spin, colour],
@@ -102,6 +104,16 @@ def correlators(x5_cols):
         cpp = cpp + np.sum(np.abs(q) ** 2, axis=(1, 2, 3, 4, 5))
         cmp_ = cmp_ + np.sum(np.abs(Q) ** 2, axis=(1, 2, 3, 4, 5))
     return cpp, cmp_, cmp_ / cpp
+
+
+def pion_correlator(fields4d):
+    """sum over each time slice's sites, spins and colours, and over the
+    given 4D fields (the columns of one source, at the sink as they are or
+    smeared), of |q|^2: the pseudoscalar correlator of those columns."""
+    c = 0.0
+    for q in fields4d:
+        c = c + np.sum(np.abs(q) ** 2, axis=(1, 2, 3, 4, 5))
+    return c
 
 
 def point_source(dims, site, spin, colour):

@@ -321,6 +321,43 @@ __global__ void __launch_bounds__(kSrcBlock) k_corr_partial(const double2* x5, d
     }
 }
 
+// the same sums of |q|^2 over nvec 4D fields (any sink): grid (nblk, T),
+// one partial per block and time slice, in the order of k_corr_partial
+__global__ void __launch_bounds__(kSrcBlock) k_corr4_partial(const double2* q4, double* partials, long nsites,
+                                                             long nspat, int nvec) {
+    const int t = blockIdx.y, nblk = gridDim.x;
+    const long j = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    double sum = 0.0;
+    if (j < nspat) {
+        const long i = long(t) * nspat + j;
+        for (int v = 0; v < nvec; ++v) {
+            const double2* p = q4 + (long(v) * nsites + i) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) sum += p[k].x * p[k].x + p[k].y * p[k].y;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    __shared__ double ws[kSrcBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) ws[wave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < kSrcBlock / 64; ++w) a += ws[w];
+        partials[long(t) * nblk + blockIdx.x] = a;
+    }
+}
+
+__global__ void k_corr4_final(const double* partials, double* out, int T, int nblk) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    double a = 0.0;
+    for (int b = 0; b < nblk; ++b) a += partials[long(t) * nblk + b];
+    out[t] = a;
+}
+
 // out[t] = C_PP(t), out[T + t] = C_mp(t), out[2T + t] = m_res(t)
 __global__ void k_corr_final(const double* partials, double* out, int T, int nblk) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -482,6 +519,35 @@ mdwf_status mdwf_mres_correlators_dev(const mdwf_geometry* geom, int L5, int nve
         mres[t] = h[2 * T + t];
     }
     return MDWF_OK;
+}
+
+mdwf_status mdwf_pion_correlator_dev(const mdwf_geometry* geom, int nvec, const double* q_dev, void* stream,
+                                     double* c) {
+    mdwf_status s = check_src_geom(geom);
+    if (s) return s;
+    if (!q_dev || !c) return fail(nullptr, MDWF_ERR_ARG, "null pointer");
+    if (nvec < 1) return fail(nullptr, MDWF_ERR_ARG, "need nvec >= 1");
+    if (geom->T > 65535) return fail(nullptr, MDWF_ERR_ARG, "T > 65535");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int T = geom->T;
+    const long nspat = long(geom->X) * geom->Y * geom->Z, nsites = nspat * T;
+    const int nblk = int(blocks_for(nspat));
+    const size_t npart = size_t(T) * nblk;
+    double* dev = nullptr;
+    if ((s = hip_check(nullptr, hipMalloc(&dev, sizeof(double) * (npart + size_t(T))), "correlator buffer")))
+        return s;
+    hipLaunchKernelGGL(k_corr4_partial, dim3(nblk, T), dim3(kSrcBlock), 0, st, reinterpret_cast<const double2*>(q_dev),
+                       dev, nsites, nspat, nvec);
+    s = hip_check(nullptr, hipGetLastError(), "correlator kernel");
+    if (!s) {
+        hipLaunchKernelGGL(k_corr4_final, dim3((T + 63) / 64), dim3(64), 0, st, dev, dev + npart, T, nblk);
+        s = hip_check(nullptr, hipGetLastError(), "correlator kernel");
+    }
+    if (!s) s = hip_check(nullptr, hipMemcpyAsync(c, dev + npart, sizeof(double) * T, hipMemcpyDeviceToHost, st),
+                          "correlator D2H");
+    if (!s) s = hip_check(nullptr, hipStreamSynchronize(st), "correlators");
+    (void)hipFree(dev);
+    return s;
 }
 
 }  // extern "C"

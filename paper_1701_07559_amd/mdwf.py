@@ -135,6 +135,7 @@ def _load():
         "mdwf_project_4d_dev": ([C.POINTER(mdwf_geometry), ip, ip, vp, vp, vp, vp], ip),
         "mdwf_mres_correlators_dev": ([C.POINTER(mdwf_geometry), ip, ip, vp, vp, C.POINTER(dp), C.POINTER(dp),
                                        C.POINTER(dp)], ip),
+        "mdwf_pion_correlator_dev": ([C.POINTER(mdwf_geometry), ip, vp, vp, C.POINTER(dp)], ip),
         "mdwf_server_create": ([ip, C.c_size_t, ip, C.POINTER(vp)], ip),
         "mdwf_server_destroy": ([vp], None),
         "mdwf_server_last_error": ([vp], C.c_char_p),
@@ -366,6 +367,14 @@ def mdwf_mres_correlators_dev(dims, L5, nvec, x_ptr, stream=None):
     return np.array(cpp[:]), np.array(cmp_[:]), np.array(mres[:])
 
 
+def mdwf_pion_correlator_dev(dims, nvec, q_ptr, stream=None):
+    """Pseudoscalar correlator per time slice of nvec device 4D fields."""
+    T = int(dims[3])
+    c = (C.c_double * T)()
+    _raise(lib.mdwf_pion_correlator_dev(C.byref(_geom(dims)), int(nvec), int(q_ptr), stream, c))
+    return np.array(c[:])
+
+
 class Server:
     """Request server (mdwf_server_*): resident gauge fields, solves admitted
     by device footprint and run concurrently on worker streams.  Host arrays
@@ -440,6 +449,6 @@ def exported_symbols():
             "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
             "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
             "mdwf_plaquette_dev", "mdwf_gauss_smear_dev", "mdwf_wall_source_dev", "mdwf_project_4d_dev",
-            "mdwf_mres_correlators_dev", "mdwf_server_create", "mdwf_server_destroy",
+            "mdwf_mres_correlators_dev", "mdwf_pion_correlator_dev", "mdwf_server_create", "mdwf_server_destroy",
             "mdwf_server_last_error", "mdwf_server_add_field", "mdwf_server_submit", "mdwf_server_wait",
             "mdwf_server_stats"]

@@ -116,6 +116,9 @@ def test_source_flow_entry_points_reject_bad_arguments_without_device():
     assert L.mdwf_mres_correlators_dev(C.byref(g), 8, 1, p, None, None, d, d) == ARG
     big_t = mdwf.mdwf_geometry(1, 1, 1, 70000, 1)
     assert L.mdwf_mres_correlators_dev(C.byref(big_t), 8, 1, p, None, d, d, d) == ARG
+    assert L.mdwf_pion_correlator_dev(C.byref(g), 0, p, None, d) == ARG
+    assert L.mdwf_pion_correlator_dev(C.byref(g), 1, None, None, d) == ARG
+    assert L.mdwf_pion_correlator_dev(C.byref(big_t), 1, p, None, d) == ARG
     # flow
     assert L.mdwf_wilson_flow_dev(C.byref(g), p, 0.0, 3, None, None) == ARG
     assert L.mdwf_wilson_flow_dev(C.byref(g), p, 0.01, -1, None, None) == ARG

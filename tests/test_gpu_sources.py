@@ -110,6 +110,15 @@ def test_projections_and_correlators_match_oracle(M):
     rpp, rmp, rres = SRC.correlators(list(x5))
     for a, b in ((cpp, rpp), (cmp_, rmp), (mres, rres)):
         assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    # the 4D correlator of the wall fields is c_pp bit for bit; with a
+    # smeared sink it matches the oracle's sums over the smeared fields
+    assert np.array_equal(M.mdwf_pion_correlator_dev(dims, n, q.data_ptr()), cpp)
+    U = I.random_links(dims, 0.3, 110)
+    Ud, sq = dev(U), empty((n, 6, 4, 3, 5, 4, 3))
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), n, q.data_ptr(), sq.data_ptr(), 2.0, 4)
+    ref = SRC.pion_correlator([SRC.gauss_smear(U, SRC.project_wall(x5[k]), 2.0, 4) for k in range(n)])
+    got = M.mdwf_pion_correlator_dev(dims, n, sq.data_ptr())
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     # deterministic, and the wall projection alone works for odd L5
     assert all(np.array_equal(a, b) for a, b in zip((cpp, cmp_, mres),
                                                      M.mdwf_mres_correlators_dev(dims, L5, n, xd.data_ptr())))

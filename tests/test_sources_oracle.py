@@ -15,6 +15,9 @@ the definitions, not against itself:
   exactly, for point and smeared sources, Shamir and Moebius actions.  A
   wrong midpoint slice or projector, a wrong wall or a missing (1 - c5 D_W)
   factor breaks it.
+* The pseudoscalar correlator as a sum of squared moduli equals the trace
+  tr[g5 S(x,0) g5 S(0,x)] over both propagator directions of the dense 4D
+  propagator, for a point and a smeared sink.
 """
 import numpy as np
 import pytest
@@ -131,3 +134,46 @@ def test_residual_mass_falls_with_L5_on_a_smooth_field():
             cols.append(x)
         means.append(float(np.mean(SRC.correlators(cols)[2][1:])))
     assert means[0] > 3 * means[1] > 9 * means[2] > 0, means
+
+
+def test_pseudoscalar_correlator_is_the_gamma5_trace():
+    """C(t) = sum_{x in t} Re tr[g5 S(x,0) g5 S(0,x)] computed from both
+    propagator directions of the dense 4D propagator equals the sum of
+    |S(x,0)|^2 over the 12 columns (the gamma5-hermiticity step used by
+    the wall and midpoint correlators), for a point and a smeared sink."""
+    dims, L5 = (2, 2, 2, 4), 4
+    U = I.random_links(dims, 0.3, 93)
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    Deff, g5 = _eff_operator(act, U)
+    n4 = Deff.shape[0]
+    S4 = (np.linalg.inv(Deff) - np.eye(n4)) / (1 - act.mq)
+    X, Y, Z, T = dims
+    shape = (T, Z, Y, X, 4, 3)
+    src = (1, 1, 0, 1)                                    # (t, z, y, x)
+    o = np.ravel_multi_index(src + (0, 0), shape)         # first row of the source site's 12
+    cols = [S4[:, o + j].reshape(shape) for j in range(12)]
+    g = np.diag(np.array([1.0, 1.0, -1.0, -1.0]))
+    direct = np.zeros(T)
+    for t in range(T):
+        for z in range(Z):
+            for y in range(Y):
+                for x in range(X):
+                    r = np.ravel_multi_index((t, z, y, x, 0, 0), shape)
+                    Sxo = S4[r:r + 12, o:o + 12]          # S(x, 0), 12 x 12
+                    Sox = S4[o:o + 12, r:r + 12]          # S(0, x)
+                    G5 = np.kron(g, np.eye(3))
+                    direct[t] += np.trace(G5 @ Sxo @ G5 @ Sox).real
+    assert np.abs(SRC.pion_correlator(cols) - direct).max() < 1e-12 * np.abs(direct).max()
+    # sink-smeared quark and antiquark: (K S)(x, 0) and (S K^+)(0, x)
+    K = lambda f: SRC.gauss_smear(U, f, 1.5, 3)
+    Kdense = dense_of(K, n4, shape)
+    SK = Kdense @ S4
+    directK = np.zeros(T)
+    for t in range(T):
+        for z in range(Z):
+            for y in range(Y):
+                for x in range(X):
+                    r = np.ravel_multi_index((t, z, y, x, 0, 0), shape)
+                    G5 = np.kron(g, np.eye(3))
+                    directK[t] += np.trace(G5 @ SK[r:r + 12, o:o + 12] @ G5 @ (S4 @ Kdense.conj().T)[o:o + 12, r:r + 12]).real
+    assert np.abs(SRC.pion_correlator([K(c) for c in cols]) - directK).max() < 1e-12 * np.abs(directK).max()
