@@ -66,6 +66,8 @@ int main() {
     EXPECT(mdwf_project_4d_dev(&good, 5, 1, buf, buf + 8, buf + 4, nullptr) == MDWF_ERR_ARG);
     EXPECT(mdwf_mres_correlators_dev(&good, 7, 1, buf, nullptr, cpp, cmp, mres) == MDWF_ERR_ARG);
     EXPECT(mdwf_mres_correlators_dev(&tall, 8, 1, buf, nullptr, cpp, cmp, mres) == MDWF_ERR_ARG);
+    EXPECT(mdwf_pion_correlator_dev(&tall, 1, buf, nullptr, cpp) == MDWF_ERR_ARG);
+    EXPECT(mdwf_pion_correlator_dev(&good, 0, buf, nullptr, cpp) == MDWF_ERR_ARG);
     EXPECT(mdwf_wilson_flow_dev(&good, buf, -1.0, 2, nullptr, plaq) == MDWF_ERR_ARG);
     EXPECT(mdwf_wilson_flow(&flat, 0, buf, 0.01, 2, plaq) == MDWF_ERR_ARG);
     EXPECT(mdwf_plaquette_dev(&good, nullptr, nullptr, plaq) == MDWF_ERR_ARG);
