@@ -127,12 +127,24 @@ struct SmearIdx {
     uint32_t G;
 };
 
+// WAVE: one wavefront per site (nvec <= 16; lanes 4 nvec .. 63 idle), so the
+// site and its links are wave-uniform and the links come by scalar loads.
+template <bool WAVE>
 __global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const SmearIdx ix, const double2* U,
                                                           const double2* in, double2* out, double kappa,
                                                           uint32_t nsites, uint32_t ntot) {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= ntot) return;
-    const uint32_t i = ix.fG.div(id), r = id - i * ix.G, v = r >> 2, sp = r & 3;
+    uint32_t i, r;
+    if constexpr (WAVE) {
+        i = uint32_t(__builtin_amdgcn_readfirstlane(int(id >> 6)));
+        r = id & 63;
+        if (i >= nsites || r >= ix.G) return;
+    } else {
+        if (id >= ntot) return;
+        i = ix.fG.div(id);
+        r = id - i * ix.G;
+    }
+    const uint32_t v = r >> 2, sp = r & 3;
     const uint32_t q1 = ix.fX.div(i), x = i - q1 * g.X;
     const uint32_t q2 = ix.fY.div(q1), y = q1 - q2 * g.Y;
     const uint32_t t = ix.fZ.div(q2), z = q2 - t * g.Z;
@@ -415,14 +427,21 @@ mdwf_status mdwf_gauss_smear_dev(const mdwf_geometry* geom, const double* U_dev,
     ix.fX = FastDiv(uint32_t(g.X));
     ix.fY = FastDiv(uint32_t(g.Y));
     ix.fZ = FastDiv(uint32_t(g.Z));
-    const uint32_t nthr = uint32_t(ntot * 4);
+    const bool wave = nvec <= 16;   // one wavefront per site
+    const uint32_t nthr = wave ? uint32_t(nsites * 64) : uint32_t(ntot * 4);
+    if (wave && double(nsites) * 64.0 >= double(1u << 31))
+        return fail(nullptr, MDWF_ERR_ARG, "lattice too large for one smearing launch");
     const auto* U = reinterpret_cast<const double2*>(U_dev);
     const double2* src = reinterpret_cast<const double2*>(in_dev);
     double2* out = reinterpret_cast<double2*>(out_dev);
     for (int k = 1; k <= niter && !s; ++k) {
         double2* dst = ((niter - k) % 2 == 0) ? out : tmp;   // the last step lands in out
-        hipLaunchKernelGGL(k_gauss_step, dim3(blocks_for(nthr)), dim3(kSrcBlock), 0, st, g, ix, U, src, dst, kappa,
-                           uint32_t(nsites), nthr);
+        if (wave)
+            hipLaunchKernelGGL(k_gauss_step<true>, dim3(blocks_for(nthr)), dim3(kSrcBlock), 0, st, g, ix, U, src, dst,
+                               kappa, uint32_t(nsites), nthr);
+        else
+            hipLaunchKernelGGL(k_gauss_step<false>, dim3(blocks_for(nthr)), dim3(kSrcBlock), 0, st, g, ix, U, src,
+                               dst, kappa, uint32_t(nsites), nthr);
         s = hip_check(nullptr, hipGetLastError(), "smearing kernel");
         src = dst;
     }

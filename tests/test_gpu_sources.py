@@ -50,7 +50,8 @@ def spinors(dims, n, seed):
 
 
 @pytest.mark.parametrize("dims,nvec,sigma,niter", [((4, 4, 4, 8), 2, 2.5, 5), ((5, 3, 4, 6), 3, 1.7, 2),
-                                                   ((6, 4, 2, 2), 1, 3.0, 1), ((3, 5, 7, 3), 2, 4.0, 12)])
+                                                   ((6, 4, 2, 2), 1, 3.0, 1), ((3, 5, 7, 3), 2, 4.0, 12),
+                                                   ((4, 2, 2, 4), 16, 2.0, 3), ((4, 2, 2, 4), 17, 2.0, 3)])
 def test_gauss_smear_matches_oracle(M, dims, nvec, sigma, niter):
     U = I.random_links(dims, 0.3, 101)
     psi = spinors(dims, nvec, 102)
