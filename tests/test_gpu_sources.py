@@ -227,3 +227,25 @@ def test_benchmark_size_properties(M):
     lhs, rhs = _ward(corr, act_t[3], q, src)
     assert abs(lhs - rhs) <= 1e-6 * abs(rhs), (lhs, rhs)
     assert np.all(corr[0] > 0) and np.all(corr[1] > 0)
+
+
+def test_smearing_at_benchmark_volume_matches_oracle_on_windows(M):
+    """24^3 x 64, the benchmark's field, 12 random vectors smeared by 3 steps
+    on the GPU (one launch per step, the benchmark's launch shape).  Three
+    steps move information at most three sites in space and none in time,
+    so the oracle's smearing of a periodic 12^3 spatial window on one time
+    slice reproduces the window's central 4^3 block exactly."""
+    dims = (24, 24, 24, 64)
+    U = I.random_links(dims, 0.25, 103, workers=8)
+    rng = np.random.default_rng(111)
+    psi = rng.standard_normal((12, 64, 24, 24, 24, 4, 3)) + 1j * rng.standard_normal((12, 64, 24, 24, 24, 4, 3))
+    Ud, ind, outd = dev(U), dev(psi), empty(psi.shape)
+    M.mdwf_gauss_smear_dev(dims, Ud.data_ptr(), 12, ind.data_ptr(), outd.data_ptr(), 4.0, 3)
+    out = host(outd, psi.shape)
+    for v, (t, z, y, x) in [(0, (0, 0, 0, 0)), (7, (40, 11, 23, 5)), (11, (63, 23, 12, 23))]:
+        iz, iy, ix = [np.arange(c - 6, c + 6) % 24 for c in (z, y, x)]
+        Uw = U[t][np.ix_(iz, iy, ix)][None]
+        pw = psi[v, t][np.ix_(iz, iy, ix)][None]
+        ref = SRC.gauss_smear(Uw, pw, 4.0, 3)[0, 4:8, 4:8, 4:8]
+        got = out[v, t][np.ix_(iz, iy, ix)][4:8, 4:8, 4:8]
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (v, t, z, y, x)
