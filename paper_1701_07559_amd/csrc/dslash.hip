@@ -128,14 +128,6 @@ __device__ __forceinline__ h2 splat_h2(float f) {
 }
 // a.x b.x + a.y b.y + c
 __device__ __forceinline__ float dot2(h2 a, h2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
-// a.x b.x + a.y b.y: the first term of a chain, in the three-operand encoding
-// with an inline zero (the builtin with c = 0 becomes a register clear plus
-// the accumulating form, one more VALU instruction per chain)
-__device__ __forceinline__ float dot2_first(h2 a, h2 b) {
-    float r;
-    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
 
 // From z = u + SGN X d (X = i for TI, else 1) the two packed operands that
 // make U z (FWD) or U^+ z a sum of dot2 products with the link element:
@@ -188,10 +180,9 @@ __device__ __forceinline__ void su3_mul_h(const h2 U[9], const h2 z1[6], const h
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const h2 u0 = FWD ? U[a * 3] : U[a];
-            float re = dot2_first(u0, z1[sp * 3]), im = dot2_first(u0, z2[sp * 3]);
+            float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int b = 1; b < 3; ++b) {
+            for (int b = 0; b < 3; ++b) {
                 const h2 u = FWD ? U[a * 3 + b] : U[b * 3 + a];
                 re = dot2(u, z1[sp * 3 + b], re);
                 im = dot2(u, z2[sp * 3 + b], im);

@@ -47,7 +47,7 @@ def test_abi_host_code_under_asan_and_ubsan(tmp_path):
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
     flags = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-             "-packed-fp32-ops", "-Wno-unused-result", "-Xarch_host", "-O1", "-Xarch_host", "-g"] + san
+             "-packed-fp32-ops", "-Xclang", "-target-feature", "-Xclang", "-dot5-insts", "-Wno-unused-result", "-Xarch_host", "-O1", "-Xarch_host", "-g"] + san
     objs, procs = [], []
     for src in SOURCES:
         obj = str(tmp_path / (src + ".o"))
