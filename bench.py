@@ -171,7 +171,11 @@ def roofline(info, inner, Vh, form):
                           for n, u, b in zip(names, us, by)})
 
 
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1701_07559_amd", "csrc", "dslash.hip")
+_PKG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1701_07559_amd")
+# what decides the hop kernels' machine code: their source, the shared
+# device header and the compiler flags
+KERNEL_SRC = os.path.join(_PKG, "csrc", "dslash.hip")
+KERNEL_DEPS = [KERNEL_SRC, os.path.join(_PKG, "csrc", "mdwf_internal.h")]
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "schur_rp_f16_24c64_L8_12rhs_counters.md")
 # hop kinds (HopKind) of kernels A, B, A^+, B^+ of each CG operator
@@ -179,9 +183,17 @@ FORM_KINDS = {"asym": (3, 4, 5, 6), "sym": (3, 9, 5, 6), "rp": (10, 11, 5, 12)}
 
 
 def kernel_sha():
+    """Digest of the hop kernels' source, the shared device header and the
+    compiler flags: a stored counter record applies only while it matches."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_DEPS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_1701_07559_amd import build as B
+    h.update(" ".join(B.HIPCC_FLAGS).encode())
+    return h.hexdigest()
 
 
 def stored_traffic(form):
