@@ -25,16 +25,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mdwf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with OpenMP over lattice sites, used only to time the
+# oracle on all host cores.  Only site loops without reductions run in
+# parallel, so it returns the same values as the single-threaded build.
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def _compile(out, extra):
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-fPIC", "-shared"] + extra + ["-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, single thread, no vector intrinsics)."""
+    """Compile the oracle with gcc (-O2, single thread, no vector intrinsics),
+    and its OpenMP timing build."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
-        )
-        os.replace(tmp, _LIB)
+        _compile(_LIB, [])
+    if force or not os.path.exists(_LIB_OMP):
+        _compile(_LIB_OMP, ["-fopenmp"])
     return _LIB
 
 
@@ -53,15 +62,29 @@ class SolveInfo(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
+_variant = "serial"
+
+
+def use_threads(n: int) -> int:
+    """Route every call of this module to the OpenMP timing build with n
+    threads (n >= 2), or back to the single-threaded oracle (n <= 1).
+    Returns the thread count now in use."""
+    global _variant
+    if n <= 1:
+        _variant = "serial"
+        return 1
+    _variant = "omp"
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    lib = _libs.get(_variant)
+    if lib is None:
+        path = _LIB_OMP if _variant == "omp" else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build()
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(path)
         P = C.POINTER(Params)
         d = C.c_void_p
         for name, args, res in [
@@ -85,12 +108,14 @@ def _load():
             ("oracle_cgls_step", [P, d, d, d, d, d, d, C.POINTER(C.c_double)], C.c_double),
             ("oracle_D5_sites", [P, d, d, d, C.c_int, d], None),
             ("oracle_schur_sites", [P, d, d, d, C.c_int, C.c_int, d], None),
+            ("oracle_schur_rp_sites", [P, d, d, d, C.c_int, C.c_int, d], None),
+            ("oracle_set_threads", [C.c_int], C.c_int),
         ]:
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = res
-        _lib = lib
-    return _lib
+        _libs[_variant] = lib
+    return lib
 
 
 class Action:
@@ -271,6 +296,17 @@ def schur_sites(act: Action, U, psi, sites, dag=False):
     s = np.ascontiguousarray(sites, dtype=np.int64)
     out = np.empty((len(s), act.L5, 4, 3), np.complex128)
     _load().oracle_schur_sites(C.byref(act.params()), pu, pi, s.ctypes.data, len(s), int(dag), out.ctypes.data)
+    return out
+
+
+def schur_rp_sites(act: Action, U, psi, sites, dag=False):
+    """(S B^-1 psi) or (B^-+ S^+ psi) at the listed even 4D sites, all slices:
+    [n, L5, 4, 3]."""
+    U, pu = _c(U)
+    psi, pi = _c(psi)
+    s = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(s), act.L5, 4, 3), np.complex128)
+    _load().oracle_schur_rp_sites(C.byref(act.params()), pu, pi, s.ctypes.data, len(s), int(dag), out.ctypes.data)
     return out
 
 

@@ -46,8 +46,12 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -188,6 +192,8 @@ static void dslash4(const oracle_params *p, const cplx *U, const cplx *in, cplx 
                     int dag, int out_parity)
 {
     const long V = volume(p);
+    init_gamma();   /* before any thread reads the table */
+#pragma omp parallel for schedule(static)
     for (long x = 0; x < V; ++x) {
         cplx acc[4][3];
         memset(acc, 0, sizeof(acc));
@@ -210,6 +216,7 @@ static void dw4(const oracle_params *p, const cplx *U, const cplx *in, cplx *out
 static void apply_C(const oracle_params *p, const cplx *in, cplx *out, int dag)
 {
     const long V = volume(p), L5 = p->L5;
+#pragma omp parallel for collapse(2) schedule(static)
     for (long s = 0; s < L5; ++s)
         for (long x = 0; x < V; ++x)
             for (int sp = 0; sp < 4; ++sp) {
@@ -289,27 +296,42 @@ static void gauss_solve(int n, double *A, cplx *r)
     }
 }
 
+/* Solve the L5 x L5 system M y = v on every 4D site, spin and colour, with
+ * M = Mc[0] on the upper (P+) spins and Mc[1] on the lower (P-) spins. */
+static void solve_fifth(const oracle_params *p, double *const Mc[2], const cplx *in, cplx *out)
+{
+    const long V = volume(p);
+    const int L5 = p->L5;
+    if (L5 > 32) {   /* the per-site scratch below holds L5 <= 32 */
+        fprintf(stderr, "oracle: L5 = %d exceeds 32\n", L5);
+        abort();
+    }
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        double A[32 * 32];
+        cplx col[32];
+        for (int sp = 0; sp < 4; ++sp)
+            for (int a = 0; a < 3; ++a) {
+                for (int s = 0; s < L5; ++s) col[s] = in[((long)s * V + x) * 12 + sp * 3 + a];
+                memcpy(A, Mc[sp < 2 ? 0 : 1], sizeof(double) * L5 * L5);
+                gauss_solve(L5, A, col);
+                for (int s = 0; s < L5; ++s) out[((long)s * V + x) * 12 + sp * 3 + a] = col[s];
+            }
+    }
+}
+
 /* K5^-1 (or (K5^+)^-1): for every 4D site, spin and colour, solve the L5 x L5
  * system of that chirality. */
 static void apply_K5inv(const oracle_params *p, const cplx *in, cplx *out, int dag)
 {
-    const long V = volume(p);
     const int L5 = p->L5;
-    double *K[2], *A = malloc(sizeof(double) * L5 * L5);
-    cplx *col = malloc(sizeof(cplx) * L5);
+    double *K[2];
     for (int u = 0; u < 2; ++u) {
         K[u] = malloc(sizeof(double) * L5 * L5);
-        k5_matrix(p, u, dag, K[u]);
+        k5_matrix(p, u == 0, dag, K[u]);
     }
-    for (long x = 0; x < V; ++x)
-        for (int sp = 0; sp < 4; ++sp)
-            for (int a = 0; a < 3; ++a) {
-                for (int s = 0; s < L5; ++s) col[s] = in[((long)s * V + x) * 12 + sp * 3 + a];
-                memcpy(A, K[sp < 2], sizeof(double) * L5 * L5);
-                gauss_solve(L5, A, col);
-                for (int s = 0; s < L5; ++s) out[((long)s * V + x) * 12 + sp * 3 + a] = col[s];
-            }
-    free(K[0]); free(K[1]); free(A); free(col);
+    solve_fifth(p, K, in, out);
+    free(K[0]); free(K[1]);
 }
 
 /* Dense L5 x L5 matrix of B = b5 + c5 C (or B^+) on one chirality, from the
@@ -332,23 +354,14 @@ static void b_matrix(const oracle_params *p, int upper, int dag, double *Bm)
 /* B^-1 (or (B^+)^-1), by Gaussian elimination per 4D site, spin and colour. */
 static void apply_Binv(const oracle_params *p, const cplx *in, cplx *out, int dag)
 {
-    const long V = volume(p);
     const int L5 = p->L5;
-    double *Bm[2], *A = malloc(sizeof(double) * L5 * L5);
-    cplx *col = malloc(sizeof(cplx) * L5);
+    double *Bm[2];
     for (int u = 0; u < 2; ++u) {
         Bm[u] = malloc(sizeof(double) * L5 * L5);
-        b_matrix(p, u, dag, Bm[u]);
+        b_matrix(p, u == 0, dag, Bm[u]);
     }
-    for (long x = 0; x < V; ++x)
-        for (int sp = 0; sp < 4; ++sp)
-            for (int a = 0; a < 3; ++a) {
-                for (int s = 0; s < L5; ++s) col[s] = in[((long)s * V + x) * 12 + sp * 3 + a];
-                memcpy(A, Bm[sp < 2], sizeof(double) * L5 * L5);
-                gauss_solve(L5, A, col);
-                for (int s = 0; s < L5; ++s) out[((long)s * V + x) * 12 + sp * 3 + a] = col[s];
-            }
-    free(Bm[0]); free(Bm[1]); free(A); free(col);
+    solve_fifth(p, Bm, in, out);
+    free(Bm[0]); free(Bm[1]);
 }
 
 /* Dslash (or Dslash^+) on every slice, input masked to parity 1-out_parity,
@@ -360,6 +373,7 @@ static void hop5(const oracle_params *p, const cplx *U, const cplx *in, cplx *ou
     cplx *tmp = malloc(n4 * sizeof(cplx));
     for (int s = 0; s < p->L5; ++s) {
         const cplx *src = in + s * n4;
+#pragma omp parallel for schedule(static)
         for (long x = 0; x < V; ++x) {
             int keep = parity_of(p, x) != out_parity;
             for (int k = 0; k < 12; ++k) tmp[12 * x + k] = keep ? src[12 * x + k] : 0;
@@ -774,9 +788,47 @@ void oracle_schur_sites(const oracle_params *p, const double *Ud, const double *
     free(x); free(src); free(kx); free(nb);
 }
 
-/* One CGLS iteration's operator work (S, S^+, and the vector updates) on
- * given vectors; used only to time the oracle on large lattices where a full
- * solve would take too long.  Returns ||r||^2 after the step. */
+/* (S B^-1 in)(x, s) or (B^-+ S^+ in)(x, s) for even 4D sites `sites` and every
+ * slice; out[n][L5][12].  B^-1 is 4D-site-local, so the forward operator is
+ * oracle_schur_sites of B^-1 in (a full-lattice site-local pass), and the
+ * adjoint solves B^+ y = (S^+ in)(x, .) on the slices of each sampled site. */
+void oracle_schur_rp_sites(const oracle_params *p, const double *Ud, const double *ind,
+                           const long *sites, int nsites, int dag, double *outd)
+{
+    const long n = n5(p);
+    const int L5 = p->L5;
+    cplx *out = (cplx *)outd;
+    if (!dag) {
+        cplx *x = malloc(n * sizeof(cplx)), *y = malloc(n * sizeof(cplx));
+        memcpy(x, ind, n * sizeof(cplx));
+        mask_parity(p, x, 0);
+        apply_Binv(p, x, y, 0);
+        oracle_schur_sites(p, Ud, (const double *)y, sites, nsites, 0, outd);
+        free(x); free(y);
+        return;
+    }
+    oracle_schur_sites(p, Ud, ind, sites, nsites, 1, outd);
+    double *Bm[2], *A = malloc(sizeof(double) * L5 * L5);
+    cplx *col = malloc(sizeof(cplx) * L5);
+    for (int u = 0; u < 2; ++u) {
+        Bm[u] = malloc(sizeof(double) * L5 * L5);
+        b_matrix(p, u == 0, 1, Bm[u]);
+    }
+    for (int k = 0; k < nsites; ++k)
+        for (int sp = 0; sp < 4; ++sp)
+            for (int a = 0; a < 3; ++a) {
+                for (int s = 0; s < L5; ++s) col[s] = out[((long)k * L5 + s) * 12 + sp * 3 + a];
+                memcpy(A, Bm[sp < 2 ? 0 : 1], sizeof(double) * L5 * L5);
+                gauss_solve(L5, A, col);
+                for (int s = 0; s < L5; ++s) out[((long)k * L5 + s) * 12 + sp * 3 + a] = col[s];
+            }
+    free(Bm[0]); free(Bm[1]); free(A); free(col);
+}
+
+/* One CGLS iteration of the asymmetric Schur system (S, S^+ and the vector
+ * updates of the recursion in oracle_solve) on given full-size vectors: the
+ * unit of work of the oracle's solve, timed on lattices where a whole solve
+ * would take too long.  Returns ||r||^2 after the step. */
 double oracle_cgls_step(const oracle_params *p, const double *Ud, double *xd, double *rd,
                         double *pd, double *sd, double *qd, double *gam)
 {
@@ -790,4 +842,18 @@ double oracle_cgls_step(const oracle_params *p, const double *Ud, double *xd, do
     *gam = gnew;
     for (long i = 0; i < n; ++i) pv[i] = s[i] + beta * pv[i];
     return norm2(r, n);
+}
+
+/* Threads of the OpenMP timing build (the plain build runs on one thread and
+ * returns 1).  Results do not depend on it: only site loops without
+ * reductions run in parallel. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -539,3 +539,88 @@ def test_right_preconditioned_schur_solution_and_adjoint():
     a1 = vdot(yv, oracle.schur_rp(act, U, xv))
     a2 = vdot(oracle.schur_rp(act, U, yv, dag=True), xv)
     assert abs(a1 - a2) <= 1e-13 * abs(a1)
+
+
+# ------------------------------------------------- sampled-site oracles
+
+def _at_sites(full, act, sites):
+    """[L5, T, Z, Y, X, 4, 3] -> [n, L5, 4, 3] at lexicographic 4D sites."""
+    X, Y, Z, T = act.dims
+    f = full.reshape(act.L5, X * Y * Z * T, 4, 3)
+    return np.transpose(f[:, sites], (1, 0, 2, 3))
+
+
+@pytest.mark.parametrize("L5,antiperiodic", [(4, True), (5, True), (1, True), (4, False)])
+def test_sampled_site_oracles_match_full_lattice_operators(L5, antiperiodic):
+    """The site-by-site oracles that check full-size GPU results evaluate B,
+    B^+, K5^-1 and the stencil inline; each must equal the full-lattice
+    operator (itself pinned by the Kronecker and dense-matrix tests above) at
+    every site, including the sites whose hops wrap in t."""
+    dims = (6, 4, 4, 6)
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.0102, antiperiodic_t=antiperiodic)
+    U = I.random_links(dims, 0.4, 11)
+    psi = rand5(act, 12)
+    X, Y, Z, T = dims
+    every = np.arange(X * Y * Z * T)
+    even = np.flatnonzero(oracle.even_mask(dims).ravel())
+
+    def close(out, ref):
+        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+    close(oracle.D5_sites(act, U, psi, every), _at_sites(oracle.D5(act, U, psi), act, every))
+    for dag in (False, True):
+        close(oracle.schur_sites(act, U, psi, even, dag=dag),
+              _at_sites(oracle.schur(act, U, psi, dag=dag), act, even))
+        close(oracle.schur_rp_sites(act, U, psi, even, dag=dag),
+              _at_sites(oracle.schur_rp(act, U, psi, dag=dag), act, even))
+    # a sampled subset in any order gives the same rows
+    pick = even[::-7][:9]
+    close(oracle.schur_rp_sites(act, U, psi, pick, dag=True),
+          _at_sites(oracle.schur_rp(act, U, psi, dag=True), act, pick))
+
+
+def test_openmp_timing_build_returns_the_same_values():
+    """The OpenMP build used to time the oracle on all host cores parallelises
+    only site loops without reductions: its results are bitwise those of the
+    single-threaded oracle."""
+    dims, L5 = (4, 4, 4, 6), 4
+    act = oracle.Action(dims, L5, **ACT)
+    U = I.random_links(dims, 0.4, 13)
+    psi = rand5(act, 14)
+    ref = [oracle.D5(act, U, psi), oracle.schur(act, U, psi, dag=True), oracle.apply_K5inv(act, psi)]
+    try:
+        assert oracle.use_threads(4) >= 2
+        out = [oracle.D5(act, U, psi), oracle.schur(act, U, psi, dag=True), oracle.apply_K5inv(act, psi)]
+    finally:
+        oracle.use_threads(1)
+    for a, b in zip(out, ref):
+        assert np.array_equal(a, b)
+
+
+def test_cgls_step_is_one_iteration_of_the_oracle_solve():
+    """oracle_cgls_step (the unit the CPU baseline times) reproduces the
+    recursion of oracle_solve: run from x = 0 it drives the tracked residual
+    below the same target in the same number of iterations, and its iterate
+    then solves the Schur system."""
+    dims, L5 = (4, 4, 4, 4), 4
+    act = oracle.Action(dims, L5, **ACT)
+    U = I.random_links(dims, 0.3, 15)
+    b = rand5(act, 16)
+    x_ref, info = oracle.solve(act, U, b, tol=1e-10)
+    bp = oracle.prep_source(act, U, b)
+    x = np.zeros_like(bp)
+    r = bp.copy()
+    s = oracle.schur(act, U, r, dag=True)
+    p = s.copy()
+    q = np.zeros_like(bp)
+    gam = float(np.vdot(s.ravel(), s.ravel()).real)
+    bnorm = np.linalg.norm(b.ravel())
+    it = 0
+    while np.linalg.norm(r.ravel()) > 0.5e-10 * bnorm:
+        rr, gam = oracle.cgls_step(act, U, x, r, p, s, q, gam)
+        it += 1
+        assert it < 10000
+    assert info["restarts"] == 0 and it == info["iters"]
+    assert rel(oracle.schur(act, U, x), bp) < 1e-9
+    full = oracle.reconstruct(act, U, b, x)
+    assert oracle.true_residual(act, U, b, full) <= 1e-10
