@@ -57,6 +57,10 @@ WORKLOADS = {
     "mixed": dict(DIMS=(24, 24, 24, 64), L5=8, MASSES=[0.0102], GAUGE_SEED=103, SITE_SEED=403, GROUPS=1),
     "batched": dict(DIMS=(32, 32, 32, 64), L5=10, MASSES=[0.0074, 0.02, 0.04], GAUGE_SEED=104, SITE_SEED=404,
                     GROUPS=3),
+    # the a15m310 volume and mass (Table I, Table III): plain FP64 CG on one
+    # Gaussian source, with the dslash bandwidth of each precision
+    "fp64": dict(DIMS=(16, 16, 16, 48), L5=12, MASSES=[0.0158], GAUGE_SEED=102, SITE_SEED=None, SRC_SEED=302,
+                 GROUPS=1),
     "serving": None,   # its own driver, serve_main
     "flow": None,      # its own driver, flow_main
     "mres": None,      # its own driver, mres_main
@@ -114,28 +118,104 @@ def time_apply(M, torch, ctx, op, prec, reps, warm=5):
                 model_bytes=bytes_, model_flops=flops)
 
 
-def cpu_baseline(U, dims, L5_, act_kw, budget_s=25.0):
-    """The FP64 oracle (single-threaded C, as it stands) applying the Schur
-    operator on the same lattice; rate in algorithmic GB/s of that apply."""
-    import oracle
-    act = oracle.Action(dims, L5_, **act_kw)
-    psi = np.zeros(act.shape5, complex)
-    rng = np.random.default_rng(SRC_SEED)
-    psi.real = rng.standard_normal(act.shape5)
-    psi.imag = rng.standard_normal(act.shape5)
+def host_cpu_info():
+    """The host's CPU model and the threads the oracle may use: the CPU share
+    given to this process (OMP_NUM_THREADS when set, else its affinity)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = int(omp) if omp.isdigit() and int(omp) > 0 else aff
+    return dict(model=model, nproc=os.cpu_count(), affinity=aff, threads=max(1, min(threads, aff)))
+
+
+def _timed(f, *a):
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        oracle.schur(act, U, psi)
-        n += 1
-        if time.perf_counter() - t0 > budget_s * 0.5 or n >= 3:
-            break
-    dt = (time.perf_counter() - t0) / n
+    r = f(*a)
+    return r, time.perf_counter() - t0
+
+
+def cpu_baseline(U, dims, L5_, act_kw, fp64_iters=None, ncols=1, check=None):
+    """The FP64 oracle (plain C, as it stands) on the host cores, in the same
+    run: its Schur operator on the workload's lattice on one thread and on all
+    the threads the host gives this process (the OpenMP timing build of the
+    same source), one D5 and one CG iteration on all threads, and the
+    CPU-sized configuration (4^3 x 8, L5 = 8, m_q = 0.05) solved to 1e-10 on
+    both.  value = algorithmic GB/s of the all-threads Schur application (the
+    GPU kernels' byte model).  With fp64_iters, the oracle's FP64 CG time to
+    solution on the workload is extrapolated from its iteration time and the
+    GPU FP64 CG's iteration counts (labelled as such).  check = (b, x) of a
+    GPU solution: the oracle's D5 gives its true residual."""
+    import oracle
+    from paper_1701_07559_amd import inputs as I
+    info = host_cpu_info()
+    nt = info["threads"]
+    act = oracle.Action(dims, L5_, **act_kw)
+    rng = np.random.default_rng(SRC_SEED)
+    psi = rng.standard_normal(act.shape5) + 1j * rng.standard_normal(act.shape5)
     X, Y, Z, T = dims
     Vh = X * Y * Z * T * L5_ // 2
-    bytes_fp64 = Vh * ((120 + 288 / L5_) * 8)   # the same algorithmic model as the GPU kernels
-    return dict(value=bytes_fp64 / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
-                sample="%d FP64 Schur applications (full 24^3x64x8 lattice, single thread), %.1f s each" % (n, dt))
+    schur_bytes = Vh * ((120 + 288 / L5_) * 8)   # the same algorithmic model as the GPU kernels
+    out = dict(kind="oracle", unit="GB/s", cpu_model=info["model"], nproc=info["nproc"],
+               affinity=info["affinity"])
+    try:
+        oracle.use_threads(1)
+        _, t1 = _timed(oracle.schur, act, U, psi)
+        nt = oracle.use_threads(nt) if nt > 1 else 1
+        _, tn = _timed(oracle.schur, act, U, psi)
+        _, tn2 = _timed(oracle.schur, act, U, psi)
+        tn = min(tn, tn2)
+        _, td5 = _timed(oracle.D5, act, U, psi)
+        # one CG iteration of the oracle's solve (S, S^+, vector updates)
+        x = np.zeros_like(psi)
+        r = psi.copy()
+        sv = oracle.schur(act, U, r, dag=True)
+        pv = sv.copy()
+        q = np.zeros_like(psi)
+        gam = float(np.vdot(sv, sv).real)
+        _, tit = _timed(oracle.cgls_step, act, U, x, r, pv, sv, q, gam)
+        del x, r, sv, pv, q
+        oracle_resid = None
+        if check is not None:
+            oracle_resid, tchk = _timed(oracle.true_residual, act, U, check[0], check[1])
+        # the CPU-sized configuration, whole solve
+        a1 = oracle.Action((4, 4, 4, 8), 8, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+        U1 = I.random_links((4, 4, 4, 8), 0.3, 101)
+        b1 = I.gaussian_source((4, 4, 4, 8), 8, 301)
+        (_, i1n), ts1n = _timed(oracle.solve, a1, U1, b1)
+        oracle.use_threads(1)
+        (_, i11), ts11 = _timed(oracle.solve, a1, U1, b1)
+    finally:
+        oracle.use_threads(1)
+    out.update(value=round(schur_bytes / tn / 1e9, 4), cores=nt,
+               sample="FP64 oracle on %dx%dx%dx%d L5=%d: Schur application %.2f s on %d threads (best of 2), "
+                      "%.2f s on 1 thread; D5 %.2f s and one CG iteration %.2f s on %d threads; 4^3x8 L5=8 "
+                      "solve to 1e-10 (%d iterations) %.3f s on %d threads, %.3f s on 1" %
+                      (X, Y, Z, T, L5_, tn, nt, t1, td5, tit, nt, i1n["iters"], ts1n, nt, ts11),
+               single_thread=dict(value=round(schur_bytes / t1 / 1e9, 4), unit="GB/s", cores=1,
+                                  schur_s=round(t1, 3)),
+               schur_s=round(tn, 3), d5_s=round(td5, 3), cg_iteration_s=round(tit, 3),
+               config1_solve=dict(dims=[4, 4, 4, 8], L5=8, iters=i1n["iters"], true_resid=i1n["true_resid"],
+                                  seconds_all_threads=round(ts1n, 4), seconds_1_thread=round(ts11, 4)))
+    if fp64_iters:
+        secs = tit * float(np.sum(fp64_iters)) * (ncols / len(fp64_iters))
+        out["time_to_solution_extrapolated"] = dict(
+            seconds=round(secs, 1), threads=nt,
+            note="extrapolated: oracle CG iteration time x the GPU FP64 CG iteration counts, %d columns" % ncols)
+    if oracle_resid is not None:
+        out["oracle_true_resid_of_gpu_solution"] = oracle_resid
+        out["oracle_check_s"] = round(tchk, 2)
+    return out
 
 
 def hop_launch_bytes(inner, Vh, nr):
@@ -143,11 +223,20 @@ def hop_launch_bytes(inner, Vh, nr):
     for nr right-hand sides: each spinor field read or written once per RHS
     (FP16: 2-byte reals plus a 4-byte norm per 5D site), the links of the
     launch once (144 reals per 4D site: 8 links of 18 reals)."""
-    w, nrm = (2, 4) if inner == "f16" else (4, 0)
+    w, nrm = {"f16": (2, 4), "f32": (4, 0), "f64": (8, 0)}[inner]
     links = Vh * 144 * w / L5
     a = Vh * nr * (48 * w + 2 * nrm) + links        # in psi, out t
     b_ = Vh * nr * (72 * w + 3 * nrm) + links       # in t, centre psi, out
     return [a, b_, a, b_]
+
+
+# What the counters show limits the hop kernels below the HBM roofline
+# (rocprofv3 summaries under profiles/).
+LIMITER = {
+    "f16": "vector-ALU issue: 82-90% VALU busy in the 12-RHS FP16 hop kernels (profiles/hop_valu_busy_24c64_L8.md)",
+    "f32": "neighbour gather through the texture path (profiles/hop_f32_24c64_L8_counters.md)",
+    "f64": "neighbour gather through the texture path (profiles/hop_f32_24c64_L8_counters.md)",
+}
 
 
 def roofline(info, inner, Vh, form):
@@ -167,6 +256,7 @@ def roofline(info, inner, Vh, form):
                         nr, info["hop_samples"]),
                 achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                 traffic=None,
+                limiter=LIMITER.get(inner),
                 launches={n: dict(us=round(u, 1), algorithmic_bytes=int(b), GBps=round(b / (u * 1e-6) / 1e9, 1))
                           for n, u, b in zip(names, us, by)})
 
@@ -886,7 +976,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--inner", choices=["f16", "f32"], default="f16")
     ap.add_argument("--nrhs", type=int, default=12)
-    ap.add_argument("--fp64-cols", type=int, default=1, help="columns solved with plain FP64 CG for the comparison")
+    ap.add_argument("--fp64-cols", type=int, default=-1,
+                    help="columns solved with plain FP64 CG for the comparison (-1: all 12 for the mixed "
+                         "workload, one per mass for the batched one; 0: none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--graph", type=int, default=0,
@@ -939,13 +1031,15 @@ def main():
     if args.workload == "mres":
         mres_main(args)
         return
-    global DIMS, L5, MASSES, GAUGE_SEED, SITE_SEED, GROUPS
+    global DIMS, L5, MASSES, GAUGE_SEED, SITE_SEED, GROUPS, SRC_SEED, EPS
     wl = WORKLOADS[args.workload]
     DIMS, L5, MASSES, GROUPS = wl["DIMS"], wl["L5"], wl["MASSES"], wl["GROUPS"]
     GAUGE_SEED, SITE_SEED = wl["GAUGE_SEED"], wl["SITE_SEED"]
+    SRC_SEED = wl.get("SRC_SEED", SRC_SEED)
     ACTION["mq"] = MASSES[0]
     if args.shamir:
         ACTION["b5"], ACTION["c5"] = 1.0, 0.0
+    fp64_workload = args.workload == "fp64"
 
     import torch
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
@@ -959,11 +1053,11 @@ def main():
     torch.cuda.set_stream(work)
     X, Y, Z, T = DIMS
     V = X * Y * Z * T
+    Vh = V * L5 // 2
     log("generating links", DIMS)
-    U = I.random_links(DIMS, EPS, GAUGE_SEED)
+    U = I.random_links(DIMS, EPS, GAUGE_SEED, workers=min(8, host_cpu_info()["threads"]))
     plaq = I.plaquette(U)
     log("plaquette %.4f" % plaq)
-    site = I.random_point_site(DIMS, SITE_SEED)
 
     ctx = M.mdwf_create(DIMS, antiperiodic_t=True, hip_device=0, hip_stream=work.cuda_stream)
     M.mdwf_set_action(ctx, ACTION["M5"], ACTION["b5"], ACTION["c5"], ACTION["mq"], L5)
@@ -998,29 +1092,43 @@ def main():
         M.mdwf_destroy(ctx)
         return
 
-    # right-hand sides: the 12 spin-colour columns of a point source, FP64
-    # canonical, built on the device; RHS k is column k // len(MASSES) at
-    # mass k % len(MASSES)
-    nrhs = args.nrhs if args.workload == "mixed" else 12 * len(MASSES)
-    ncol = min(12, nrhs) if args.workload == "mixed" else 12
     ncan = L5 * V * 24
-    b = torch.zeros((ncol, ncan), dtype=torch.float64, device=dev)
-    xs, ys, zs, ts = site
-    for k in range(ncol):
-        spin, colour = k // 3, k % 3
-        s = L5 - 1 if spin < 2 else 0
-        idx = ((((s * T + ts) * Z + zs) * Y + ys) * X + xs) * 12 + spin * 3 + colour
-        b[k, 2 * idx] = 1.0
+    if fp64_workload:
+        # one Gaussian 5D source (the a15m310 row: a single RHS), solved by
+        # plain FP64 CG on the asymmetric Schur system
+        nrhs, ncol = 1, 1
+        src = I.gaussian_source(DIMS, L5, SRC_SEED)
+        b = torch.from_numpy(src.view(np.float64).ravel()).to(dev).view(1, ncan)
+        del src
+        rhs_col, rhs_mass = [0], [MASSES[0]]
+        inner_name = "f64"
+        inner = M.MDWF_F64
+        form = args.fp64_form
+    else:
+        # the 12 spin-colour columns of a point source, FP64 canonical, built
+        # on the device; RHS k is column k // len(MASSES) at mass k % len(MASSES)
+        nrhs = args.nrhs if args.workload == "mixed" else 12 * len(MASSES)
+        ncol = min(12, nrhs) if args.workload == "mixed" else 12
+        site = I.random_point_site(DIMS, SITE_SEED)
+        b = torch.zeros((ncol, ncan), dtype=torch.float64, device=dev)
+        xs, ys, zs, ts = site
+        for k in range(ncol):
+            spin, colour = k // 3, k % 3
+            s = L5 - 1 if spin < 2 else 0
+            idx = ((((s * T + ts) * Z + zs) * Y + ys) * X + xs) * 12 + spin * 3 + colour
+            b[k, 2 * idx] = 1.0
+        rhs_col = [(k // len(MASSES)) % ncol for k in range(nrhs)]
+        rhs_mass = [MASSES[k % len(MASSES)] for k in range(nrhs)]
+        inner_name = args.inner
+        inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
+        form = args.schur_form
     per = nrhs // GROUPS
     x = torch.zeros((per, ncan), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-    rhs_col = [(k // len(MASSES)) % ncol for k in range(nrhs)]
-    rhs_mass = [MASSES[k % len(MASSES)] for k in range(nrhs)]
-    inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
     # profile_iters: the library times its batched hop launches of 10 CG
     # iterations with HIP events on the solve stream (the roofline figure)
     opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1, use_graph=args.graph,
-                profile_iters=0 if args.graph else 10, schur_form=FORMS[args.schur_form])
+                profile_iters=0 if args.graph else 10, schur_form=FORMS[form])
     bptr = [b[rhs_col[k]].data_ptr() for k in range(nrhs)]
     xptr = [x[k].data_ptr() for k in range(per)]
     # launch shapes for the solve itself: the inner precision on its CG
@@ -1065,33 +1173,69 @@ def main():
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
     all_ok = st == M.MDWF_OK and all(i["true_resid"] <= 1e-10 for i in infos)
 
-    # plain FP64 CG on the same columns (solved one at a time)
+    # the other side of "mixed vs FP64": for the mixed workloads, plain FP64
+    # CG on the same columns, one at a time, every solution kept; for the
+    # FP64 workload, the mixed (FP16-inner) solve of the same source
     fp64 = None
-    if args.fp64_cols > 0:
+    errs = None
+    other = None
+    if fp64_workload:
+        xm = torch.zeros((1, ncan), dtype=torch.float64, device=dev)
+        om = dict(tol=1e-10, inner=M.MDWF_F16, max_iter=args.max_iter, schur_form=FORMS["rp"],
+                  x_ref=[x[0].data_ptr()])
+        M.mdwf_autotune_solve(ctx, 1, om)
+        t_a = time.perf_counter()
+        stm, im = M.mdwf_solve_dev(ctx, [bptr[0]], [xm[0].data_ptr()], mq=[rhs_mass[0]], opts=om, stream=stream)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t_a
+        log("mixed f16 solve: %.3f s iters %d resid %.2e err vs fp64 %.2e" %
+            (tm, im[0]["iters"], im[0]["true_resid"], im[0]["err_vs_ref"]))
+        other = dict(inner="f16", form=FORM_NAMES["rp"], seconds=round(tm, 4), iters=im[0]["iters"],
+                     reliable_updates=im[0]["reliable_updates"], true_resid=im[0]["true_resid"],
+                     err_vs_fp64=im[0]["err_vs_ref"], speedup_vs_fp64=round((ms_per_step / 1e3) / tm, 3),
+                     note="includes its own first-call allocations; tuned for 1 RHS")
+        del xm
+    elif args.fp64_cols != 0:
+        ncols64 = nrhs if args.fp64_cols < 0 and args.workload == "mixed" else \
+            (len(MASSES) if args.fp64_cols < 0 else min(args.fp64_cols, nrhs))
+        # columns measured: all of them (mixed), or one per mass (batched)
+        cols = list(range(ncols64)) if args.workload == "mixed" else \
+            [k * (nrhs // ncols64) + (k % len(MASSES)) for k in range(ncols64)]
         o64 = dict(tol=1e-10, inner=M.MDWF_F64, max_iter=50000, use_graph=args.graph,
                    schur_form=FORMS[args.fp64_form])
-        t64 = []
-        it64 = []
-        for k in range(min(args.fp64_cols, nrhs)):
+        x64 = torch.zeros((len(cols), ncan), dtype=torch.float64, device=dev)
+        t64, it64, r64 = [], [], []
+        for j, k in enumerate(cols):
             t_a = time.perf_counter()
-            st64, i64 = M.mdwf_solve_dev(ctx, [bptr[k]], [xptr[0]], mq=[rhs_mass[k]], opts=o64, stream=stream)
+            st64, i64 = M.mdwf_solve_dev(ctx, [bptr[k]], [x64[j].data_ptr()], mq=[rhs_mass[k]], opts=o64,
+                                         stream=stream)
             torch.cuda.synchronize()
             t64.append(time.perf_counter() - t_a)
             it64.append(i64[0]["iters"])
-            log("fp64 column %d: %.3f s iters %d resid %.2e" % (k, t64[-1], it64[-1], i64[0]["true_resid"]))
-        per_col = float(np.mean(t64))
-        fp64 = dict(form=FORM_NAMES[args.fp64_form], columns_solved=len(t64), seconds_per_column=per_col, iters=it64,
-                    seconds_all_columns=per_col * nrhs,
-                    note="sum over %d columns = measured per-column time x %d" % (nrhs, nrhs)
-                    if len(t64) < nrhs else "measured")
+            r64.append(i64[0]["true_resid"])
+            log("fp64 column %d: %.3f s iters %d resid %.2e" % (k, t64[-1], it64[-1], r64[-1]))
+        measured_all = len(cols) == nrhs
+        fp64 = dict(form=FORM_NAMES[args.fp64_form], columns_solved=len(cols), seconds=[round(t, 4) for t in t64],
+                    iters=it64, max_true_resid=max(r64),
+                    seconds_all_columns=round(sum(t64) if measured_all else float(np.mean(t64)) * nrhs, 4),
+                    note="measured: sum over the %d columns" % nrhs if measured_all else
+                    "sum over %d columns = mean of %d measured columns x %d" % (nrhs, len(cols), nrhs))
+        # per-solve error of the mixed solution against the FP64 one: the
+        # mixed solve of the measured columns once more, outside the timed
+        # region, with the FP64 solutions as references
+        for g0 in range(0, len(cols), per):
+            gc = cols[g0:g0 + per]
+            xe = torch.zeros((len(gc), ncan), dtype=torch.float64, device=dev)
+            oe = dict(opts, profile_iters=0, x_ref=[x64[g0 + j].data_ptr() for j in range(len(gc))])
+            ste, ie = M.mdwf_solve_dev(ctx, [bptr[k] for k in gc], [v.data_ptr() for v in xe],
+                                       mq=[rhs_mass[k] for k in gc], opts=oe, stream=stream)
+            torch.cuda.synchronize()
+            errs = (errs or []) + [i["err_vs_ref"] for i in ie]
+            del xe
+        log("err vs fp64 per column: %s" % ", ".join("%.2e" % e for e in errs))
+        del x64
 
-    cpu = None
-    if not args.no_cpu:
-        log("timing the CPU oracle")
-        cpu = cpu_baseline(U, DIMS, L5, ACTION)
-        log("cpu oracle %.3f GB/s" % cpu["value"])
-
-    roof = roofline(infos[0], args.inner, V * L5 // 2, args.schur_form)
+    roof = roofline(infos[0], inner_name, Vh, form)
     rec = stored_traffic(args.schur_form) if (roof and args.inner == "f16" and args.workload == "mixed"
                                               and nrhs == 12 and not args.shamir) else None
     if rec:
@@ -1099,6 +1243,19 @@ def main():
         roof["traffic_note"] = "HBM bytes per operator application (kernels A + B) from rocprofv3 FETCH_SIZE / WRITE_SIZE, " \
                                "scaled by the 1 GiB copy calibration; %s" % os.path.relpath(TRAFFIC_FILE)
 
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        bk = b[rhs_col[0]].cpu().numpy().view(np.complex128).reshape(L5, T, Z, Y, X, 4, 3)
+        xk = x[0].cpu().numpy().view(np.complex128).reshape(L5, T, Z, Y, X, 4, 3)
+        it_ref = fp64["iters"] if fp64 else [infos[0]["iters"]] if fp64_workload else None
+        cpu = cpu_baseline(U, DIMS, L5, dict(ACTION, mq=rhs_mass[0]), fp64_iters=it_ref, ncols=nrhs,
+                           check=(bk, xk))
+        del bk, xk
+        log("cpu oracle %.3f GB/s on %d threads (%.3f on 1); oracle true residual of column 0: %.2e" %
+            (cpu["value"], cpu["cores"], cpu["single_thread"]["value"], cpu["oracle_true_resid_of_gpu_solution"]))
+
+    t_step = ms_per_step / 1e3
     out = {
         "metric": "Moebius DWF dslash GB/s (% HBM peak); time to r=1e-10 solve, mixed vs FP64",
         "value": round(value, 2),
@@ -1110,32 +1267,42 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.inner,
+        "dtype": inner_name,
         "data": "synthetic",
+        "value_definition": "algorithmic HBM bytes of every kernel of the step (per 5D site: each spinor field "
+                            "read or written once per kernel, the links once per multi-RHS launch) / step time; "
+                            "the dslash kernels alone are in roofline.achieved",
         "config": {
-            "workload": "%dx%dx%dx%d L5=%d M5=%g b5=%g c5=%g m_q=%s, exp(i0.25H) links (plaquette %.3f), "
-                        "%d point-source RHS (%d columns x %d masses) in %d multi-RHS %s-inner launch(es) of %d, "
-                        "%s Schur form, each to true residual 1e-10" %
-                        (X, Y, Z, T, L5, ACTION["M5"], ACTION["b5"], ACTION["c5"],
-                         "/".join(str(m) for m in MASSES), plaq, nrhs, ncol, len(MASSES),
-                         GROUPS, args.inner, per, FORM_NAMES[args.schur_form]),
+            "workload": ("%dx%dx%dx%d L5=%d M5=%g b5=%g c5=%g m_q=%s, exp(i0.25H) links (plaquette %.3f), "
+                         "1 Gaussian RHS, plain FP64 CG on the %s Schur form to true residual 1e-10" %
+                         (X, Y, Z, T, L5, ACTION["M5"], ACTION["b5"], ACTION["c5"], MASSES[0], plaq,
+                          FORM_NAMES[form])) if fp64_workload else
+                        ("%dx%dx%dx%d L5=%d M5=%g b5=%g c5=%g m_q=%s, exp(i0.25H) links (plaquette %.3f), "
+                         "%d point-source RHS (%d columns x %d masses) in %d multi-RHS %s-inner launch(es) of %d, "
+                         "%s Schur form, each to true residual 1e-10" %
+                         (X, Y, Z, T, L5, ACTION["M5"], ACTION["b5"], ACTION["c5"],
+                          "/".join(str(m) for m in MASSES), plaq, nrhs, ncol, len(MASSES),
+                          GROUPS, args.inner, per, FORM_NAMES[form])),
             "name": args.workload,
-            "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": args.inner,
-            "schur_form": args.schur_form, "b5": ACTION["b5"], "c5": ACTION["c5"],
+            "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": inner_name,
+            "schur_form": form, "b5": ACTION["b5"], "c5": ACTION["c5"],
             "launch_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), tune)} if tune else None),
             "solve_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), solve_tune)} if solve_tune else None),
         },
         "solve": {
-            "seconds": round(ms_per_step / 1e3, 4),
+            "seconds": round(t_step, 4),
             "iters": [i["iters"] for i in infos],
             "reliable_updates": [i["reliable_updates"] for i in infos],
             "max_true_resid": max(i["true_resid"] for i in infos),
             "all_within_1e-10": bool(all_ok),
             "model_GFLOPs": round(step_flops / (ms_per_step * 1e-3) / 1e9, 1),
+            "model_bytes": step_bytes,
+            "err_vs_fp64": [float("%.3g" % e) for e in errs] if errs else None,
         },
         "fp64_cg": fp64,
-        "speedup_mixed_multirhs_vs_fp64": (round(fp64["seconds_all_columns"] / (ms_per_step / 1e3), 3)
-                                           if fp64 else None),
+        "mixed_solve": other,
+        "speedup_mixed_multirhs_vs_fp64": (round(fp64["seconds_all_columns"] / t_step, 3) if fp64 else None),
+        "dslash_GBps": roof["achieved"] if roof else None,
         "dslash": {k: dict(ms=round(v["ms"], 4), GBps=round(v["GBps"], 1), frac=round(v["GBps"] / HBM_PEAK_GBS, 4),
                            GFLOPs=round(v["GFLOPs"], 1)) for k, v in micro.items()},
         "roofline": roof,
@@ -1143,6 +1310,9 @@ def main():
         "paper": "QUDA double-half MDWF solver, 1250 GFLOP/s on 2x K40 (Surface), 1785 on 4x K80 dies "
                  "(RZHasGPU), volume not stated (context only)",
     }
+    if fp64_workload:
+        out["note"] = ("FP64 working set of one hop launch (in + out + links) is about %.0f MB, so part of it can "
+                       "sit in the 256 MB Infinity Cache" % ((2 * Vh * 192 + V * 4 * 144) / 1e6))
     print(json.dumps(out), flush=True)
     M.mdwf_destroy(ctx)
 

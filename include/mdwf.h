@@ -138,6 +138,12 @@ typedef struct {
     double max_seconds;  /* > 0: a time limit for the call; once it has run
                             this long every unconverged RHS stops as at
                             max_iter (ERR_NOCONV, best x written); 0 = none */
+    const double *const *x_ref; /* optional reference solutions, one per RHS
+                            (NULL = none): canonical full FP64 fields in the
+                            memory space of x (host for mdwf_solve, device for
+                            mdwf_solve_dev), e.g. the plain FP64 CG solutions
+                            of the same systems.  Each is read once, after its
+                            RHS has been solved, to fill info.err_vs_ref */
 } mdwf_solver_opts;
 
 typedef struct {
@@ -154,6 +160,10 @@ typedef struct {
                              RHS together); else 0 */
     int hop_rhs;          /* right-hand sides in those launches                   */
     int hop_samples;      /* iterations sampled                                   */
+    double err_vs_ref;    /* ||x - x_ref|| / ||x_ref|| in FP64 over the full 5D
+                             field when opts.x_ref is given, else -1 (a mixed-
+                             precision solution against the FP64 one: the
+                             per-solve error of the mixed solver, Sec. VII)    */
 } mdwf_solve_info;
 
 /* Create a context for one lattice geometry on HIP device `hip_device`.
@@ -168,15 +178,23 @@ void mdwf_destroy(mdwf_ctx *ctx);
  * is NULL).  Valid until the next call on the same context. */
 const char *mdwf_last_error(const mdwf_ctx *ctx);
 
-/* Copy gauge links from host memory (canonical layout, FP64) to the device,
- * in FP64, FP32 and FP16 native link layouts, with the antiperiodic time sign
- * folded into the links on the last time slice. */
+/* Copy the SU(3) gauge links U_mu(x) the Wilson hop of D_W uses (Sec. I:
+ * the 4D links are copied onto every fifth-dimension slice) from host memory
+ * (canonical layout, FP64) to the device, in FP64, FP32 and FP16 native link
+ * layouts (the three precisions of the mixed solver, Sec. VII), with the
+ * antiperiodic time sign folded into the links on the last time slice.
+ * Synchronous.  ERR_ARG on a null pointer. */
 mdwf_status mdwf_load_gauge(mdwf_ctx *ctx, const double *U);
 
 /* Same as mdwf_load_gauge from a device pointer in the canonical layout. */
 mdwf_status mdwf_load_gauge_dev(mdwf_ctx *ctx, const double *U_dev);
 
-/* Set M5, b5, c5, L5, m_q (paper Sec. II).  Validates as documented above. */
+/* Set M5, b5, c5, L5, m_q (paper Sec. II, the Moebius kernel, and Sec. III.A,
+ * the tuned parameters).  Validates as documented above.  Waits for the work
+ * already enqueued on the context's stream, which reads the coefficient
+ * table this call replaces; launches that mdwf_apply_dev enqueued on another
+ * stream must have completed before this call (the caller synchronizes that
+ * stream). */
 mdwf_status mdwf_set_action(mdwf_ctx *ctx, const mdwf_action *act);
 
 /* Bytes of one field of the given kind and precision in the native layout. */
@@ -189,8 +207,12 @@ mdwf_status mdwf_pack_dev(mdwf_ctx *ctx, mdwf_prec prec, mdwf_field_kind kind,
 mdwf_status mdwf_unpack_dev(mdwf_ctx *ctx, mdwf_prec prec, mdwf_field_kind kind,
                             const void *native_dev, double *canon_dev, void *stream);
 
-/* Apply an operator to a host canonical FP64 field; the arithmetic runs on the
- * device in precision `prec` (input rounded to it, output widened back). */
+/* Apply an operator of the list above -- D5 (the Moebius operator, Sec. II),
+ * the even-odd Schur complements (Sec. VII) or their parts -- to a host
+ * canonical FP64 field; the arithmetic runs on the device in precision
+ * `prec` (input rounded to it, output widened back).  Synchronous.  ERR_ARG
+ * on a bad operator, precision or null pointer; ERR_STATE before
+ * mdwf_set_action / mdwf_load_gauge. */
 mdwf_status mdwf_apply(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const double *in, double *out);
 
 /* Apply an operator to device native fields in precision `prec` on `stream`
@@ -199,7 +221,24 @@ mdwf_status mdwf_apply(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const double *
 mdwf_status mdwf_apply_dev(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const void *in, void *out,
                            void *stream);
 
-/* Solve D5 x_k = b_k for k < nrhs (host canonical full FP64 fields).
+/* Apply an operator to nrhs device native fields at once, right-hand side k
+ * at in + k * stride and out + k * stride (bytes; stride >= the field's
+ * bytes, a multiple of 256), each with its own quark mass mq[k] (host array;
+ * NULL = the action's m_q for all).  Every launch takes all RHS together and
+ * reads each link once for them, as the solver's multi-RHS iterations do
+ * (Sec. III.A: propagators at several masses and sources), in the launch
+ * shape installed for `prec` (mdwf_autotune_solve).  Symmetric-form ops are
+ * not batched here (ERR_ARG).  Asynchronous on `stream` (NULL = the context's
+ * stream); in and out must not overlap.  Allocates (grow-only, kept by the
+ * context) a coefficient table and, for the Schur ops, the odd temporary of
+ * nrhs fields. */
+mdwf_status mdwf_apply_batch_dev(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, int nrhs, const void *in, void *out,
+                                 size_t stride, const double *mq, void *stream);
+
+/* Solve D5 x_k = b_k for k < nrhs (host canonical full FP64 fields): the
+ * MDWF propagator solves of the paper (Sec. III.A) by CG on the normal
+ * equations of the even-odd system (Sec. VII), in FP64 or with the FP32 /
+ * FP16 inner solve and FP64 reliable updates of the mixed solver (Sec. VII).
  * mq: per-RHS quark mass (NULL = the action's m_q); all other action
  * parameters are shared.  info: array of nrhs records (may be NULL).
  * All RHS share every operator launch; when their vectors do not fit in
@@ -216,8 +255,18 @@ mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, 
                            void *stream);
 
 /* Fill opts with defaults: tol 1e-10, max_iter 100000, inner F64, delta 0.1,
- * check_every 1, use_graph 0, profile_iters 0, schur_form 0, max_seconds 0. */
+ * check_every 1, use_graph 0, profile_iters 0, schur_form 0, max_seconds 0,
+ * x_ref NULL. */
 void mdwf_default_opts(mdwf_solver_opts *opts);
+
+/* Device bytes a solve of nrhs RHS on this lattice at fifth-dimension extent
+ * L5 allocates (its memory plan: per RHS x_hi and b' in FP64, r, p, p', s, q
+ * in the inner precision and an FP32 x_lo when mixed; shared FP64 scratch,
+ * the hop temporary, the canonical staging field when host_io, and a
+ * margin for small tables).  Host arithmetic only, no device needed.
+ * ERR_ARG on a bad geometry, L5, precision or nrhs < 1. */
+mdwf_status mdwf_solve_footprint(const mdwf_geometry *geom, int L5, mdwf_prec inner, int nrhs, int host_io,
+                                 size_t *bytes);
 
 /* Launch shape of the hop kernels for one storage precision. */
 typedef struct {
@@ -367,7 +416,10 @@ void mdwf_server_destroy(mdwf_server *srv);
 const char *mdwf_server_last_error(const mdwf_server *srv);
 
 /* Upload a gauge field (host canonical, as mdwf_load_gauge); *field_id
- * names it in requests. */
+ * names it in requests.  Its resident links come out of the budget: queued
+ * requests are re-split into sub-batches that fit the smaller budget, and a
+ * queued request of which not even one RHS fits any more ends at once with
+ * ERR_OOM (its mdwf_server_wait returns that status). */
 mdwf_status mdwf_server_add_field(mdwf_server *srv, const mdwf_geometry *geom, const double *U, int *field_id);
 
 /* Queue a solve of nrhs RHS on field_id with action act (mq: per-RHS masses

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <new>
+#include <vector>
 
 #include "ctx.h"
 
@@ -428,6 +429,17 @@ void mdwf_default_opts(mdwf_solver_opts* o) {
     o->profile_iters = 0;
     o->schur_form = 0;
     o->max_seconds = 0.0;
+    o->x_ref = nullptr;
+}
+
+mdwf_status mdwf_solve_footprint(const mdwf_geometry* geom, int L5, mdwf_prec inner, int nrhs, int host_io,
+                                 size_t* bytes) {
+    if (!geom || !bytes || nrhs < 1 || L5 < 1 || L5 > kMaxL5 || !valid_prec(inner)) return MDWF_ERR_ARG;
+    const int L[4] = {geom->X, geom->Y, geom->Z, geom->T};
+    for (int k = 0; k < 4; ++k)
+        if (L[k] < 2 || (L[k] & 1)) return MDWF_ERR_ARG;
+    *bytes = solve_footprint(plan_geo(*geom, L5), Prec(inner), nrhs, host_io != 0);
+    return MDWF_OK;
 }
 
 static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_device) {
@@ -487,11 +499,18 @@ mdwf_status mdwf_set_action(mdwf_ctx* c, const mdwf_action* a) {
         return fail(c, MDWF_ERR_ARG, "non-finite action parameter");
     mdwf_status s = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
     if (s) return s;
+    // launches already enqueued on the context's stream read the coefficient
+    // table and the geometry's L5: let them finish before either changes
+    s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+    if (s) return s;
     c->act = *a;
     c->geo.L5 = a->L5;
     c->geo.Vh = c->geo.Vh4 * a->L5;
     const RhsCoef cf[2] = {make_coef(*a, a->mq), make_coef_sym(*a, a->mq)};
-    s = hip_check(c, hipMemcpy(c->d_coef1, cf, sizeof(cf), hipMemcpyHostToDevice), "coefficient upload");
+    s = hip_check(c, hipMemcpyAsync(c->d_coef1, cf, sizeof(cf), hipMemcpyHostToDevice, c->stream),
+                  "coefficient upload");
+    if (s) return s;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "coefficient upload");
     if (s) return s;
     c->have_action = true;
     return MDWF_OK;
@@ -536,6 +555,40 @@ mdwf_status mdwf_apply_dev(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, const void* 
     const size_t hb = half_field_bytes(Prec(prec), c->geo.Vh);
     const size_t stride = op_full(op) ? 2 * hb : hb;
     return apply_native(c, op, Prec(prec), in, out, stride, 1, c->d_coef1, nullptr, st);
+}
+
+mdwf_status mdwf_apply_batch_dev(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, int nrhs, const void* in, void* out,
+                                 size_t stride, const double* mq, void* stream) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!valid_prec(prec) || op < 0 || op >= MDWF_OP_COUNT) return fail(c, MDWF_ERR_ARG, "bad operator or precision");
+    if (nrhs < 1) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1");
+    if (!in || !out) return fail(c, MDWF_ERR_ARG, "null field pointer");
+    const size_t hb = half_field_bytes(Prec(prec), c->geo.Vh);
+    const size_t fb = op_full(op) ? 2 * hb : hb;
+    if (stride < fb || stride % 256 != 0)
+        return fail(c, MDWF_ERR_ARG, "stride must be at least the field's bytes and a multiple of 256");
+    const char* ib = static_cast<const char*>(in);
+    char* ob = static_cast<char*>(out);
+    const size_t span = stride * size_t(nrhs - 1) + fb;
+    if (ib < ob + span && ob < ib + span) return fail(c, MDWF_ERR_ARG, "in and out must not overlap");
+    std::vector<RhsCoef> hc(2 * size_t(nrhs));
+    for (int k = 0; k < nrhs; ++k) {
+        const double m = mq ? mq[k] : c->act.mq;
+        if (!(m >= 0.0 && m <= 1.0)) return fail(c, MDWF_ERR_ARG, "need 0 <= mq <= 1");
+        hc[k] = make_coef(c->act, m);
+        hc[nrhs + k] = make_coef_sym(c->act, m);
+    }
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    RhsCoef* dc = static_cast<RhsCoef*>(buf(c, "batch_coef", hc.size() * sizeof(RhsCoef), &s));
+    if (!dc) return s;
+    if ((s = hip_check(c, hipMemcpyAsync(dc, hc.data(), hc.size() * sizeof(RhsCoef), hipMemcpyHostToDevice, st),
+                       "coefficient upload")))
+        return s;
+    // the table is reused by the next call: keep the host copy alive until
+    // the upload has read it
+    if ((s = hip_check(c, hipStreamSynchronize(st), "coefficient upload"))) return s;
+    return apply_native(c, op, Prec(prec), in, out, stride, nrhs, dc, nullptr, st);
 }
 
 mdwf_status mdwf_apply(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, const double* in, double* out) {

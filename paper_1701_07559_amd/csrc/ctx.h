@@ -77,9 +77,19 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b, doubl
                             const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st);
 
 namespace mdwf {
+// Device memory plan of a solve (bytes): per_rhs resident vectors of one RHS,
+// shared FP64 scratch (and host I/O staging), the hop temporary per RHS of a
+// launch chunk, and a margin for the small tables.
+struct SolvePlan {
+    size_t per_rhs, shared, tmp_per_rhs, margin;
+};
+SolvePlan solve_plan(const Geo& g, Prec inner, bool host_io);
 // Device bytes a solve of nrhs RHS allocates (solver vectors, shared
 // scratch, hop temporary for all RHS at once), as its memory plan counts them.
 size_t solve_footprint(const Geo& g, Prec inner, int nrhs, bool host_io);
+// Geometry of a lattice at fifth-dimension extent L5 (sizes only: enough for
+// memory plans, not for launches).
+Geo plan_geo(const mdwf_geometry& geom, int L5);
 // Free the solver's device buffers held by the context (grow-only otherwise).
 void release_solver_buffers(mdwf_ctx* c);
 // Make dst use src's resident links (same geometry; src must outlive dst).

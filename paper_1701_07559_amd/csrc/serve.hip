@@ -39,6 +39,7 @@ struct Request {
     std::vector<const double*> b;
     std::vector<double*> x;
     std::vector<double> mq;
+    std::vector<const double*> xref;   // reference solutions (opts.x_ref), or empty
     mdwf_solver_opts opts{};
     size_t footprint = 0;       // of one sub-batch
     int batch = 0;              // RHS per sub-batch
@@ -80,12 +81,7 @@ mdwf_status sfail(mdwf_server* s, mdwf_status st, const std::string& msg) {
 
 // footprint of a request (solver buffers with host I/O; links are resident)
 size_t footprint(const GaugeField& f, const mdwf_action& a, int nrhs, mdwf_prec inner) {
-    Geo g{};
-    g.X = f.geom.X; g.Y = f.geom.Y; g.Z = f.geom.Z; g.T = f.geom.T;
-    g.Vh4 = g.X * g.Y * g.Z * g.T / 2;
-    g.L5 = a.L5;
-    g.Vh = g.Vh4 * a.L5;
-    return solve_footprint(g, Prec(inner), nrhs, true);
+    return solve_footprint(plan_geo(f.geom, a.L5), Prec(inner), nrhs, true);
 }
 
 void worker_loop(mdwf_server* s) {
@@ -128,6 +124,7 @@ void worker_loop(mdwf_server* s) {
             const int k = std::min(r->batch, n - k0);
             mdwf_solver_opts ok = r->opts;   // the time limit covers the whole request
             if (r->opts.max_seconds > 0.0) ok.max_seconds = std::max(1e-9, r->opts.max_seconds - (wall() - r->t_start));
+            ok.x_ref = r->xref.empty() ? nullptr : r->xref.data() + k0;
             const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0, &ok,
                                               r->info.data() + k0);
             if (sk == MDWF_OK) continue;
@@ -198,11 +195,35 @@ mdwf_status mdwf_server_add_field(mdwf_server* s, const mdwf_geometry* geom, con
         return sfail(s, st, msg);
     }
     release_solver_buffers(c);   // drop the upload staging
-    std::lock_guard<std::mutex> lk(s->m);
-    const size_t gb = gauge_bytes(c);
-    s->budget = s->budget > gb ? s->budget - gb : 0;   // the links stay resident
-    s->fields.push_back({*geom, c});
-    *field_id = int(s->fields.size()) - 1;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        const size_t gb = gauge_bytes(c);
+        s->budget = s->budget > gb ? s->budget - gb : 0;   // the links stay resident
+        s->fields.push_back({*geom, c});
+        *field_id = int(s->fields.size()) - 1;
+        // queued requests were sized for the old budget: shrink their
+        // sub-batches to fit the new one, and fail those whose single RHS no
+        // longer fits (they could never be admitted)
+        for (auto it = s->pending.begin(); it != s->pending.end();) {
+            Request& r = s->reqs[*it];
+            const GaugeField& fld = s->fields[r.field];
+            while (r.batch > 0 && footprint(fld, r.act, r.batch, r.opts.inner) > s->budget) --r.batch;
+            if (r.batch > 0) {
+                r.footprint = footprint(fld, r.act, r.batch, r.opts.inner);
+                ++it;
+                continue;
+            }
+            r.status = MDWF_ERR_OOM;
+            r.err = "after a gauge field was added, one RHS of this request needs " +
+                    std::to_string(footprint(fld, r.act, 1, r.opts.inner)) + " device bytes, the budget is " +
+                    std::to_string(s->budget);
+            r.t_start = r.t_end = wall();
+            r.done = true;
+            it = s->pending.erase(it);
+        }
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
     return MDWF_OK;
 }
 
@@ -226,6 +247,12 @@ mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* 
     if (mq) r.mq.assign(mq, mq + nrhs);
     mdwf_default_opts(&r.opts);
     if (opts) r.opts = *opts;
+    if (r.opts.x_ref) {   // copied like b and x; the fields stay the caller's
+        r.xref.assign(r.opts.x_ref, r.opts.x_ref + nrhs);
+        for (int k = 0; k < nrhs; ++k)
+            if (!r.xref[k]) return sfail(s, MDWF_ERR_ARG, "null reference solution pointer");
+    }
+    r.opts.x_ref = nullptr;
     r.opts.use_graph = 0;       // each solve runs eagerly on its worker's stream
     r.opts.profile_iters = 0;
     r.info.assign(nrhs, mdwf_solve_info{});

@@ -185,14 +185,36 @@ double now() {
 }  // namespace
 
 namespace mdwf {
-size_t solve_footprint(const Geo& g, Prec inner, int n, bool host_io) {
+// The solver's device memory plan, shared by the allocation below and by
+// every footprint estimate (the server's admission, mdwf_solve_footprint).
+SolvePlan solve_plan(const Geo& g, Prec inner, bool host_io) {
     const bool mixed = inner != P64;
     const size_t H64 = half_field_bytes(P64, g.Vh), Hi = half_field_bytes(inner, g.Vh);
     const size_t Hx = half_field_bytes(P32, g.Vh);
-    const size_t per_rhs = 2 * H64 + (mixed ? 5 * Hi + Hx : 5 * H64);
-    const size_t shared = 6 * H64 + (host_io ? size_t(2) * g.Vh * 24 * sizeof(double) : 0);
-    const size_t tmp = size_t(n) * (mixed ? Hi : H64);   // hop temporary for every RHS at once
-    return per_rhs * n + shared + tmp + (size_t(64) << 20);
+    SolvePlan pl;
+    // x_hi and b' in FP64; r, p, p', s, q in the inner precision; the FP32
+    // inner solution x_lo when mixed
+    pl.per_rhs = 2 * H64 + (mixed ? 5 * Hi + Hx : 5 * H64);
+    // FP64 scratch be, bo, r_hi, t64, ye, xo; the canonical staging field
+    pl.shared = 6 * H64 + (host_io ? size_t(2) * g.Vh * 24 * sizeof(double) : 0);
+    pl.tmp_per_rhs = mixed ? Hi : H64;   // hop temporary of one RHS of a chunk
+    pl.margin = size_t(64) << 20;        // coefficient tables, scalars, partials
+    return pl;
+}
+
+Geo plan_geo(const mdwf_geometry& geom, int L5) {
+    Geo g{};
+    g.X = geom.X; g.Y = geom.Y; g.Z = geom.Z; g.T = geom.T;
+    g.Xh = geom.X / 2;
+    g.Vh4 = int(size_t(geom.X) * geom.Y * geom.Z * geom.T / 2);
+    g.L5 = L5;
+    g.Vh = g.Vh4 * L5;
+    return g;
+}
+
+size_t solve_footprint(const Geo& g, Prec inner, int n, bool host_io) {
+    const SolvePlan pl = solve_plan(g, inner, host_io);
+    return pl.per_rhs * n + pl.shared + pl.tmp_per_rhs * n + pl.margin;
 }
 }  // namespace mdwf
 
@@ -239,22 +261,22 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
 
     // memory plan: the hop temporary is shared by `chunk` RHS; shrink the
     // chunk when the whole batch would not fit next to the resident state
-    const size_t per_rhs = 2 * S.H64 + (S.mixed ? 4 * S.Hi + S.Hx : 4 * S.H64);
-    const size_t shared = 6 * S.H64 + (host_io ? S.canon_bytes : 0);
+    const SolvePlan plan = solve_plan(g, S.pi, host_io);
+    const size_t per_rhs = plan.per_rhs, shared = plan.shared;
     size_t held = 0;
     for (auto& kv : c->bufs)
         if (kv.first.rfind("sv_", 0) == 0) held += kv.second.n;
     size_t freeb = 0, totalb = 0;
     if (!S.hipok(hipMemGetInfo(&freeb, &totalb), "hipMemGetInfo")) return S.err;
     const size_t avail = freeb + held;
-    const size_t need_fixed = per_rhs * n + shared + (size_t(64) << 20);
+    const size_t need_fixed = per_rhs * n + shared + plan.margin;
     int cap = 0;   // explicit sub-batch size (memory / tests)
     if (const char* e = std::getenv("MDWF_SOLVE_BATCH")) cap = std::max(0, std::atoi(e));
-    if (n > 1 && (need_fixed + S.Hi > avail || (cap > 0 && cap < n))) {
+    if (n > 1 && (need_fixed + plan.tmp_per_rhs > avail || (cap > 0 && cap < n))) {
         // the batch does not fit even with a one-RHS hop temporary: solve it
         // in consecutive sub-batches that do (same arithmetic per RHS)
-        const size_t base = shared + (size_t(64) << 20);
-        int nb = avail > base + per_rhs + S.Hi ? int((avail - base - S.Hi) / per_rhs) : 1;
+        const size_t base = shared + plan.margin;
+        int nb = avail > base + per_rhs + plan.tmp_per_rhs ? int((avail - base - plan.tmp_per_rhs) / per_rhs) : 1;
         if (cap > 0) nb = std::min(nb, cap);
         if (nb < n) {
             mdwf_status worst = MDWF_OK;
@@ -262,6 +284,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
                 const int nk = std::min(nb, n - k0);
                 mdwf_solver_opts ok = o;   // the time limit covers the whole call
                 if (o.max_seconds > 0.0) ok.max_seconds = std::max(1e-9, o.max_seconds - (now() - t_start));
+                if (o.x_ref) ok.x_ref = o.x_ref + k0;
                 const mdwf_status r = mdwf_solve_impl(c, nk, b_in + k0, x_out + k0, host_io, mq ? mq + k0 : nullptr,
                                                       &ok, info ? info + k0 : nullptr, st);
                 if (r != MDWF_OK && r != MDWF_ERR_NOCONV && r != MDWF_ERR_NUMERIC) return r;
@@ -271,9 +294,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         }
     }
     S.chunk = n;
-    if (need_fixed + size_t(n) * S.Hi > avail) {
+    if (need_fixed + size_t(n) * plan.tmp_per_rhs > avail) {
         const size_t room = avail > need_fixed ? avail - need_fixed : 0;
-        S.chunk = int(std::max<size_t>(1, room / S.Hi));
+        S.chunk = int(std::max<size_t>(1, room / plan.tmp_per_rhs));
         if (S.chunk > n) S.chunk = n;
     }
     if (const char* e = std::getenv("MDWF_SOLVE_CHUNK")) {   // explicit chunk (memory / tests)
@@ -313,6 +336,9 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     if (host_io) {
         ALLOC(canon, "sv_canon", S.canon_bytes);
     }
+    if (o.x_ref)
+        for (int k = 0; k < n; ++k)
+            if (!o.x_ref[k]) return fail(c, MDWF_ERR_ARG, "null reference solution pointer");
     ALLOC(coef, "sv_coef", 2 * sizeof(RhsCoef) * n);
     ALLOC(sc, "sv_scal", sizeof(CGScal) * n);
     ALLOC(act, "sv_act", sizeof(int) * n);
@@ -344,7 +370,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         if (!S.hipok(hipEventCreateWithFlags(&S.ev[e], hipEventDisableTiming), "event")) return S.err;
 
     std::vector<int> active(n, 1), done(n, 0), iters(n, 0), updates(n, 0), restarts(n, 0), stopped(n, 0);
-    std::vector<double> true_res(n, -1.0), bnorm(n, 0.0), rmax(n, 0.0);
+    std::vector<double> true_res(n, -1.0), bnorm(n, 0.0), rmax(n, 0.0), err_ref(n, -1.0);
 
     // ---- source preparation, one RHS at a time: b'_e = b_e + 1/2 D_eo B K5^-1 b_o
     for (int k = 0; k < n && !S.err; ++k) {
@@ -441,6 +467,23 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             if (host_io)
                 S.hipok(hipMemcpyAsync(x_out[k], S.canon, S.canon_bytes, hipMemcpyDeviceToHost, st), "x D2H");
             S.hipok(hipStreamSynchronize(st), "x write");
+            if (o.x_ref) {
+                // ||x - x_ref|| / ||x_ref|| over both parities, x_ref packed
+                // into the source scratch (free once the residual is known)
+                const double* ref = o.x_ref[k];
+                if (host_io) {
+                    S.hipok(hipMemcpyAsync(S.canon, ref, S.canon_bytes, hipMemcpyHostToDevice, st), "x_ref H2D");
+                    ref = S.canon;
+                }
+                launch_pack_parity(g, P64, 1, 0, ref, S.be, st);
+                launch_pack_parity(g, P64, 1, 1, ref, S.bo, st);
+                launch_axpby(g, P64, 1.0, xk, -1.0, S.be, S.ye, S.H64, 1, nullptr, S.part, st);
+                const double de = S.fetch_sums(S.nbb, 1, nullptr)[0];
+                launch_axpby(g, P64, 1.0, S.xo, -1.0, S.bo, S.t64, S.H64, 1, nullptr, S.part, st);
+                const double dd = S.fetch_sums(S.nbb, 1, nullptr)[0];
+                const double nr = S.norm2_one(P64, S.be) + S.norm2_one(P64, S.bo);
+                err_ref[k] = nr > 0.0 ? std::sqrt((de + dd) / nr) : (de + dd > 0.0 ? INFINITY : 0.0);
+            }
         }
         return bnorm[k] > 0.0 ? std::sqrt(se + so) / bnorm[k] : 0.0;
     };
@@ -585,10 +628,17 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     const double blI = link_site_bytes(S.pi, g.L5), bl64 = link_site_bytes(P64, g.L5);
     // A, B, A^+, B^+ (10 inner fields), r -= alpha q (3), the direction update
     // (3 inner fields) and, every second iteration, x read and written with
-    // one more inner read: 16.5 inner fields and one x field per iteration
-    const double it_bytes = g.Vh * (16.5 * bsI + bsX + 4 * blI);
+    // one more inner read: 16.5 inner fields and one x field per iteration.
+    // The four hop launches read the links once for all RHS of a chunk, so
+    // an RHS is charged its share of them.
+    const double rpl = double(std::min(S.chunk, n));
+    const double it_bytes = g.Vh * (16.5 * bsI + bsX + 4 * blI / rpl);
     const double it_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 5 * 48.0);
-    const double up_bytes = g.Vh * (5 * bs64 + 2 * bl64 + 3 * bs64 + bs64 + bsI + 5 * bsI + 2 * blI + 2 * bs64 + 2 * bsX);
+    // reliable update: FP64 S on one RHS (5 fields, 2 link sets), r_hi =
+    // b' - S x (3), conversion (FP64 read, inner write), the batched inner
+    // S^+ (5 inner fields, its share of 2 link sets), the flush x_hi += x_lo
+    const double up_bytes = g.Vh * (5 * bs64 + 2 * bl64 + 3 * bs64 + bs64 + bsI + 5 * bsI + 2 * blI / rpl +
+                                    2 * bs64 + 2 * bsX);
     const double up_flops = g.Vh * (2 * (2832.0 + 48.0 * g.L5) + 3 * 48.0);
     for (int k = 0; k < n; ++k) {
         if (stopped[k] == 2) result = MDWF_ERR_NUMERIC;
@@ -604,6 +654,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             for (int q = 0; q < 4; ++q) info[k].hop_us[q] = hop_us[q];
             info[k].hop_rhs = prof_done ? std::min(S.chunk, n) : 0;
             info[k].hop_samples = prof_done;
+            info[k].err_vs_ref = err_ref[k];
         }
     }
     if (result == MDWF_ERR_NOCONV) fail(c, result, "solver reached max_iter before the target residual");

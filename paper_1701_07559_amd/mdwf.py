@@ -53,14 +53,14 @@ class mdwf_action(C.Structure):
 class mdwf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner", C.c_int), ("delta", C.c_double),
                 ("check_every", C.c_int), ("use_graph", C.c_int), ("profile_iters", C.c_int),
-                ("schur_form", C.c_int), ("max_seconds", C.c_double)]
+                ("schur_form", C.c_int), ("max_seconds", C.c_double), ("x_ref", C.c_void_p)]
 
 
 class mdwf_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("restarts", C.c_int),
                 ("true_resid", C.c_double), ("seconds", C.c_double), ("model_flops", C.c_double),
                 ("model_bytes", C.c_double), ("hop_us", C.c_double * 4), ("hop_rhs", C.c_int),
-                ("hop_samples", C.c_int)]
+                ("hop_samples", C.c_int), ("err_vs_ref", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -118,6 +118,8 @@ def _load():
         "mdwf_unpack_dev": ([vp, ip, ip, vp, vp, vp], ip),
         "mdwf_apply": ([vp, ip, ip, vp, vp], ip),
         "mdwf_apply_dev": ([vp, ip, ip, vp, vp, vp], ip),
+        "mdwf_apply_batch_dev": ([vp, ip, ip, ip, vp, vp, C.c_size_t, C.POINTER(dp), vp], ip),
+        "mdwf_solve_footprint": ([C.POINTER(mdwf_geometry), ip, ip, ip, ip, C.POINTER(C.c_size_t)], ip),
         "mdwf_solve": ([vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
                         C.POINTER(mdwf_solve_info)], ip),
         "mdwf_solve_dev": ([vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
@@ -223,6 +225,24 @@ def mdwf_apply_dev(ctx, op, prec, in_ptr, out_ptr, stream=None):
     _check(ctx, lib.mdwf_apply_dev(ctx, int(op), int(prec), int(in_ptr), int(out_ptr), stream))
 
 
+def mdwf_apply_batch_dev(ctx, op, prec, nrhs, in_ptr, out_ptr, stride, mq=None, stream=None):
+    """Apply op to nrhs device native fields `stride` bytes apart, RHS k with
+    mass mq[k] (None = the action's), all in one launch set."""
+    m = (C.c_double * int(nrhs))(*mq) if mq is not None else None
+    _check(ctx, lib.mdwf_apply_batch_dev(ctx, int(op), int(prec), int(nrhs), int(in_ptr), int(out_ptr),
+                                         int(stride), m, stream))
+
+
+def mdwf_solve_footprint(dims, L5, inner, nrhs, host_io=True):
+    """Device bytes a solve of nrhs RHS would allocate (no device needed)."""
+    g = mdwf_geometry(*[int(d) for d in dims], 1)
+    n = C.c_size_t()
+    st = lib.mdwf_solve_footprint(C.byref(g), int(L5), int(inner), int(nrhs), int(bool(host_io)), C.byref(n))
+    if st != MDWF_OK:
+        raise MdwfError(st, "bad footprint arguments")
+    return int(n.value)
+
+
 def mdwf_default_opts() -> mdwf_solver_opts:
     o = mdwf_solver_opts()
     lib.mdwf_default_opts(C.byref(o))
@@ -230,10 +250,22 @@ def mdwf_default_opts() -> mdwf_solver_opts:
 
 
 def _opts(opts):
+    """Options struct from a dict; x_ref (a list of canonical FP64 fields:
+    device pointers for *_dev calls, host complex128 arrays otherwise) is
+    kept alive on the returned struct."""
     o = mdwf_default_opts()
     if isinstance(opts, mdwf_solver_opts):
         return opts
     for k, v in (opts or {}).items():
+        if k == "x_ref":
+            if v is None:
+                continue
+            keep = [_c128(a) if isinstance(a, np.ndarray) else a for a in v]
+            ptrs = [a.ctypes.data if isinstance(a, np.ndarray) else int(a) for a in keep]
+            arr = (C.c_void_p * len(ptrs))(*ptrs)
+            o._x_ref_keep = (keep, arr)
+            o.x_ref = C.cast(arr, C.c_void_p).value
+            continue
         setattr(o, k, v)
     return o
 
@@ -446,7 +478,7 @@ def exported_symbols():
     """Names of the C entry points declared in include/mdwf.h."""
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
-            "mdwf_apply_dev", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
+            "mdwf_apply_dev", "mdwf_apply_batch_dev", "mdwf_solve_footprint", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
             "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
             "mdwf_plaquette_dev", "mdwf_gauss_smear_dev", "mdwf_wall_source_dev", "mdwf_project_4d_dev",
             "mdwf_mres_correlators_dev", "mdwf_pion_correlator_dev", "mdwf_server_create", "mdwf_server_destroy",

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -124,3 +125,32 @@ def test_source_flow_entry_points_reject_bad_arguments_without_device():
     assert L.mdwf_wilson_flow_dev(C.byref(g), p, 0.01, -1, None, None) == ARG
     assert L.mdwf_wilson_flow_dev(C.byref(mdwf.mdwf_geometry(4, 1, 4, 4, 0)), p, 0.01, 1, None, None) == ARG
     assert L.mdwf_plaquette_dev(C.byref(g), None, None, d) == ARG
+
+
+def test_solve_footprint_counts_every_solver_vector():
+    """The memory plan (no device needed): per RHS x_hi and b' in FP64 and five
+    inner vectors r, p, p', s, q (plus the FP32 x_lo when mixed), the hop
+    temporary per RHS, six shared FP64 half fields, the canonical staging
+    field with host I/O, and a 64 MiB margin."""
+    from paper_1701_07559_amd import mdwf
+
+    def a256(n):
+        return (n + 255) // 256 * 256
+
+    for dims, L5 in [((24, 24, 24, 64), 8), ((16, 16, 16, 48), 12), ((4, 4, 4, 8), 5)]:
+        Vh = int(np.prod(dims)) // 2 * L5
+        H = {0: a256(192 * Vh), 1: a256(96 * Vh), 2: a256(48 * Vh) + a256(4 * Vh)}
+        for inner in (0, 1, 2):
+            for n in (1, 3, 12):
+                for host_io in (False, True):
+                    mixed = inner != 0
+                    per = 2 * H[0] + (5 * H[inner] + H[1] if mixed else 5 * H[0])
+                    shared = 6 * H[0] + (2 * Vh * 24 * 8 if host_io else 0)
+                    want = per * n + shared + n * H[inner] + (64 << 20)
+                    assert mdwf.mdwf_solve_footprint(dims, L5, inner, n, host_io) == want
+    with pytest.raises(mdwf.MdwfError):
+        mdwf.mdwf_solve_footprint((3, 4, 4, 4), 8, 0, 1)
+    with pytest.raises(mdwf.MdwfError):
+        mdwf.mdwf_solve_footprint((4, 4, 4, 4), 0, 0, 1)
+    with pytest.raises(mdwf.MdwfError):
+        mdwf.mdwf_solve_footprint((4, 4, 4, 4), 8, 0, 0)
