@@ -164,6 +164,9 @@ typedef struct {
                              field when opts.x_ref is given, else -1 (a mixed-
                              precision solution against the FP64 one: the
                              per-solve error of the mixed solver, Sec. VII)    */
+    int launch_rhs;       /* right-hand sides that shared this RHS's operator
+                             launches (served requests: of every request in
+                             the shared solve)                                 */
 } mdwf_solve_info;
 
 /* Create a context for one lattice geometry on HIP device `hip_device`.
@@ -283,6 +286,12 @@ typedef struct {
                         together, RHS fastest (they share each tile's links);
                         groups follow each other; 0 = all RHS in one group    */
     double us;       /* measured time of one Schur application with this shape (us)   */
+    int plane_bt;    /* > 0 (dividing T): the bare hops (MDWF_OP_HOP_*) of FP32 and FP16
+                        run plane-staged: a workgroup copies each time plane of
+                        a 4x4x4 spatial block and its faces into LDS once and
+                        marches plane_bt planes along t (spatial extents
+                        multiples of 4, L5 <= 16, else the lane-per-site
+                        kernel runs); 0 = off */
 } mdwf_launch_tune;
 
 /* Autotuner: for each precision (index mdwf_prec), time one Schur operator
@@ -307,6 +316,12 @@ mdwf_status mdwf_autotune_solve(mdwf_ctx *ctx, const mdwf_solver_opts *opts, int
 
 /* Current launch shape of precision `prec` (defaults before autotuning). */
 mdwf_status mdwf_get_tune(const mdwf_ctx *ctx, mdwf_prec prec, mdwf_launch_tune *out);
+
+/* Install a launch shape for precision `prec` (e.g. one mdwf_autotune chose
+ * earlier).  Launches already enqueued keep the shape they were given.
+ * ERR_ARG if a tile extent does not divide the lattice's or plane_bt does not
+ * divide T. */
+mdwf_status mdwf_set_tune(mdwf_ctx *ctx, mdwf_prec prec, const mdwf_launch_tune *t);
 
 /* Model flop and byte counts for one application of an operator (per call). */
 mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, double *flops, double *bytes);
@@ -425,10 +440,17 @@ mdwf_status mdwf_server_add_field(mdwf_server *srv, const mdwf_geometry *geom, c
 /* Queue a solve of nrhs RHS on field_id with action act (mq: per-RHS masses
  * or NULL for act->mq; opts NULL = defaults; use_graph and profile_iters are
  * ignored; max_seconds > 0 is the request's time limit from the moment it
- * starts running, across its sub-batches).  Returns at once with *req_id.  A request whose footprint exceeds
- * the budget is split into sub-batches of the most RHS that fit, solved one
- * after another (bitwise the same results).  ERR_ARG on bad arguments,
- * ERR_OOM if not even one RHS fits the budget. */
+ * starts running, across its sub-batches).  Returns at once with *req_id.
+ * A request whose footprint exceeds the budget is split into sub-batches of
+ * the most RHS that fit, solved one after another (bitwise the same
+ * results).  When a worker takes the request at the head of the queue, the
+ * queued requests that can share its solve (same field, L5, M5, b5, c5 and
+ * solver options, none split) join it while the combined footprint fits, up
+ * to 24 RHS: their RHS then share every operator launch and its link loads,
+ * each with its own mass, and each request's results are still bitwise
+ * those of the same request solved alone (info.launch_rhs tells how many RHS
+ * shared the launches).  ERR_ARG on bad arguments, ERR_OOM if not even one
+ * RHS fits the budget. */
 mdwf_status mdwf_server_submit(mdwf_server *srv, int field_id, const mdwf_action *act, int nrhs,
                                const double *const *b, double *const *x, const double *mq,
                                const mdwf_solver_opts *opts, int *req_id);

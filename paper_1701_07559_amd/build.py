@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdwf.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "dslash.hip", "blas.hip", "solver.hip", "serve.hip", "flow.hip", "source.hip"]
+SOURCES = ["api.hip", "dslash.hip", "dslash_plane.hip", "blas.hip", "solver.hip", "serve.hip", "flow.hip", "source.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC",

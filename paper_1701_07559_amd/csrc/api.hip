@@ -168,6 +168,7 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
     g.nt_store[p] = t.nt_store ? 1 : 0;
     g.link_mode[p] = (t.link_mode >= 0 && t.link_mode <= 2) ? t.link_mode : 0;
     g.rhs_group[p] = t.rhs_group > 0 ? t.rhs_group : 0;
+    g.plane_bt[p] = (t.plane_bt > 0 && g.T % t.plane_bt == 0) ? t.plane_bt : 0;
 }
 
 void release_solver_buffers(mdwf_ctx* c) {
@@ -256,13 +257,16 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
         case MDWF_OP_SCHUR_SYM_DAG:
         case MDWF_OP_SCHUR_RP:
         case MDWF_OP_SCHUR_RP_DAG: {
-            void* tmp = buf(c, "apply_tmp", stride * nrhs, &s);
-            if (!tmp) return s;
             const bool dag = op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_SCHUR_SYM_DAG || op == MDWF_OP_SCHUR_RP_DAG;
             const bool sym = op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG;
             const int form = sym ? 1 : (op == MDWF_OP_SCHUR_RP || op == MDWF_OP_SCHUR_RP_DAG) ? 2 : 0;
-            void* tmp2 = sym && dag ? buf(c, "apply_tmp2", stride * nrhs, &s) : nullptr;
-            if (sym && dag && !tmp2) return s;
+            void* tmp = buf(c, "apply_tmp", stride * nrhs, &s);
+            if (!tmp) return s;
+            void* tmp2 = nullptr;
+            if (sym && dag) {
+                tmp2 = buf(c, "apply_tmp2", stride * nrhs, &s);
+                if (!tmp2) return s;
+            }
             schur_launch(g, c->gs, p, form, dag, in, out, tmp, tmp2, stride, nrhs, d_coef,
                          sym ? d_coef + nrhs : nullptr, d_active, nullptr, st);
             break;
@@ -383,7 +387,7 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     // of 4 (or 2) planes with t inside; the MDWF_TILE ("bx,by,bz,bt"),
     // MDWF_XCD_REMAP, MDWF_NT_STORE, MDWF_LINK_MODE and MDWF_RHS_GROUP
     // variables override it
-    mdwf_launch_tune t0{{g.Xh, g.Y, (g.Z % 4 == 0) ? 4 : 2, 1}, 1, 0, 0, 0, 0.0};
+    mdwf_launch_tune t0{{g.Xh, g.Y, (g.Z % 4 == 0) ? 4 : 2, 1}, 1, 0, 0, 0, 0.0, 0};
     if (const char* e = std::getenv("MDWF_TILE")) {
         int b[4];
         if (std::sscanf(e, "%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3]) == 4 && tile_fits(g, b))
@@ -393,6 +397,7 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     if (const char* e = std::getenv("MDWF_NT_STORE")) t0.nt_store = std::atoi(e) != 0;
     if (const char* e = std::getenv("MDWF_LINK_MODE")) t0.link_mode = std::atoi(e);
     if (const char* e = std::getenv("MDWF_RHS_GROUP")) t0.rhs_group = std::atoi(e);
+    if (const char* e = std::getenv("MDWF_PLANE_BT")) t0.plane_bt = std::atoi(e);
     for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
     if (hipMalloc(&c->d_coef1, 2 * sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
@@ -638,6 +643,18 @@ mdwf_status mdwf_get_tune(const mdwf_ctx* c, mdwf_prec prec, mdwf_launch_tune* o
     out->link_mode = c->geo.link_mode[prec];
     out->rhs_group = c->geo.rhs_group[prec];
     out->us = c->tuned_us[prec];
+    out->plane_bt = c->geo.plane_bt[prec];
+    return MDWF_OK;
+}
+
+mdwf_status mdwf_set_tune(mdwf_ctx* c, mdwf_prec prec, const mdwf_launch_tune* t) {
+    if (!c || !t) return fail(c, MDWF_ERR_ARG, "null argument");
+    if (!valid_prec(prec)) return fail(c, MDWF_ERR_ARG, "bad precision");
+    if (!tile_fits(c->geo, t->tile)) return fail(c, MDWF_ERR_ARG, "tile extents must divide the lattice's");
+    if (t->plane_bt < 0 || (t->plane_bt > 0 && c->geo.T % t->plane_bt))
+        return fail(c, MDWF_ERR_ARG, "plane_bt must divide T");
+    set_tune(c->geo, Prec(prec), *t);   // enqueued launches took the old shape by value
+    c->tuned_us[prec] = t->us;
     return MDWF_OK;
 }
 

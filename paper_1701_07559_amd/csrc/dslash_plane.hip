@@ -1,0 +1,407 @@
+// Plane-staged Wilson hop on every fifth-dimension slice (the Dslash of the
+// Moebius operator's D_W, arXiv:1701.07559, Sec. II, and its adjoint).
+//
+// The lane-per-5D-site hop (dslash.hip) reads each input spinor once per
+// neighbour, eight times, through the vector-memory path.  Here a workgroup
+// owns a 4 x 4 x 4 block of spatial sites (full coordinates) and a run of bt
+// time planes of one right-hand side, and marches along t.  For each input
+// plane it copies into LDS, once, every input-parity spinor its hops read
+// from that plane -- the 32 sites inside the block and the 48 on its six
+// faces, all L5 slices -- together with the 256 links the plane's terms use.
+// An input plane t feeds three output planes: its own (the six spatial hops),
+// t - 1 (the t+ hop) and t + 1 (the t- hop), so each thread carries the
+// accumulators of three planes and finishes one plane per step.
+//
+// Threads: the L5 slices of one output site in consecutive lanes, as in the
+// lane-per-site kernel; 32 output sites per plane.  LDS per workgroup: 80
+// spinor slots of L5 sites plus 256 links (see PlaneLds).
+#include "hop_device.h"
+
+namespace mdwf {
+
+constexpr int kPlaneSites = 32;      // output sites of one parity in a 4x4x4 block
+constexpr int kPlaneSlots = 80;      // input sites staged per plane (32 inside, 48 on faces)
+constexpr int kPlaneLinks = 256;     // 8 link sets x 32 sites
+constexpr int kPlaneMaxThreads = 512;
+
+// LDS layout of one staged plane for precision P: spinor slots of L5 5D
+// sites, each [blocks][L5] 16-byte units (FP16: then [L5] float norms), and
+// the links as [parts][256] 16-byte units (the short tail part in 8 / 4 bytes).
+template <Prec P> struct PlaneLds;
+template <> struct PlaneLds<P32> {
+    static constexpr int NB = 6;   // 16-byte blocks per 5D site
+    static constexpr int LP = 4;   // 16-byte link parts, then a float2 tail
+    static __host__ __device__ int slot_bytes(int L5) { return NB * 16 * L5; }
+    static __host__ __device__ int link_bytes() { return kPlaneLinks * (LP * 16 + 8); }
+};
+template <> struct PlaneLds<P16> {
+    static constexpr int NB = 3;
+    static constexpr int LP = 2;   // then a 4-byte tail
+    static __host__ __device__ int slot_bytes(int L5) { return (NB * 16 * L5 + 4 * L5 + 15) & ~15; }
+    static __host__ __device__ int link_bytes() { return kPlaneLinks * (LP * 16 + 4); }
+};
+
+struct PlaneDev {
+    int bt;            // time planes per workgroup
+    int nbx, nby, nbz, nbt;
+    int nthreads;
+    FastDiv fUnits;    // 16-byte spinor units per slot: NB * L5
+    FastDiv fL5;
+};
+
+// Position (lx, ly, lz) inside the block of staged slot `slot` of a plane
+// whose input-parity sites satisfy (lx + ly + lz + t) = ip (mod 2): slots
+// 0..31 inside the block (x fastest, parity-compressed), then eight per face
+// in the order x-, x+, y-, y+, z-, z+.
+__device__ __forceinline__ void slot_position(int slot, int cls, int& lx, int& ly, int& lz) {
+    if (slot < kPlaneSites) {
+        ly = (slot >> 1) & 3;
+        lz = slot >> 3;
+        lx = 2 * (slot & 1) + ((cls + ly + lz) & 1);
+        return;
+    }
+    const int f = (slot - kPlaneSites) & 7, face = (slot - kPlaneSites) >> 3;
+    const int v = (face & 1) ? 4 : -1;   // the fixed coordinate
+    const int b = f >> 1;
+    const int a = 2 * (f & 1) + ((cls + v + b) & 1);
+    if (face < 2) { lx = v; ly = a; lz = b; }
+    else if (face < 4) { ly = v; lx = a; lz = b; }
+    else { lz = v; lx = a; ly = b; }
+}
+
+// Slots of the six spatial neighbours of the output site at (lx, ly, lz):
+// inside the block, or on the face the hop leaves through.
+__device__ __forceinline__ int inner_slot(int lx, int ly, int lz) { return (lx >> 1) + 2 * (ly + 4 * lz); }
+
+template <Prec P> struct PlaneIO;
+
+template <> struct PlaneIO<P32> {
+    using R = float;
+    static __device__ __forceinline__ void spinor(const unsigned char* slot, int L5, int s, cx<float> v[12]) {
+        const nf4* p = reinterpret_cast<const nf4*>(slot) + s;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const nf4 w = p[k * L5];
+            v[2 * k] = {w.x, w.y};
+            v[2 * k + 1] = {w.z, w.w};
+        }
+    }
+    static __device__ __forceinline__ void link(const unsigned char* lds, int id, cx<float> U[9]) {
+        const nf4* p = reinterpret_cast<const nf4*>(lds) + id;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const nf4 w = p[k * kPlaneLinks];
+            U[2 * k] = {w.x, w.y};
+            U[2 * k + 1] = {w.z, w.w};
+        }
+        const nf2 t = reinterpret_cast<const nf2*>(lds + 4 * 16 * kPlaneLinks)[id];
+        U[8] = {t.x, t.y};
+    }
+    // copy one link from its global segment into LDS
+    static __device__ __forceinline__ void stage_link(const char* seg, size_t lblk, uint32_t i, unsigned char* lds,
+                                                      int id) {
+        nf4* p = reinterpret_cast<nf4*>(lds) + id;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k * kPlaneLinks] = ldu<nf4>(seg + k * lblk, i * 16u);
+        reinterpret_cast<nf2*>(lds + 4 * 16 * kPlaneLinks)[id] = ldu<nf2>(seg + 4 * lblk, i * 8u);
+    }
+};
+
+template <> struct PlaneIO<P16> {
+    using R = float;
+    // the stored binary16 pairs and the site's norm
+    static __device__ __forceinline__ float spinor_h(const unsigned char* slot, int L5, int s, h2 v[12]) {
+        const nu4* p = reinterpret_cast<const nu4*>(slot) + s;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const nu4 w = p[k * L5];
+            v[4 * k] = as_h2(w.x);
+            v[4 * k + 1] = as_h2(w.y);
+            v[4 * k + 2] = as_h2(w.z);
+            v[4 * k + 3] = as_h2(w.w);
+        }
+        return reinterpret_cast<const float*>(slot + 3 * 16 * L5)[s];
+    }
+    static __device__ __forceinline__ void link_h(const unsigned char* lds, int id, h2 U[9]) {
+        const nu4* p = reinterpret_cast<const nu4*>(lds) + id;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const nu4 w = p[k * kPlaneLinks];
+            U[4 * k] = as_h2(w.x);
+            U[4 * k + 1] = as_h2(w.y);
+            U[4 * k + 2] = as_h2(w.z);
+            U[4 * k + 3] = as_h2(w.w);
+        }
+        U[8] = as_h2(reinterpret_cast<const uint32_t*>(lds + 2 * 16 * kPlaneLinks)[id]);
+    }
+    static __device__ __forceinline__ void stage_link(const char* seg, size_t lblk, uint32_t i, unsigned char* lds,
+                                                      int id) {
+        nu4* p = reinterpret_cast<nu4*>(lds) + id;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) p[k * kPlaneLinks] = ldu<nu4>(seg + k * lblk, i * 16u);
+        reinterpret_cast<uint32_t*>(lds + 2 * 16 * kPlaneLinks)[id] = ldu<uint32_t>(seg + 2 * lblk, i * 4u);
+    }
+};
+
+// One hop term of direction (MU, DIR) from a staged spinor slot and link.
+template <Prec P, bool DAG, int MU, int DIR>
+__device__ __forceinline__ void plane_term(cx<typename Real<P>::T> acc[12], const unsigned char* slot, int L5, int s,
+                                           const unsigned char* lk, int lid) {
+    if constexpr (P == P16) {
+        h2 psi[12], U[9];
+        const float scale = PlaneIO<P16>::spinor_h(slot, L5, s, psi);
+        PlaneIO<P16>::link_h(lk, lid, U);
+        constexpr int sg = ((DIR > 0) != DAG) ? 1 : -1;
+        h2 z1[6], z2[6];
+        project_h<MU, sg, (DIR > 0)>(psi, z1, z2);
+        cx<float> w[6];
+        su3_mul_h<(DIR > 0)>(U, z1, z2, w);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) w[c] = scale * w[c];
+        reconstruct_add<MU>(float(sg), w, acc);
+    } else {
+        using R = typename Real<P>::T;
+        cx<R> psi[12], U[9];
+        PlaneIO<P>::spinor(slot, L5, s, psi);
+        PlaneIO<P>::link(lk, lid, U);
+        constexpr R sg = ((DIR > 0) != DAG) ? R(1) : R(-1);
+        cx<R> h[6], w[6];
+        project<MU>(sg, psi, h);
+        su3_mul<(DIR > 0)>(U, h, w);
+        reconstruct_add<MU>(sg, w, acc);
+    }
+}
+
+// Link sets of a staged plane t (output sites k of plane t unless noted):
+// 0/1 x forward (at k) / backward (at its x- neighbour), 2/3 y, 4/5 z,
+// 6 t forward at the output site of plane t-1 above slot k, 7 t backward at
+// the input site of slot k (plane t), used by plane t+1.
+template <Prec P, int K>
+__global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, const HopDev a, const PlaneDev pd) {
+    using R = typename Real<P>::T;
+    using IO = PlaneIO<P>;
+    constexpr bool DAG = HopTraits<K>::dag;
+    extern __shared__ __align__(16) unsigned char plane_lds[];
+    const int L5 = g.L5;
+    const int slot_bytes = PlaneLds<P>::slot_bytes(L5);
+    unsigned char* sp = plane_lds;
+    unsigned char* lk = plane_lds + size_t(kPlaneSlots) * slot_bytes;
+
+    // workgroup -> right-hand side (fastest, they share links), block, t-run
+    const int lb = g.xcd_remap[P] ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
+    const int rhs = lb % a.nrhs;
+    int rest = lb / a.nrhs;
+    const int bx = rest % pd.nbx;
+    rest /= pd.nbx;
+    const int by = rest % pd.nby;
+    rest /= pd.nby;
+    const int bz = rest % pd.nbz;
+    const int btr = rest / pd.nbz;
+    if (a.active && !a.active[rhs]) return;   // uniform over the workgroup
+    const int x0 = 4 * bx, y0 = 4 * by, z0 = 4 * bz, t0 = btr * pd.bt;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int spw = 64 / L5;
+    const int sw = lane / L5;
+    const int s = lane - sw * L5;
+    const int k = wave * spw + sw;   // output site of the plane
+    const bool valid = sw < spw && k < kPlaneSites;
+    const int kk = valid ? k : 0;
+    const int ky = (kk >> 1) & 3, kz = kk >> 3;
+    const int p = a.out_parity, ip = 1 - p;
+
+    const char* src = static_cast<const char*>(at_rhs(a.in, a.stride, rhs));
+    char* dst = static_cast<char*>(at_rhs(a.out, a.stride, rhs));
+    const size_t sblk = size_t(g.Vh) * 16;
+    const size_t lblk = size_t(g.Vh4) * 16;
+    const int units = int(pd.fUnits.d);   // 16-byte spinor units per slot
+
+    auto gidx = [&](int lx, int ly, int lz, int t) -> uint32_t {
+        int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        gx = gx < 0 ? gx + g.X : (gx >= g.X ? gx - g.X : gx);
+        gy = gy < 0 ? gy + g.Y : (gy >= g.Y ? gy - g.Y : gy);
+        gz = gz < 0 ? gz + g.Z : (gz >= g.Z ? gz - g.Z : gz);
+        return uint32_t((gx >> 1) + g.Xh * (gy + g.Y * (gz + g.Z * t)));
+    };
+
+    // spatial part of the parity-compressed index of every slot, for both
+    // classes of input sites (planes alternate between them)
+    int* tab = reinterpret_cast<int*>(lk + PlaneLds<P>::link_bytes());
+    for (int e = tid; e < 2 * kPlaneSlots; e += pd.nthreads) {
+        int lx, ly, lz;
+        slot_position(e % kPlaneSlots, e / kPlaneSlots, lx, ly, lz);
+        tab[e] = int(gidx(lx, ly, lz, 0));
+    }
+
+    cx<R> acc_prev[12], acc_cur[12], acc_next[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc_prev[c] = acc_cur[c] = acc_next[c] = {R(-0.0), R(-0.0)};
+
+    for (int tp = t0 - 1; tp <= t0 + pd.bt; ++tp) {
+        const int t = tp < 0 ? tp + g.T : (tp >= g.T ? tp - g.T : tp);
+        const int cin = (ip + t) & 1;        // class of the input sites of plane t
+        const bool edge = tp < t0 || tp >= t0 + pd.bt;   // only the t hops use this plane
+        const int nslots = edge ? kPlaneSites : kPlaneSlots;
+        __syncthreads();   // every thread is done with the previous plane
+        // ---- stage the plane's input spinors: unit u = (slot, block, slice)
+        const int* ctab = tab + cin * kPlaneSlots;
+        const uint32_t tofs = uint32_t(g.Xh * g.Y * g.Z) * uint32_t(t);
+        for (int u = tid; u < nslots * units; u += pd.nthreads) {
+            const int slot = int(pd.fUnits.div(uint32_t(u)));
+            const int r = u - slot * units;
+            const int blk = int(pd.fL5.div(uint32_t(r)));
+            const uint32_t j = (uint32_t(ctab[slot]) + tofs) * uint32_t(L5) + uint32_t(r - blk * L5);
+            *reinterpret_cast<nu4*>(sp + size_t(slot) * slot_bytes + size_t(r) * 16) =
+                ldu<nu4>(src + blk * sblk, j * 16u);
+        }
+        if constexpr (P == P16) {
+            const char* nsrc = src + align256(3 * sblk);
+            for (int u = tid; u < nslots * L5; u += pd.nthreads) {
+                const int slot = int(pd.fL5.div(uint32_t(u)));
+                const int ss = u - slot * L5;
+                const uint32_t j = (uint32_t(ctab[slot]) + tofs) * uint32_t(L5) + uint32_t(ss);
+                reinterpret_cast<float*>(sp + size_t(slot) * slot_bytes + 48 * L5)[ss] = ldu<float>(nsrc, j * 4u);
+            }
+        }
+        // ---- stage the links of the plane's terms
+        for (int id = tid; id < kPlaneLinks; id += pd.nthreads) {
+            const int set = id >> 5, q = id & 31;
+            if (edge && set < 6) continue;
+            const int qy = (q >> 1) & 3, qz = q >> 3;
+            const int mu = set >> 1;
+            const bool fwd = (set & 1) == 0;
+            int lx, ly = qy, lz = qz, tl = t;
+            if (set < 6) {
+                lx = 2 * (q & 1) + ((p + t + qy + qz) & 1);   // output site q of plane t
+                if (!fwd) {
+                    if (mu == 0) lx -= 1;
+                    else if (mu == 1) ly -= 1;
+                    else lz -= 1;
+                }
+            } else {
+                lx = 2 * (q & 1) + ((cin + qy + qz) & 1);      // input slot q of plane t
+                if (fwd) tl = t == 0 ? g.T - 1 : t - 1;        // output site of plane t-1
+            }
+            const char* seg = (fwd ? a.links_out : a.links_in) + size_t(mu) * a.lseg;
+            IO::stage_link(seg, lblk, gidx(lx, ly, lz, tl), lk, id);
+        }
+        __syncthreads();
+        if (!valid) continue;
+        // ---- plane t-1 gets its t+ term and is finished
+        if (tp - 1 >= t0) {
+            plane_term<P, DAG, 3, +1>(acc_prev, sp + size_t(kk) * slot_bytes, L5, s, lk, 6 * 32 + kk);
+            const int lx = 2 * (kk & 1) + ((p + tp - 1 + ky + kz) & 1);
+            const int tw = tp - 1 >= g.T ? tp - 1 - g.T : tp - 1;
+            const uint32_t j = gidx(lx, ky, kz, tw) * uint32_t(L5) + uint32_t(s);
+            if (g.nt_store[P]) Field<P>::template store<true>(dst, g.Vh, int(j), acc_prev);
+            else Field<P>::store(dst, g.Vh, int(j), acc_prev);
+        }
+        // ---- plane t: the six spatial terms
+        if (!edge) {
+            const int lx = 2 * (kk & 1) + ((p + t + ky + kz) & 1);
+            const int sxp = lx < 3 ? inner_slot(lx + 1, ky, kz) : 40 + 2 * kz + (ky >> 1);
+            const int sxm = lx > 0 ? inner_slot(lx - 1, ky, kz) : 32 + 2 * kz + (ky >> 1);
+            const int syp = ky < 3 ? inner_slot(lx, ky + 1, kz) : 56 + 2 * kz + (lx >> 1);
+            const int sym = ky > 0 ? inner_slot(lx, ky - 1, kz) : 48 + 2 * kz + (lx >> 1);
+            const int szp = kz < 3 ? inner_slot(lx, ky, kz + 1) : 72 + 2 * ky + (lx >> 1);
+            const int szm = kz > 0 ? inner_slot(lx, ky, kz - 1) : 64 + 2 * ky + (lx >> 1);
+            plane_term<P, DAG, 0, +1>(acc_cur, sp + size_t(sxp) * slot_bytes, L5, s, lk, 0 * 32 + kk);
+            plane_term<P, DAG, 0, -1>(acc_cur, sp + size_t(sxm) * slot_bytes, L5, s, lk, 1 * 32 + kk);
+            plane_term<P, DAG, 1, +1>(acc_cur, sp + size_t(syp) * slot_bytes, L5, s, lk, 2 * 32 + kk);
+            plane_term<P, DAG, 1, -1>(acc_cur, sp + size_t(sym) * slot_bytes, L5, s, lk, 3 * 32 + kk);
+            plane_term<P, DAG, 2, +1>(acc_cur, sp + size_t(szp) * slot_bytes, L5, s, lk, 4 * 32 + kk);
+            plane_term<P, DAG, 2, -1>(acc_cur, sp + size_t(szm) * slot_bytes, L5, s, lk, 5 * 32 + kk);
+        }
+        // ---- plane t+1 starts with its t- term
+        if (tp + 1 < t0 + pd.bt)
+            plane_term<P, DAG, 3, -1>(acc_next, sp + size_t(kk) * slot_bytes, L5, s, lk, 7 * 32 + kk);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            acc_prev[c] = acc_cur[c];
+            acc_cur[c] = acc_next[c];
+            acc_next[c] = {R(-0.0), R(-0.0)};
+        }
+    }
+}
+
+// The plane-staged kernel applies when the launch shape asks for it, the
+// operator is the bare hop, the spatial extents are multiples of 4, T of bt,
+// L5 <= 16 and the plane fits in LDS; it returns false otherwise.
+template <Prec P>
+static bool launch_plane_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
+    const int bt = g.plane_bt[P];
+    if constexpr (P == P64) return false;
+    else {
+        if (bt <= 0 || (L.kind != HOP_BARE && L.kind != HOP_BARE_DAG)) return false;
+        if (g.X % 4 || g.Y % 4 || g.Z % 4 || g.T % bt || g.L5 > 16) return false;
+        const int spw = 64 / g.L5;
+        const int nthreads = 64 * ((kPlaneSites + spw - 1) / spw);
+        const size_t lds = size_t(kPlaneSlots) * PlaneLds<P>::slot_bytes(g.L5) + PlaneLds<P>::link_bytes() +
+                           2 * kPlaneSlots * sizeof(int);
+        if (nthreads > kPlaneMaxThreads || lds > plane_lds_limit()) return false;
+        HopDev a{};
+        a.out = L.out;
+        a.in = L.in;
+        a.centre = L.centre;
+        const size_t seg = gs.seg_bytes[P];
+        a.lseg = seg;
+        a.links_out = gs.seg[P] + size_t(L.out_parity) * 4 * seg;
+        a.links_in = gs.seg[P] + size_t(1 - L.out_parity) * 4 * seg;
+        a.stride = L.stride;
+        a.nrhs = L.nrhs;
+        a.out_parity = L.out_parity;
+        a.coef = L.coef;
+        a.active = L.active;
+        a.partials = nullptr;
+        PlaneDev pd{};
+        pd.bt = bt;
+        pd.nbx = g.X / 4; pd.nby = g.Y / 4; pd.nbz = g.Z / 4; pd.nbt = g.T / bt;
+        pd.nthreads = nthreads;
+        pd.fUnits = FastDiv(uint32_t(PlaneLds<P>::NB * g.L5));
+        pd.fL5 = FastDiv(uint32_t(g.L5));
+        a.nblk = pd.nbx * pd.nby * pd.nbz * pd.nbt;
+        L.nblocks_per_rhs = a.nblk;
+        const dim3 grid(a.nblk * L.nrhs);
+        if (L.kind == HOP_BARE)
+            hipLaunchKernelGGL((k_hop_plane<P, HOP_BARE>), grid, dim3(nthreads), lds, st, g, a, pd);
+        else
+            hipLaunchKernelGGL((k_hop_plane<P, HOP_BARE_DAG>), grid, dim3(nthreads), lds, st, g, a, pd);
+        return true;
+    }
+}
+
+bool launch_hop_plane(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
+    switch (L.prec) {
+        case P32: return launch_plane_p<P32>(g, gs, L, st);
+        case P16: return launch_plane_p<P16>(g, gs, L, st);
+        default: return false;
+    }
+}
+
+// Dynamic LDS the plane kernels may take: every instantiation is allowed the
+// whole of a CU's LDS (set once per process).
+size_t plane_lds_limit() {
+    static size_t limit = [] {
+        int dev = 0, v = 0;
+        size_t lim = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            lim = size_t(v);
+        (void)hipGetLastError();
+        const int li = int(lim);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P32, HOP_BARE>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P32, HOP_BARE_DAG>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P16, HOP_BARE>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P16, HOP_BARE_DAG>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
+        (void)hipGetLastError();
+        return lim;
+    }();
+    return limit;
+}
+
+}  // namespace mdwf

@@ -96,6 +96,7 @@ struct Geo {
     int nt_store[3];    // write hop outputs with non-temporal stores
     int link_mode[3];   // 0 per-lane links, 1 LDS stage, 2 lane gather
     int rhs_group[3];   // multi-RHS launches: RHS per group sweeping the tiles together (0 = all)
+    int plane_bt[3];    // > 0: bare hops by the plane-staged kernel, this many time planes per workgroup
 };
 
 // Coefficients of one right-hand side (its mass); all fifth-dimension
@@ -379,6 +380,10 @@ struct HopLaunch {
 enum FifthKind { FIFTH_K5 = 0, FIFTH_K5INV, FIFTH_B, FIFTH_BINV };
 
 void launch_hop(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st);
+// The plane-staged bare hop (dslash_plane.hip) when the launch shape selects
+// it and it applies to this launch; false (nothing launched) otherwise.
+bool launch_hop_plane(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st);
+size_t plane_lds_limit();
 void launch_fifth(const Geo& g, Prec p, FifthKind kind, int dag, const void* in, void* out, size_t stride,
                   int nrhs, const RhsCoef* coef, const int* active, hipStream_t st);
 int hop_blocks_per_rhs(const Geo& g);

@@ -15,6 +15,7 @@
 // result equals the same solve run alone.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -28,6 +29,8 @@
 using namespace mdwf;
 
 namespace {
+
+constexpr int kMaxShared = 24;   // RHS of one shared solve at most
 
 double wall() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -43,6 +46,7 @@ struct Request {
     mdwf_solver_opts opts{};
     size_t footprint = 0;       // of one sub-batch
     int batch = 0;              // RHS per sub-batch
+    int shared_rhs = 0;         // RHS of the solve it ran in (its own, or a shared one)
     double t_submit = 0, t_start = 0, t_end = 0;
     bool done = false;
     mdwf_status status = MDWF_OK;
@@ -84,12 +88,36 @@ size_t footprint(const GaugeField& f, const mdwf_action& a, int nrhs, mdwf_prec 
     return solve_footprint(plan_geo(f.geom, a.L5), Prec(inner), nrhs, true);
 }
 
+// Requests that can share one solve, so that every hop launch of it reads
+// the links once for all their RHS: the same field, the same action apart
+// from the masses (each RHS keeps its own), the same solver options, and
+// neither split into sub-batches.
+bool same_opts(const mdwf_solver_opts& a, const mdwf_solver_opts& b) {
+    return a.tol == b.tol && a.max_iter == b.max_iter && a.inner == b.inner && a.delta == b.delta &&
+           a.check_every == b.check_every && a.schur_form == b.schur_form && a.max_seconds == b.max_seconds;
+}
+bool can_share(const Request& a, const Request& b) {
+    return a.field == b.field && a.act.L5 == b.act.L5 && a.act.M5 == b.act.M5 && a.act.b5 == b.act.b5 &&
+           a.act.c5 == b.act.c5 && same_opts(a.opts, b.opts) && a.xref.empty() == b.xref.empty() &&
+           a.batch == int(a.b.size()) && b.batch == int(b.b.size());
+}
+
+// Status of one request of a shared solve from its RHS's records.
+mdwf_status request_status(const Request& r) {
+    mdwf_status st = MDWF_OK;
+    for (const mdwf_solve_info& i : r.info) {
+        if (!std::isfinite(i.true_resid)) return MDWF_ERR_NUMERIC;
+        if (i.true_resid > r.opts.tol) st = MDWF_ERR_NOCONV;
+    }
+    return st;
+}
+
 void worker_loop(mdwf_server* s) {
     (void)hipSetDevice(s->device);
     std::map<std::pair<int, int>, mdwf_ctx*> ctxs;   // (field, L5) -> context on this worker's stream
     for (;;) {
-        int id = 0;
-        Request* r = nullptr;
+        std::vector<Request*> grp;
+        size_t fp = 0;
         GaugeField f;
         {
             std::unique_lock<std::mutex> lk(s->m);
@@ -99,15 +127,39 @@ void worker_loop(mdwf_server* s) {
                 return s->reserved + f.footprint <= s->budget;
             });
             if (s->pending.empty()) break;   // stop requested and nothing left
-            id = s->pending.front();
+            Request* r = &s->reqs[s->pending.front()];
             s->pending.pop_front();
-            r = &s->reqs[id];
-            s->reserved += r->footprint;
-            s->peak = std::max(s->peak, s->reserved);
-            r->t_start = wall();
+            grp.push_back(r);
+            fp = r->footprint;
             f = s->fields[r->field];   // copied: add_field may grow the list meanwhile
+            // queued requests that can share this solve join it while the
+            // combined footprint fits (they would otherwise wait behind it)
+            int n = int(r->b.size());
+            if (r->batch == n) {
+                for (auto it = s->pending.begin(); it != s->pending.end() && n < kMaxShared;) {
+                    Request& q = s->reqs[*it];
+                    const int nq = int(q.b.size());
+                    const size_t fq = footprint(f, r->act, n + nq, r->opts.inner);
+                    if (can_share(*r, q) && n + nq <= kMaxShared && s->reserved + fq <= s->budget) {
+                        grp.push_back(&q);
+                        n += nq;
+                        fp = fq;
+                        it = s->pending.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            s->reserved += fp;
+            s->peak = std::max(s->peak, s->reserved);
+            const double t0 = wall();
+            for (Request* q : grp) {
+                q->t_start = t0;
+                q->shared_rhs = n;
+            }
         }
-        // the request record (a map node) is not touched by other threads until done
+        // the request records (map nodes) are not touched by other threads until done
+        Request* r = grp[0];
         mdwf_ctx*& c = ctxs[{r->field, r->act.L5}];
         mdwf_status st = MDWF_OK;
         if (!c) {
@@ -116,32 +168,66 @@ void worker_loop(mdwf_server* s) {
         }
         if (st == MDWF_OK) st = mdwf_set_action(c, &r->act);
         std::string msg = st == MDWF_OK ? std::string() : std::string(mdwf_last_error(c));
-        const int n = int(r->b.size());
-        // sub-batches in order; one that did not converge still wrote its
-        // results, so the rest still run; a hard error stops the request
-        for (int k0 = 0; st == MDWF_OK || st == MDWF_ERR_NOCONV || st == MDWF_ERR_NUMERIC; k0 += r->batch) {
-            if (k0 >= n) break;
-            const int k = std::min(r->batch, n - k0);
-            mdwf_solver_opts ok = r->opts;   // the time limit covers the whole request
-            if (r->opts.max_seconds > 0.0) ok.max_seconds = std::max(1e-9, r->opts.max_seconds - (wall() - r->t_start));
-            ok.x_ref = r->xref.empty() ? nullptr : r->xref.data() + k0;
-            const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0, &ok,
-                                              r->info.data() + k0);
-            if (sk == MDWF_OK) continue;
-            const bool hard = sk != MDWF_ERR_NOCONV && sk != MDWF_ERR_NUMERIC;
-            if (st == MDWF_OK || hard) {
-                st = sk;
-                msg = mdwf_last_error(c);
+        if (grp.size() == 1) {
+            const int n = int(r->b.size());
+            // sub-batches in order; one that did not converge still wrote its
+            // results, so the rest still run; a hard error stops the request
+            for (int k0 = 0; st == MDWF_OK || st == MDWF_ERR_NOCONV || st == MDWF_ERR_NUMERIC; k0 += r->batch) {
+                if (k0 >= n) break;
+                const int k = std::min(r->batch, n - k0);
+                mdwf_solver_opts ok = r->opts;   // the time limit covers the whole request
+                if (r->opts.max_seconds > 0.0)
+                    ok.max_seconds = std::max(1e-9, r->opts.max_seconds - (wall() - r->t_start));
+                ok.x_ref = r->xref.empty() ? nullptr : r->xref.data() + k0;
+                const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0, &ok,
+                                                  r->info.data() + k0);
+                if (sk == MDWF_OK) continue;
+                const bool hard = sk != MDWF_ERR_NOCONV && sk != MDWF_ERR_NUMERIC;
+                if (st == MDWF_OK || hard) {
+                    st = sk;
+                    msg = mdwf_last_error(c);
+                }
+            }
+            r->status = st;
+            r->err = msg;
+        } else {
+            // one solve for the whole group: RHS of every request side by
+            // side, each with its own mass; its results go back per request
+            std::vector<const double*> b;
+            std::vector<double*> x;
+            std::vector<double> mq;
+            std::vector<const double*> xref;
+            for (Request* q : grp) {
+                b.insert(b.end(), q->b.begin(), q->b.end());
+                x.insert(x.end(), q->x.begin(), q->x.end());
+                mq.insert(mq.end(), q->mq.begin(), q->mq.end());
+                xref.insert(xref.end(), q->xref.begin(), q->xref.end());
+            }
+            std::vector<mdwf_solve_info> info(b.size());
+            if (st == MDWF_OK) {
+                mdwf_solver_opts ok = r->opts;
+                ok.x_ref = xref.empty() ? nullptr : xref.data();
+                st = mdwf_solve(c, int(b.size()), b.data(), x.data(), mq.data(), &ok, info.data());
+                if (st != MDWF_OK) msg = mdwf_last_error(c);
+            }
+            const bool hard = st != MDWF_OK && st != MDWF_ERR_NOCONV && st != MDWF_ERR_NUMERIC;
+            size_t k0 = 0;
+            for (Request* q : grp) {
+                std::copy(info.begin() + k0, info.begin() + k0 + q->b.size(), q->info.begin());
+                k0 += q->b.size();
+                q->status = hard ? st : request_status(*q);
+                q->err = q->status == MDWF_OK ? std::string() : msg;
             }
         }
         if (c) release_solver_buffers(c);
         {
             std::lock_guard<std::mutex> lk(s->m);
-            r->status = st;
-            r->err = msg;
-            r->t_end = wall();
-            r->done = true;
-            s->reserved -= r->footprint;
+            const double t1 = wall();
+            for (Request* q : grp) {
+                q->t_end = t1;
+                q->done = true;
+            }
+            s->reserved -= fp;
         }
         s->cv_done.notify_all();
         s->cv_work.notify_all();

@@ -655,6 +655,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             info[k].hop_rhs = prof_done ? std::min(S.chunk, n) : 0;
             info[k].hop_samples = prof_done;
             info[k].err_vs_ref = err_ref[k];
+            info[k].launch_rhs = std::min(S.chunk, n);
         }
     }
     if (result == MDWF_ERR_NOCONV) fail(c, result, "solver reached max_iter before the target residual");

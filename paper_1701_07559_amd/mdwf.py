@@ -60,7 +60,7 @@ class mdwf_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("restarts", C.c_int),
                 ("true_resid", C.c_double), ("seconds", C.c_double), ("model_flops", C.c_double),
                 ("model_bytes", C.c_double), ("hop_us", C.c_double * 4), ("hop_rhs", C.c_int),
-                ("hop_samples", C.c_int), ("err_vs_ref", C.c_double)]
+                ("hop_samples", C.c_int), ("err_vs_ref", C.c_double), ("launch_rhs", C.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,8 +69,8 @@ class mdwf_solve_info(C.Structure):
 
 
 class mdwf_launch_tune(C.Structure):
-    _fields_ = [("tile", C.c_int * 4), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int), ("rhs_group", C.c_int),
-                ("us", C.c_double)]
+    _fields_ = [("tile", C.c_int * 4), ("xcd_remap", C.c_int), ("nt_store", C.c_int), ("link_mode", C.c_int),
+                ("rhs_group", C.c_int), ("us", C.c_double), ("plane_bt", C.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -129,6 +129,7 @@ def _load():
         "mdwf_autotune": ([vp, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_autotune_solve": ([vp, C.POINTER(mdwf_solver_opts), ip, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_get_tune": ([vp, ip, C.POINTER(mdwf_launch_tune)], ip),
+        "mdwf_set_tune": ([vp, ip, C.POINTER(mdwf_launch_tune)], ip),
         "mdwf_wilson_flow": ([C.POINTER(mdwf_geometry), ip, vp, dp, ip, C.POINTER(dp)], ip),
         "mdwf_wilson_flow_dev": ([C.POINTER(mdwf_geometry), vp, dp, ip, vp, C.POINTER(dp)], ip),
         "mdwf_plaquette_dev": ([C.POINTER(mdwf_geometry), vp, vp, C.POINTER(dp)], ip),
@@ -328,6 +329,17 @@ def mdwf_get_tune(ctx, prec):
     return t.as_dict()
 
 
+def mdwf_set_tune(ctx, prec, tune):
+    """Install a launch shape (a dict as mdwf_get_tune returns) for prec."""
+    t = mdwf_launch_tune()
+    for k, v in tune.items():
+        if k == "tile":
+            t.tile = (C.c_int * 4)(*v)
+        else:
+            setattr(t, k, v)
+    _check(ctx, lib.mdwf_set_tune(ctx, int(prec), C.byref(t)))
+
+
 def mdwf_wilson_flow(dims, U, eps, nsteps, hip_device=0):
     """Wilson gradient flow of a host canonical gauge field (a flowed copy is
     returned); returns (U_flowed, (plaquette before, after))."""
@@ -479,7 +491,7 @@ def exported_symbols():
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
             "mdwf_apply_dev", "mdwf_apply_batch_dev", "mdwf_solve_footprint", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
-            "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
+            "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_set_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
             "mdwf_plaquette_dev", "mdwf_gauss_smear_dev", "mdwf_wall_source_dev", "mdwf_project_4d_dev",
             "mdwf_mres_correlators_dev", "mdwf_pion_correlator_dev", "mdwf_server_create", "mdwf_server_destroy",
             "mdwf_server_last_error", "mdwf_server_add_field", "mdwf_server_submit", "mdwf_server_wait",

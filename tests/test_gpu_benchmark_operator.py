@@ -101,6 +101,7 @@ def test_benchmark_operator_batched_sampled_sites(bench_ctx, prec, dag):
     hidx = torch.from_numpy(sites // 2).to(dev)
     out_c = torch.empty_like(canon[0])
     worst = 0.0
+    oracle.use_threads(WORKERS)   # the site oracle's full-lattice B^-1 / K5 passes, same values
     for k in range(NRHS):
         M.mdwf_unpack_dev(ctx, prec, M.MDWF_HALF_EVEN, nat_out.data_ptr() + k * stride, out_c.data_ptr(), st)
         got = out_c.view(L5, -1, 24)[:, hidx].cpu().numpy()                 # [L5, n, 24] doubles
@@ -112,6 +113,7 @@ def test_benchmark_operator_batched_sampled_sites(bench_ctx, prec, dag):
         worst = max(worst, e)
         assert e <= TOL[prec], "RHS %d (field %d, m %g): worst per-site error %.3e" % (
             k, rhs_field[k], rhs_mass[k], e)
+    oracle.use_threads(1)
     print("[bench-operator] worst per-site relative error %.3e" % worst, flush=True)
 
 

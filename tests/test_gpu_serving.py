@@ -159,3 +159,42 @@ def test_request_larger_than_the_budget_runs_in_sub_batches(M):
     assert [i["iters"] for i in info] == its
     for a, b in zip(xs, ref):
         assert np.array_equal(a, b)
+
+
+def test_queued_requests_share_one_solve(M):
+    """Requests of the same field, L5 and options that wait behind a running
+    one are solved together when the worker frees up: their RHS share every
+    operator launch (launch_rhs counts all of them), each keeps its own mass,
+    and each request's solutions are bitwise those of the request alone."""
+    dims, L5 = (8, 8, 8, 8), 8
+    U = I.random_links(dims, 0.3, 68)
+    big = (16, 16, 16, 16)
+    Ub = I.random_links(big, 0.3, 69)
+    srv = M.Server(mem_budget=0, max_active=1)
+    try:
+        fid = srv.add_field(dims, U)
+        fbig = srv.add_field(big, Ub)
+        # the worker is busy with a long FP64 solve meanwhile
+        bb = I.gaussian_source(big, L5, 70)
+        xb = np.zeros_like(bb)
+        r0 = srv.submit(fbig, 1.3, 1.5, 0.5, 0.01, L5, [bb], [xb], opts=dict(tol=1e-11))
+        reqs = [([0.05], (71,)), ([0.1, 0.02], (72, 73)), ([0.2], (74,))]
+        jobs = []
+        for masses, seeds in reqs:
+            bs = [I.gaussian_source(dims, L5, s) for s in seeds]
+            xs = [np.zeros_like(b) for b in bs]
+            rid = srv.submit(fid, 1.3, 1.5, 0.5, masses[0], L5, bs, xs, masses=masses, opts=dict(inner=2))
+            jobs.append((rid, masses, bs, xs))
+        st0, info0, _ = srv.wait(r0)
+        assert st0 == M.MDWF_OK and info0[0]["launch_rhs"] == 1
+        total = sum(len(m) for m, _ in reqs)
+        for rid, masses, bs, xs in jobs:
+            st, info, _ = srv.wait(rid)
+            assert st == M.MDWF_OK and all(i["true_resid"] <= 1e-10 for i in info)
+            assert all(i["launch_rhs"] == total for i in info), [i["launch_rhs"] for i in info]
+            ref, its = alone(M, dims, U, L5, masses, 2, bs)
+            assert [i["iters"] for i in info] == its
+            for a, b in zip(xs, ref):
+                assert np.array_equal(a, b), "a request in a shared solve differs from the request alone"
+    finally:
+        srv.close()
