@@ -224,6 +224,23 @@ mdwf_status mdwf_apply(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const double *
 mdwf_status mdwf_apply_dev(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const void *in, void *out,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * mdwf_apply_dev (asynchronous on `stream`, NULL = the context's stream),
+ * but it calls no allocating routine.  The Schur operators' odd-parity
+ * intermediate (two of them for MDWF_OP_SCHUR_SYM_DAG) lives in a static
+ * device array of MDWF_STATIC_SCRATCH_BYTES that the library holds on each
+ * device it runs on until the process ends; an operator whose intermediate
+ * does not fit fails with ERR_ARG.  The intermediate is written in full
+ * before it is read, so nothing in the array needs clearing.  Every call on
+ * one device shares that device's array and it keeps the last call's
+ * contents: calls whose work overlaps on one device (different streams or
+ * host threads, or a caller's graph replayed beside them) race, and the
+ * caller must order them.  The caller still owns and passes in and out. */
+#define MDWF_STATIC_SCRATCH_BYTES (256u << 20)
+mdwf_status mdwf_apply_dev_noalloc(mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, const void *in, void *out,
+                                   void *stream);
+
 /* Apply an operator to nrhs device native fields at once, right-hand side k
  * at in + k * stride and out + k * stride (bytes; stride >= the field's
  * bytes, a multiple of 256), each with its own quark mass mq[k] (host array;

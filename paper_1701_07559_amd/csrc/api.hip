@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -12,6 +13,47 @@
 using namespace mdwf;
 
 static thread_local std::string g_create_err;
+
+// ------------------------------------------ allocation-free scratch memory
+// Device scratch of mdwf_apply_dev_noalloc: the odd-parity intermediate of the
+// Schur operators (two of them for the symmetric adjoint), for callers that
+// cannot allocate.  Each device holds its own copy for the life of the
+// process.  On the host the array's name is only a stand-in for the symbol:
+// its device address is looked up once per device (scratch_init, from
+// mdwf_create) and only that address is handed to kernels.
+static constexpr size_t kStaticScratchBytes = size_t(MDWF_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With `dev` current: the device address of its copy of the scratch array.
+void scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[dev]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_err[dev] = e;
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[dev] = true;
+}
+
+void* scratch_ptr(int dev, hipError_t* err) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch_done[dev]) {
+        *err = hipErrorNotInitialized;
+        return nullptr;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
+}  // namespace
 
 namespace mdwf {
 
@@ -227,7 +269,7 @@ void schur_launch(const Geo& g, const GaugeSet& gs, Prec p, int form, bool dag, 
 }
 
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
-                         const RhsCoef* d_coef, const int* d_active, hipStream_t st) {
+                         const RhsCoef* d_coef, const int* d_active, hipStream_t st, void* scratch_mem) {
     const Geo& g = c->geo;
     const size_t hb = half_field_bytes(p, g.Vh);
     const char* ie = static_cast<const char*>(in);
@@ -260,11 +302,12 @@ mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* 
             const bool dag = op == MDWF_OP_SCHUR_DAG || op == MDWF_OP_SCHUR_SYM_DAG || op == MDWF_OP_SCHUR_RP_DAG;
             const bool sym = op == MDWF_OP_SCHUR_SYM || op == MDWF_OP_SCHUR_SYM_DAG;
             const int form = sym ? 1 : (op == MDWF_OP_SCHUR_RP || op == MDWF_OP_SCHUR_RP_DAG) ? 2 : 0;
-            void* tmp = buf(c, "apply_tmp", stride * nrhs, &s);
+            void* tmp = scratch_mem ? scratch_mem : buf(c, "apply_tmp", stride * nrhs, &s);
             if (!tmp) return s;
             void* tmp2 = nullptr;
             if (sym && dag) {
-                tmp2 = buf(c, "apply_tmp2", stride * nrhs, &s);
+                tmp2 = scratch_mem ? static_cast<char*>(scratch_mem) + stride * nrhs
+                                   : buf(c, "apply_tmp2", stride * nrhs, &s);
                 if (!tmp2) return s;
             }
             schur_launch(g, c->gs, p, form, dag, in, out, tmp, tmp2, stride, nrhs, d_coef,
@@ -399,6 +442,7 @@ mdwf_status mdwf_create(const mdwf_geometry* geom, int hip_device, void* hip_str
     if (const char* e = std::getenv("MDWF_RHS_GROUP")) t0.rhs_group = std::atoi(e);
     if (const char* e = std::getenv("MDWF_PLANE_BT")) t0.plane_bt = std::atoi(e);
     for (int p = 0; p < 3; ++p) set_tune(g, Prec(p), t0);
+    scratch_init(hip_device);   // the device address of this device's static scratch
     if (hipMalloc(&c->d_coef1, 2 * sizeof(RhsCoef)) != hipSuccess) {
         (void)hipGetLastError();
         mdwf_destroy(c);
@@ -560,6 +604,30 @@ mdwf_status mdwf_apply_dev(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, const void* 
     const size_t hb = half_field_bytes(Prec(prec), c->geo.Vh);
     const size_t stride = op_full(op) ? 2 * hb : hb;
     return apply_native(c, op, Prec(prec), in, out, stride, 1, c->d_coef1, nullptr, st);
+}
+
+mdwf_status mdwf_apply_dev_noalloc(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, const void* in, void* out,
+                                   void* stream) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!valid_prec(prec) || op < 0 || op >= MDWF_OP_COUNT) return fail(c, MDWF_ERR_ARG, "bad operator or precision");
+    if (!in || !out) return fail(c, MDWF_ERR_ARG, "null field pointer");
+    if (in == out) return fail(c, MDWF_ERR_ARG, "in and out must not overlap");
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
+    const size_t hb = half_field_bytes(Prec(prec), c->geo.Vh);
+    const size_t stride = op_full(op) ? 2 * hb : hb;
+    void* mem = nullptr;
+    if (op_schur(op)) {
+        const size_t need = (op == MDWF_OP_SCHUR_SYM_DAG ? 2 : 1) * stride;
+        if (need > kStaticScratchBytes)
+            return fail(c, MDWF_ERR_ARG, "the operator's intermediate needs " + std::to_string(need) +
+                                             " bytes, more than the " + std::to_string(kStaticScratchBytes) +
+                                             "-byte static scratch");
+        hipError_t e = hipSuccess;
+        mem = scratch_ptr(c->device, &e);
+        if (!mem) return hip_check(c, e == hipSuccess ? hipErrorInvalidSymbol : e, "static scratch address");
+    }
+    return apply_native(c, op, Prec(prec), in, out, stride, 1, c->d_coef1, nullptr, st, mem);
 }
 
 mdwf_status mdwf_apply_batch_dev(mdwf_ctx* c, mdwf_op op, mdwf_prec prec, int nrhs, const void* in, void* out,

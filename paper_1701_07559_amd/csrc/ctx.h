@@ -62,8 +62,11 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t);
 // half_field_bytes each and `stride` then covers both).  For the symmetric
 // Schur ops d_coef holds nrhs action tables followed by nrhs make_coef_sym
 // tables.
+// scratch_mem: device memory for the Schur ops' odd intermediate(s) (two
+// fields of nrhs for the symmetric adjoint); nullptr = the context's own
+// grow-only buffers.
 mdwf_status apply_native(mdwf_ctx* c, mdwf_op op, Prec p, const void* in, void* out, size_t stride, int nrhs,
-                         const RhsCoef* d_coef, const int* d_active, hipStream_t st);
+                         const RhsCoef* d_coef, const int* d_active, hipStream_t st, void* scratch_mem = nullptr);
 
 // Model counts (per application, all right-hand sides counted once).
 void op_model(const Geo& g, mdwf_op op, Prec p, double* flops, double* bytes);

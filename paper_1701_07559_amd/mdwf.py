@@ -22,6 +22,7 @@ MDWF_OK, MDWF_ERR_ARG, MDWF_ERR_STATE, MDWF_ERR_OOM, MDWF_ERR_HIP, MDWF_ERR_NOCO
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_STATE", "ERR_OOM", "ERR_HIP", "ERR_NOCONV", "ERR_NUMERIC"]
 MDWF_F64, MDWF_F32, MDWF_F16 = 0, 1, 2
 MDWF_FULL, MDWF_HALF_EVEN, MDWF_HALF_ODD = 0, 1, 2
+MDWF_STATIC_SCRATCH_BYTES = 256 << 20   # the static scratch of mdwf_apply_dev_noalloc
 (MDWF_OP_D5, MDWF_OP_D5_DAG, MDWF_OP_SCHUR, MDWF_OP_SCHUR_DAG, MDWF_OP_HOP_EO, MDWF_OP_HOP_OE,
  MDWF_OP_K5, MDWF_OP_K5INV, MDWF_OP_HOP_EO_DAG, MDWF_OP_HOP_OE_DAG, MDWF_OP_K5_DAG, MDWF_OP_K5INV_DAG,
  MDWF_OP_B, MDWF_OP_B_DAG, MDWF_OP_SCHUR_SYM, MDWF_OP_SCHUR_SYM_DAG, MDWF_OP_SCHUR_RP, MDWF_OP_SCHUR_RP_DAG,
@@ -118,6 +119,7 @@ def _load():
         "mdwf_unpack_dev": ([vp, ip, ip, vp, vp, vp], ip),
         "mdwf_apply": ([vp, ip, ip, vp, vp], ip),
         "mdwf_apply_dev": ([vp, ip, ip, vp, vp, vp], ip),
+        "mdwf_apply_dev_noalloc": ([vp, ip, ip, vp, vp, vp], ip),
         "mdwf_apply_batch_dev": ([vp, ip, ip, ip, vp, vp, C.c_size_t, C.POINTER(dp), vp], ip),
         "mdwf_solve_footprint": ([C.POINTER(mdwf_geometry), ip, ip, ip, ip, C.POINTER(C.c_size_t)], ip),
         "mdwf_solve": ([vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
@@ -224,6 +226,11 @@ def mdwf_apply(ctx, op, prec, inp, out):
 
 def mdwf_apply_dev(ctx, op, prec, in_ptr, out_ptr, stream=None):
     _check(ctx, lib.mdwf_apply_dev(ctx, int(op), int(prec), int(in_ptr), int(out_ptr), stream))
+
+
+def mdwf_apply_dev_noalloc(ctx, op, prec, in_ptr, out_ptr, stream=None):
+    """mdwf_apply_dev without any device allocation (static scratch)."""
+    _check(ctx, lib.mdwf_apply_dev_noalloc(ctx, int(op), int(prec), int(in_ptr), int(out_ptr), stream))
 
 
 def mdwf_apply_batch_dev(ctx, op, prec, nrhs, in_ptr, out_ptr, stride, mq=None, stream=None):
@@ -490,7 +497,7 @@ def exported_symbols():
     """Names of the C entry points declared in include/mdwf.h."""
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
-            "mdwf_apply_dev", "mdwf_apply_batch_dev", "mdwf_solve_footprint", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
+            "mdwf_apply_dev", "mdwf_apply_dev_noalloc", "mdwf_apply_batch_dev", "mdwf_solve_footprint", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
             "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_set_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
             "mdwf_plaquette_dev", "mdwf_gauss_smear_dev", "mdwf_wall_source_dev", "mdwf_project_4d_dev",
             "mdwf_mres_correlators_dev", "mdwf_pion_correlator_dev", "mdwf_server_create", "mdwf_server_destroy",
