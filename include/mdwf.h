@@ -298,7 +298,10 @@ typedef struct {
     int nt_store;    /* 1: hop outputs written with non-temporal stores               */
     int link_mode;   /* links: 0 loaded by every lane, 1 staged in LDS (L5 >= 8),
                         2 one 16-byte part per lane, gathered by lane exchange
-                        (FP32 / FP16, L5 >= 4 / 2); otherwise 0 is used      */
+                        (FP32 / FP16, L5 >= 4 / 2), 3 FP16 SU(3) products on
+                        the matrix cores (4x4x4 blocks of four slices of one
+                        site: L5 a multiple of 4; kernels without a B
+                        pre-hop); otherwise 0 is used                      */
     int rhs_group;   /* multi-RHS launches: groups of this many RHS sweep the tiles
                         together, RHS fastest (they share each tile's links);
                         groups follow each other; 0 = all RHS in one group    */

@@ -208,7 +208,7 @@ void set_tune(Geo& g, Prec p, const mdwf_launch_tune& t) {
     tr.fNy = FastDiv(uint32_t(g.Y / t.tile[1]));
     g.xcd_remap[p] = t.xcd_remap ? 1 : 0;
     g.nt_store[p] = t.nt_store ? 1 : 0;
-    g.link_mode[p] = (t.link_mode >= 0 && t.link_mode <= 2) ? t.link_mode : 0;
+    g.link_mode[p] = (t.link_mode >= 0 && t.link_mode <= 3) ? t.link_mode : 0;
     g.rhs_group[p] = t.rhs_group > 0 ? t.rhs_group : 0;
     g.plane_bt[p] = (t.plane_bt > 0 && g.T % t.plane_bt == 0) ? t.plane_bt : 0;
 }
@@ -230,7 +230,7 @@ void share_gauge(mdwf_ctx* dst, const mdwf_ctx* src) {
 size_t gauge_bytes(const mdwf_ctx* c) {
     size_t tot = 0;
     for (int p = 0; p < 3; ++p) tot += 8 * link_segment_bytes(Prec(p), c->geo.Vh4);
-    return tot;
+    return tot + 16 * link_rows_bytes(c->geo.Vh4);
 }
 
 // The even-odd operator of Schur form `form` or its adjoint on nrhs fields
@@ -502,6 +502,8 @@ static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_devic
         seg[p] = link_segment_bytes(Prec(p), g.Vh4);
         tot += 8 * seg[p];
     }
+    const size_t rows = link_rows_bytes(g.Vh4);
+    tot += 16 * rows;
     if (!c->gauge_mem) {
         s = hip_check(c, hipMalloc(&c->gauge_mem, tot), "gauge allocation");
         if (s) return s;
@@ -512,6 +514,8 @@ static mdwf_status load_gauge_common(mdwf_ctx* c, const double* U, bool on_devic
         c->gs.seg_bytes[p] = seg[p];
         base += 8 * seg[p];
     }
+    c->gs.mrow = base;
+    c->gs.mrow_bytes = rows;
     const size_t canon_bytes = size_t(2) * g.Vh4 * 4 * 18 * sizeof(double);
     const double* src = U;
     if (!on_device) {
@@ -809,9 +813,10 @@ mdwf_status tune_precision(mdwf_ctx* c, Prec p, int form, int nrhs, bool with_da
         if (s) return s;
         if (tn.us < best.us) best = tn;
     }
-    for (int lm : {1, 2}) {
+    for (int lm : {1, 2, 3}) {
         if (lm == 1 && 64 / g.L5 > 8) continue;
         if (lm == 2 && (p == P64 || g.L5 < (p == P32 ? 4 : 2))) continue;
+        if (lm == 3 && (p != P16 || g.L5 % 4 != 0)) continue;
         mdwf_launch_tune tn = best;
         tn.link_mode = lm;
         tn = timed(tn);

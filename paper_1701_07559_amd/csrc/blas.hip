@@ -62,8 +62,32 @@ __device__ __forceinline__ void block_partial(double v, double* partials, int rh
 // FP64, FP32 and FP16, with the antiperiodic sign folded into the t-links on
 // the last time slice (it multiplies both the forward hop out of t = T-1 and
 // the backward hop into it).
+__device__ __forceinline__ void store_link_rows(char* seg, size_t rb, int Vh4, int i, const cx<double> u[9]) {
+    // form 0: rows of U; form 1: rows of U^+ (conjugated columns of U)
+    nu4* f0 = reinterpret_cast<nu4*>(seg);
+    nu4* f1 = reinterpret_cast<nu4*>(seg + 8 * rb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        nu4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
+        if (r < 3) {
+            const cx<double> x0 = u[3 * r], x1 = u[3 * r + 1], x2 = u[3 * r + 2];   // U[r][k]
+            const cx<double> y0 = u[r], y1 = u[3 + r], y2 = u[6 + r];               // U[k][r]
+            a.x = f2h(float(x0.re)) | (f2h(float(x1.re)) << 16);
+            a.y = f2h(float(x2.re));
+            a.z = f2h(float(x0.im)) | (f2h(float(x1.im)) << 16);
+            a.w = f2h(float(x2.im));
+            b.x = f2h(float(y0.re)) | (f2h(float(y1.re)) << 16);
+            b.y = f2h(float(y2.re));
+            b.z = f2h(float(-y0.im)) | (f2h(float(-y1.im)) << 16);
+            b.w = f2h(float(-y2.im));
+        }
+        f0[size_t(r) * Vh4 + i] = a;
+        f1[size_t(r) * Vh4 + i] = b;
+    }
+}
+
 __global__ void k_gauge_layout(const Geo g, const double* canon, char* s64, size_t b64, char* s32, size_t b32,
-                               char* s16, size_t b16) {
+                               char* s16, size_t b16, char* rows, size_t rb) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 2 * g.Vh4) return;
     const int p = idx / g.Vh4;
@@ -90,13 +114,14 @@ __global__ void k_gauge_layout(const Geo g, const double* canon, char* s64, size
         Link<P64>::store(s64 + sgi * b64, g.Vh4, i, u);
         Link<P32>::store(s32 + sgi * b32, g.Vh4, i, u);
         Link<P16>::store(s16 + sgi * b16, g.Vh4, i, u);
+        if (rows) store_link_rows(rows + sgi * rb, rb, g.Vh4, i, u);
     }
 }
 
 void launch_gauge_layout(const Geo& g, const double* canon, GaugeSet& gs, hipStream_t st) {
     const int n = 2 * g.Vh4;
     hipLaunchKernelGGL(k_gauge_layout, dim3((n + 255) / 256), dim3(256), 0, st, g, canon, gs.seg[0], gs.seg_bytes[0],
-                       gs.seg[1], gs.seg_bytes[1], gs.seg[2], gs.seg_bytes[2]);
+                       gs.seg[1], gs.seg_bytes[1], gs.seg[2], gs.seg_bytes[2], gs.mrow, gs.mrow_bytes);
 }
 
 // ----------------------------------------------------------- pack / unpack

@@ -58,6 +58,9 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
         t = int(q - q1 * nt) * tr.b[3] + int(r3);
         i = xh + g.Xh * (y + g.Y * (z + g.Z * t));
     }
+    if constexpr (LM == 3) {   // every lane takes part in the matrix products: idle ones read site 0
+        if (!valid) xh = y = z = t = i = 0;
+    }
 
     const RhsCoef& cf = a.coef[rhs];
     const R mq = R(cf.mq), b5 = R(cf.b5), c5 = R(cf.c5);
@@ -124,7 +127,49 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
         __syncthreads();
     }
 
-    if (valid) {
+    if constexpr (LM == 3) {
+        // FP16 on the matrix cores: lane s of the site group holds row s & 3
+        // of each link; the neighbour norms are gathered first so that every
+        // direction enters one accumulator at a common scale
+        const char* rseg[8] = {a.rows_out, a.rows_in, a.rows_out + a.rseg, a.rows_in + a.rseg,
+                               a.rows_out + 2 * a.rseg, a.rows_in + 2 * a.rseg, a.rows_out + 3 * a.rseg,
+                               a.rows_in + 3 * a.rseg};
+        const size_t roff = size_t(s & 3) * lblk;   // this lane's row block
+        const char* nsrc = src + align256(3 * sblk);
+        float nrm[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) nrm[d] = ldu<float>(nsrc, jn[d] * 4u);
+        float S = 1.17549435e-38f;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) S = fmaxf(S, nrm[d]);
+        const float inv = __builtin_amdgcn_rcpf(S);
+        f4 acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+        nu4 sp0[3], sp1[3];
+        nu4 lr0, lr1;
+        auto load = [&](int d, nu4 sp[3], nu4& lr) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sp[k] = ldu<nu4>(src + k * sblk, jn[d] * 16u);
+            lr = ldu<nu4>(rseg[d] + roff, lidx[d] * 16u);
+        };
+        load(0, sp0, lr0);
+#define MDWF_MMA(d, spc, lrc, spn, lrn)                                                  \
+    if ((d) < 7) load((d) + 1, spn, lrn);                                                \
+    {                                                                                    \
+        RowA A;                                                                          \
+        A.set(lrc);                                                                      \
+        mma_term<(d) / 2, (((d) % 2 == 0) != D) ? 1 : -1>(acc, A, spc, nrm[d] * inv);   \
+    }
+        MDWF_MMA(0, sp0, lr0, sp1, lr1) MDWF_MMA(1, sp1, lr1, sp0, lr0) MDWF_MMA(2, sp0, lr0, sp1, lr1)
+        MDWF_MMA(3, sp1, lr1, sp0, lr0) MDWF_MMA(4, sp0, lr0, sp1, lr1) MDWF_MMA(5, sp1, lr1, sp0, lr0)
+        MDWF_MMA(6, sp0, lr0, sp1, lr1) MDWF_MMA(7, sp1, lr1, sp0, lr0)
+#undef MDWF_MMA
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) res[sp * 3 + c] = {S * acc[2 * sp][c], S * acc[2 * sp + 1][c]};
+    } else if (valid) {
         if constexpr (P == P64) {
             // FP64: one direction in flight (two would exceed the register file)
             Raw<P> r;
@@ -287,6 +332,8 @@ static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
     int lm = g.link_mode[P];
     if (lm == 1 && 64 / g.L5 > kStageSites) lm = 0;
     if (lm == 2 && (P == P64 || g.L5 < link_parts<P>())) lm = 0;
+    // matrix cores: FP16, blocks of four slices of one site, no B pre-hop
+    if (lm == 3 && (P != P16 || g.L5 % 4 != 0 || HopTraits<K>::preB || !gs.mrow)) lm = 0;
     HopDev a;
     a.out = L.out;
     a.in = L.in;
@@ -295,6 +342,9 @@ static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
     a.lseg = seg;
     a.links_out = gs.seg[P] + size_t(L.out_parity) * 4 * seg;
     a.links_in = gs.seg[P] + size_t(1 - L.out_parity) * 4 * seg;
+    a.rseg = gs.mrow_bytes;
+    a.rows_out = gs.mrow ? gs.mrow + size_t(L.out_parity) * 4 * gs.mrow_bytes : nullptr;
+    a.rows_in = gs.mrow ? gs.mrow + size_t(8 + (1 - L.out_parity) * 4) * gs.mrow_bytes : nullptr;
     a.stride = L.stride;
     a.nrhs = L.nrhs;
     a.nblk = hop_blocks_per_rhs(g);
@@ -308,6 +358,9 @@ static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
         hipLaunchKernelGGL((k_hop<P, K, 1>), grid, dim3(kBlock), 0, st, g, a);
     } else if (lm == 2) {
         if constexpr (P != P64) hipLaunchKernelGGL((k_hop<P, K, 2>), grid, dim3(kBlock), 0, st, g, a);
+    } else if (lm == 3) {
+        if constexpr (P == P16 && !HopTraits<K>::preB)
+            hipLaunchKernelGGL((k_hop<P, K, 3>), grid, dim3(kBlock), 0, st, g, a);
     } else {
         hipLaunchKernelGGL((k_hop<P, K, 0>), grid, dim3(kBlock), 0, st, g, a);
     }

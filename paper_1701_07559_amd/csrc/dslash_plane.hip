@@ -14,7 +14,8 @@
 //
 // Threads: the L5 slices of one output site in consecutive lanes, as in the
 // lane-per-site kernel; 32 output sites per plane.  LDS per workgroup: 80
-// spinor slots of L5 sites plus 256 links (see PlaneLds).
+// spinor slots of L5 sites plus 256 links (see PlaneLds), copied by direct
+// global-to-LDS loads that need no registers.
 #include "hop_device.h"
 
 namespace mdwf {
@@ -24,22 +25,27 @@ constexpr int kPlaneSlots = 80;      // input sites staged per plane (32 inside,
 constexpr int kPlaneLinks = 256;     // 8 link sets x 32 sites
 constexpr int kPlaneMaxThreads = 512;
 
-// LDS layout of one staged plane for precision P: spinor slots of L5 5D
-// sites, each [blocks][L5] 16-byte units (FP16: then [L5] float norms), and
-// the links as [parts][256] 16-byte units (the short tail part in 8 / 4 bytes).
+// LDS of one staged plane, filled by direct global-to-LDS loads (each wave
+// writes 64 consecutive units): spinor slots [80][blocks][L5] of 16-byte
+// units; FP16 norms [80][L5]; links [parts][256] of 16-byte units, then the
+// short tail (FP32: re and im arrays of 256 floats, FP16: 256 words); the
+// index table [2][80].
 template <Prec P> struct PlaneLds;
 template <> struct PlaneLds<P32> {
     static constexpr int NB = 6;   // 16-byte blocks per 5D site
-    static constexpr int LP = 4;   // 16-byte link parts, then a float2 tail
-    static __host__ __device__ int slot_bytes(int L5) { return NB * 16 * L5; }
+    static constexpr int LP = 4;   // 16-byte link parts
+    static __host__ __device__ int spinor_bytes(int L5) { return kPlaneSlots * NB * 16 * L5; }
     static __host__ __device__ int link_bytes() { return kPlaneLinks * (LP * 16 + 8); }
 };
 template <> struct PlaneLds<P16> {
     static constexpr int NB = 3;
-    static constexpr int LP = 2;   // then a 4-byte tail
-    static __host__ __device__ int slot_bytes(int L5) { return (NB * 16 * L5 + 4 * L5 + 15) & ~15; }
+    static constexpr int LP = 2;
+    static __host__ __device__ int spinor_bytes(int L5) { return kPlaneSlots * (NB * 16 + 4) * L5; }
     static __host__ __device__ int link_bytes() { return kPlaneLinks * (LP * 16 + 4); }
 };
+template <Prec P> inline size_t plane_lds_bytes(int L5) {
+    return size_t(PlaneLds<P>::spinor_bytes(L5)) + PlaneLds<P>::link_bytes() + 2 * kPlaneSlots * sizeof(int);
+}
 
 struct PlaneDev {
     int bt;            // time planes per workgroup
@@ -50,9 +56,9 @@ struct PlaneDev {
 };
 
 // Position (lx, ly, lz) inside the block of staged slot `slot` of a plane
-// whose input-parity sites satisfy (lx + ly + lz + t) = ip (mod 2): slots
-// 0..31 inside the block (x fastest, parity-compressed), then eight per face
-// in the order x-, x+, y-, y+, z-, z+.
+// whose input-parity sites satisfy (lx + ly + lz + t) = ip (mod 2), cls =
+// (ip + t) mod 2: slots 0..31 inside the block (x fastest, parity-
+// compressed), then eight per face in the order x-, x+, y-, y+, z-, z+.
 __device__ __forceinline__ void slot_position(int slot, int cls, int& lx, int& ly, int& lz) {
     if (slot < kPlaneSites) {
         ly = (slot >> 1) & 3;
@@ -69,14 +75,20 @@ __device__ __forceinline__ void slot_position(int slot, int cls, int& lx, int& l
     else { lz = v; lx = a; ly = b; }
 }
 
-// Slots of the six spatial neighbours of the output site at (lx, ly, lz):
-// inside the block, or on the face the hop leaves through.
+// Slot of a neighbour inside the block (the face slots are computed where
+// the hop leaves the block).
 __device__ __forceinline__ int inner_slot(int lx, int ly, int lz) { return (lx >> 1) + 2 * (ly + 4 * lz); }
+
+// Direct global-to-LDS copy: lane l of the wave writes `bytes` bytes at
+// lds_base + l * bytes (lds_base wave-uniform); inactive lanes write nothing.
+template <int BYTES> __device__ __forceinline__ void copy_to_lds(const void* gsrc, void* lds_base) {
+    if constexpr (BYTES == 16) __builtin_amdgcn_global_load_lds(gsrc, lds_base, 16, 0, 0);
+    else __builtin_amdgcn_global_load_lds(gsrc, lds_base, 4, 0, 0);
+}
 
 template <Prec P> struct PlaneIO;
 
 template <> struct PlaneIO<P32> {
-    using R = float;
     static __device__ __forceinline__ void spinor(const unsigned char* slot, int L5, int s, cx<float> v[12]) {
         const nf4* p = reinterpret_cast<const nf4*>(slot) + s;
 #pragma unroll
@@ -94,23 +106,26 @@ template <> struct PlaneIO<P32> {
             U[2 * k] = {w.x, w.y};
             U[2 * k + 1] = {w.z, w.w};
         }
-        const nf2 t = reinterpret_cast<const nf2*>(lds + 4 * 16 * kPlaneLinks)[id];
-        U[8] = {t.x, t.y};
+        const float* t = reinterpret_cast<const float*>(lds + 4 * 16 * kPlaneLinks);
+        U[8] = {t[id], t[kPlaneLinks + id]};
     }
-    // copy one link from its global segment into LDS
-    static __device__ __forceinline__ void stage_link(const char* seg, size_t lblk, uint32_t i, unsigned char* lds,
-                                                      int id) {
-        nf4* p = reinterpret_cast<nf4*>(lds) + id;
+    // the links of 64 consecutive ids (this lane's link in segment seg at
+    // index i; active lanes only)
+    static __device__ __forceinline__ void stage_links(const char* seg, size_t lblk, uint32_t i, unsigned char* lds,
+                                                       int chunk) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) p[k * kPlaneLinks] = ldu<nf4>(seg + k * lblk, i * 16u);
-        reinterpret_cast<nf2*>(lds + 4 * 16 * kPlaneLinks)[id] = ldu<nf2>(seg + 4 * lblk, i * 8u);
+        for (int k = 0; k < 4; ++k)
+            copy_to_lds<16>(seg + k * lblk + size_t(i) * 16, lds + k * 16 * kPlaneLinks + chunk * 64 * 16);
+        unsigned char* t = lds + 4 * 16 * kPlaneLinks;
+        const char* tail = seg + 4 * lblk + size_t(i) * 8;
+        copy_to_lds<4>(tail, t + chunk * 64 * 4);
+        copy_to_lds<4>(tail + 4, t + 4 * kPlaneLinks + chunk * 64 * 4);
     }
 };
 
 template <> struct PlaneIO<P16> {
-    using R = float;
-    // the stored binary16 pairs and the site's norm
-    static __device__ __forceinline__ float spinor_h(const unsigned char* slot, int L5, int s, h2 v[12]) {
+    // the stored binary16 pairs (the site's norm is read separately)
+    static __device__ __forceinline__ void spinor_h(const unsigned char* slot, int L5, int s, h2 v[12]) {
         const nu4* p = reinterpret_cast<const nu4*>(slot) + s;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -120,7 +135,6 @@ template <> struct PlaneIO<P16> {
             v[4 * k + 2] = as_h2(w.z);
             v[4 * k + 3] = as_h2(w.w);
         }
-        return reinterpret_cast<const float*>(slot + 3 * 16 * L5)[s];
     }
     static __device__ __forceinline__ void link_h(const unsigned char* lds, int id, h2 U[9]) {
         const nu4* p = reinterpret_cast<const nu4*>(lds) + id;
@@ -134,22 +148,23 @@ template <> struct PlaneIO<P16> {
         }
         U[8] = as_h2(reinterpret_cast<const uint32_t*>(lds + 2 * 16 * kPlaneLinks)[id]);
     }
-    static __device__ __forceinline__ void stage_link(const char* seg, size_t lblk, uint32_t i, unsigned char* lds,
-                                                      int id) {
-        nu4* p = reinterpret_cast<nu4*>(lds) + id;
+    static __device__ __forceinline__ void stage_links(const char* seg, size_t lblk, uint32_t i, unsigned char* lds,
+                                                       int chunk) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) p[k * kPlaneLinks] = ldu<nu4>(seg + k * lblk, i * 16u);
-        reinterpret_cast<uint32_t*>(lds + 2 * 16 * kPlaneLinks)[id] = ldu<uint32_t>(seg + 2 * lblk, i * 4u);
+        for (int k = 0; k < 2; ++k)
+            copy_to_lds<16>(seg + k * lblk + size_t(i) * 16, lds + k * 16 * kPlaneLinks + chunk * 64 * 16);
+        copy_to_lds<4>(seg + 2 * lblk + size_t(i) * 4, lds + 2 * 16 * kPlaneLinks + chunk * 64 * 4);
     }
 };
 
-// One hop term of direction (MU, DIR) from a staged spinor slot and link.
+// One hop term of direction (MU, DIR) from a staged spinor slot and link;
+// nrm: the FP16 site norm (unused otherwise).
 template <Prec P, bool DAG, int MU, int DIR>
-__device__ __forceinline__ void plane_term(cx<typename Real<P>::T> acc[12], const unsigned char* slot, int L5, int s,
-                                           const unsigned char* lk, int lid) {
+__device__ __forceinline__ void plane_term(cx<typename Real<P>::T> acc[12], const unsigned char* slot, float nrm,
+                                           int L5, int s, const unsigned char* lk, int lid) {
     if constexpr (P == P16) {
         h2 psi[12], U[9];
-        const float scale = PlaneIO<P16>::spinor_h(slot, L5, s, psi);
+        PlaneIO<P16>::spinor_h(slot, L5, s, psi);
         PlaneIO<P16>::link_h(lk, lid, U);
         constexpr int sg = ((DIR > 0) != DAG) ? 1 : -1;
         h2 z1[6], z2[6];
@@ -157,7 +172,7 @@ __device__ __forceinline__ void plane_term(cx<typename Real<P>::T> acc[12], cons
         cx<float> w[6];
         su3_mul_h<(DIR > 0)>(U, z1, z2, w);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) w[c] = scale * w[c];
+        for (int c = 0; c < 6; ++c) w[c] = nrm * w[c];
         reconstruct_add<MU>(float(sg), w, acc);
     } else {
         using R = typename Real<P>::T;
@@ -183,9 +198,12 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
     constexpr bool DAG = HopTraits<K>::dag;
     extern __shared__ __align__(16) unsigned char plane_lds[];
     const int L5 = g.L5;
-    const int slot_bytes = PlaneLds<P>::slot_bytes(L5);
+    const int units = int(pd.fUnits.d);          // 16-byte spinor units per slot
+    const int slot_bytes = units * 16;
     unsigned char* sp = plane_lds;
-    unsigned char* lk = plane_lds + size_t(kPlaneSlots) * slot_bytes;
+    const float* snorm = reinterpret_cast<const float*>(sp + size_t(kPlaneSlots) * slot_bytes);   // FP16
+    unsigned char* lk = plane_lds + PlaneLds<P>::spinor_bytes(L5);
+    int* tab = reinterpret_cast<int*>(lk + PlaneLds<P>::link_bytes());
 
     // workgroup -> right-hand side (fastest, they share links), block, t-run
     const int lb = g.xcd_remap[P] ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
@@ -202,6 +220,7 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    const int nwaves = pd.nthreads >> 6;
     const int spw = 64 / L5;
     const int sw = lane / L5;
     const int s = lane - sw * L5;
@@ -215,7 +234,7 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
     char* dst = static_cast<char*>(at_rhs(a.out, a.stride, rhs));
     const size_t sblk = size_t(g.Vh) * 16;
     const size_t lblk = size_t(g.Vh4) * 16;
-    const int units = int(pd.fUnits.d);   // 16-byte spinor units per slot
+    const uint32_t plane_sites = uint32_t(g.Xh * g.Y * g.Z);
 
     auto gidx = [&](int lx, int ly, int lz, int t) -> uint32_t {
         int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
@@ -227,7 +246,6 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
 
     // spatial part of the parity-compressed index of every slot, for both
     // classes of input sites (planes alternate between them)
-    int* tab = reinterpret_cast<int*>(lk + PlaneLds<P>::link_bytes());
     for (int e = tid; e < 2 * kPlaneSlots; e += pd.nthreads) {
         int lx, ly, lz;
         slot_position(e % kPlaneSlots, e / kPlaneSlots, lx, ly, lz);
@@ -243,57 +261,70 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
         const int cin = (ip + t) & 1;        // class of the input sites of plane t
         const bool edge = tp < t0 || tp >= t0 + pd.bt;   // only the t hops use this plane
         const int nslots = edge ? kPlaneSites : kPlaneSlots;
-        __syncthreads();   // every thread is done with the previous plane
-        // ---- stage the plane's input spinors: unit u = (slot, block, slice)
+        __syncthreads();   // every thread is done with the previous plane (and the table is written)
+        // ---- stage the plane's input spinors: unit u = (slot, block, slice),
+        // 64 consecutive units per wave and copy
         const int* ctab = tab + cin * kPlaneSlots;
-        const uint32_t tofs = uint32_t(g.Xh * g.Y * g.Z) * uint32_t(t);
-        for (int u = tid; u < nslots * units; u += pd.nthreads) {
-            const int slot = int(pd.fUnits.div(uint32_t(u)));
-            const int r = u - slot * units;
-            const int blk = int(pd.fL5.div(uint32_t(r)));
-            const uint32_t j = (uint32_t(ctab[slot]) + tofs) * uint32_t(L5) + uint32_t(r - blk * L5);
-            *reinterpret_cast<nu4*>(sp + size_t(slot) * slot_bytes + size_t(r) * 16) =
-                ldu<nu4>(src + blk * sblk, j * 16u);
-        }
-        if constexpr (P == P16) {
-            const char* nsrc = src + align256(3 * sblk);
-            for (int u = tid; u < nslots * L5; u += pd.nthreads) {
-                const int slot = int(pd.fL5.div(uint32_t(u)));
-                const int ss = u - slot * L5;
-                const uint32_t j = (uint32_t(ctab[slot]) + tofs) * uint32_t(L5) + uint32_t(ss);
-                reinterpret_cast<float*>(sp + size_t(slot) * slot_bytes + 48 * L5)[ss] = ldu<float>(nsrc, j * 4u);
+        const uint32_t tofs = plane_sites * uint32_t(t);
+        const int nunits = nslots * units;
+        for (int c = wave; c * 64 < nunits; c += nwaves) {
+            const int u = c * 64 + lane;
+            if (u < nunits) {
+                const int slot = int(pd.fUnits.div(uint32_t(u)));
+                const int r = u - slot * units;
+                const int blk = int(pd.fL5.div(uint32_t(r)));
+                const uint32_t j = (uint32_t(ctab[slot]) + tofs) * uint32_t(L5) + uint32_t(r - blk * L5);
+                copy_to_lds<16>(src + blk * sblk + size_t(j) * 16, sp + size_t(c) * 64 * 16);
             }
         }
-        // ---- stage the links of the plane's terms
-        for (int id = tid; id < kPlaneLinks; id += pd.nthreads) {
-            const int set = id >> 5, q = id & 31;
-            if (edge && set < 6) continue;
-            const int qy = (q >> 1) & 3, qz = q >> 3;
+        if constexpr (P == P16) {   // norms [slot][slice]
+            const char* nsrc = src + align256(3 * sblk);
+            unsigned char* nb = sp + size_t(kPlaneSlots) * slot_bytes;
+            const int nn = nslots * L5;
+            for (int c = wave; c * 64 < nn; c += nwaves) {
+                const int u = c * 64 + lane;
+                if (u < nn) {
+                    const int slot = int(pd.fL5.div(uint32_t(u)));
+                    const uint32_t j = (uint32_t(ctab[slot]) + tofs) * uint32_t(L5) + uint32_t(u - slot * L5);
+                    copy_to_lds<4>(nsrc + size_t(j) * 4, nb + size_t(c) * 64 * 4);
+                }
+            }
+        }
+        // ---- stage the links of the plane's terms, 64 ids per wave and copy
+        for (int c = edge ? 3 : wave; c < 4; c += nwaves) {
+            if (edge && wave != 0) break;   // edge planes: one wave copies sets 6 and 7
+            const int id = c * 64 + lane;
+            const int set = id >> 5, w = id & 31;
+            const int wy = (w >> 1) & 3, wz = w >> 3;
             const int mu = set >> 1;
             const bool fwd = (set & 1) == 0;
-            int lx, ly = qy, lz = qz, tl = t;
+            int lx, ly = wy, lz = wz, tl = t;
             if (set < 6) {
-                lx = 2 * (q & 1) + ((p + t + qy + qz) & 1);   // output site q of plane t
+                lx = 2 * (w & 1) + ((p + t + wy + wz) & 1);   // output site w of plane t
                 if (!fwd) {
                     if (mu == 0) lx -= 1;
                     else if (mu == 1) ly -= 1;
                     else lz -= 1;
                 }
             } else {
-                lx = 2 * (q & 1) + ((cin + qy + qz) & 1);      // input slot q of plane t
+                lx = 2 * (w & 1) + ((cin + wy + wz) & 1);      // input slot w of plane t
                 if (fwd) tl = t == 0 ? g.T - 1 : t - 1;        // output site of plane t-1
             }
             const char* seg = (fwd ? a.links_out : a.links_in) + size_t(mu) * a.lseg;
-            IO::stage_link(seg, lblk, gidx(lx, ly, lz, tl), lk, id);
+            IO::stage_links(seg, lblk, gidx(lx, ly, lz, tl), lk, c);
         }
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed
         __syncthreads();
         if (!valid) continue;
+        auto norm = [&](int slot) -> float {
+            if constexpr (P == P16) return snorm[slot * L5 + s];
+            else return 1.f;
+        };
         // ---- plane t-1 gets its t+ term and is finished
         if (tp - 1 >= t0) {
-            plane_term<P, DAG, 3, +1>(acc_prev, sp + size_t(kk) * slot_bytes, L5, s, lk, 6 * 32 + kk);
+            plane_term<P, DAG, 3, +1>(acc_prev, sp + size_t(kk) * slot_bytes, norm(kk), L5, s, lk, 6 * 32 + kk);
             const int lx = 2 * (kk & 1) + ((p + tp - 1 + ky + kz) & 1);
-            const int tw = tp - 1 >= g.T ? tp - 1 - g.T : tp - 1;
-            const uint32_t j = gidx(lx, ky, kz, tw) * uint32_t(L5) + uint32_t(s);
+            const uint32_t j = gidx(lx, ky, kz, tp - 1) * uint32_t(L5) + uint32_t(s);
             if (g.nt_store[P]) Field<P>::template store<true>(dst, g.Vh, int(j), acc_prev);
             else Field<P>::store(dst, g.Vh, int(j), acc_prev);
         }
@@ -306,16 +337,16 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
             const int sym = ky > 0 ? inner_slot(lx, ky - 1, kz) : 48 + 2 * kz + (lx >> 1);
             const int szp = kz < 3 ? inner_slot(lx, ky, kz + 1) : 72 + 2 * ky + (lx >> 1);
             const int szm = kz > 0 ? inner_slot(lx, ky, kz - 1) : 64 + 2 * ky + (lx >> 1);
-            plane_term<P, DAG, 0, +1>(acc_cur, sp + size_t(sxp) * slot_bytes, L5, s, lk, 0 * 32 + kk);
-            plane_term<P, DAG, 0, -1>(acc_cur, sp + size_t(sxm) * slot_bytes, L5, s, lk, 1 * 32 + kk);
-            plane_term<P, DAG, 1, +1>(acc_cur, sp + size_t(syp) * slot_bytes, L5, s, lk, 2 * 32 + kk);
-            plane_term<P, DAG, 1, -1>(acc_cur, sp + size_t(sym) * slot_bytes, L5, s, lk, 3 * 32 + kk);
-            plane_term<P, DAG, 2, +1>(acc_cur, sp + size_t(szp) * slot_bytes, L5, s, lk, 4 * 32 + kk);
-            plane_term<P, DAG, 2, -1>(acc_cur, sp + size_t(szm) * slot_bytes, L5, s, lk, 5 * 32 + kk);
+            plane_term<P, DAG, 0, +1>(acc_cur, sp + size_t(sxp) * slot_bytes, norm(sxp), L5, s, lk, 0 * 32 + kk);
+            plane_term<P, DAG, 0, -1>(acc_cur, sp + size_t(sxm) * slot_bytes, norm(sxm), L5, s, lk, 1 * 32 + kk);
+            plane_term<P, DAG, 1, +1>(acc_cur, sp + size_t(syp) * slot_bytes, norm(syp), L5, s, lk, 2 * 32 + kk);
+            plane_term<P, DAG, 1, -1>(acc_cur, sp + size_t(sym) * slot_bytes, norm(sym), L5, s, lk, 3 * 32 + kk);
+            plane_term<P, DAG, 2, +1>(acc_cur, sp + size_t(szp) * slot_bytes, norm(szp), L5, s, lk, 4 * 32 + kk);
+            plane_term<P, DAG, 2, -1>(acc_cur, sp + size_t(szm) * slot_bytes, norm(szm), L5, s, lk, 5 * 32 + kk);
         }
         // ---- plane t+1 starts with its t- term
         if (tp + 1 < t0 + pd.bt)
-            plane_term<P, DAG, 3, -1>(acc_next, sp + size_t(kk) * slot_bytes, L5, s, lk, 7 * 32 + kk);
+            plane_term<P, DAG, 3, -1>(acc_next, sp + size_t(kk) * slot_bytes, norm(kk), L5, s, lk, 7 * 32 + kk);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             acc_prev[c] = acc_cur[c];
@@ -325,9 +356,37 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
     }
 }
 
+// Dynamic LDS the plane kernels may take: a CU's whole LDS.
+size_t plane_lds_limit() {
+    static size_t limit = [] {
+        int dev = 0, v = 0;
+        size_t lim = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            lim = size_t(v);
+        (void)hipGetLastError();
+        return lim;
+    }();
+    return limit;
+}
+
+template <Prec P, int K>
+static void launch_plane_k(const dim3& grid, int nthreads, size_t lds, hipStream_t st, const Geo& g,
+                           const HopDev& a, const PlaneDev& pd) {
+    static const bool attr = [] {   // allow this instantiation the whole LDS (once per process)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P, K>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(plane_lds_limit()));
+        (void)hipGetLastError();
+        return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL((k_hop_plane<P, K>), grid, dim3(nthreads), lds, st, g, a, pd);
+}
+
 // The plane-staged kernel applies when the launch shape asks for it, the
 // operator is the bare hop, the spatial extents are multiples of 4, T of bt,
-// L5 <= 16 and the plane fits in LDS; it returns false otherwise.
+// a workgroup has 128 to 512 threads (L5 from 3 to 16) and the plane fits in
+// LDS; it returns false otherwise.
 template <Prec P>
 static bool launch_plane_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_t st) {
     const int bt = g.plane_bt[P];
@@ -337,9 +396,8 @@ static bool launch_plane_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipSt
         if (g.X % 4 || g.Y % 4 || g.Z % 4 || g.T % bt || g.L5 > 16) return false;
         const int spw = 64 / g.L5;
         const int nthreads = 64 * ((kPlaneSites + spw - 1) / spw);
-        const size_t lds = size_t(kPlaneSlots) * PlaneLds<P>::slot_bytes(g.L5) + PlaneLds<P>::link_bytes() +
-                           2 * kPlaneSlots * sizeof(int);
-        if (nthreads > kPlaneMaxThreads || lds > plane_lds_limit()) return false;
+        const size_t lds = plane_lds_bytes<P>(g.L5);
+        if (nthreads < 128 || nthreads > kPlaneMaxThreads || lds > plane_lds_limit()) return false;
         HopDev a{};
         a.out = L.out;
         a.in = L.in;
@@ -363,10 +421,8 @@ static bool launch_plane_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipSt
         a.nblk = pd.nbx * pd.nby * pd.nbz * pd.nbt;
         L.nblocks_per_rhs = a.nblk;
         const dim3 grid(a.nblk * L.nrhs);
-        if (L.kind == HOP_BARE)
-            hipLaunchKernelGGL((k_hop_plane<P, HOP_BARE>), grid, dim3(nthreads), lds, st, g, a, pd);
-        else
-            hipLaunchKernelGGL((k_hop_plane<P, HOP_BARE_DAG>), grid, dim3(nthreads), lds, st, g, a, pd);
+        if (L.kind == HOP_BARE) launch_plane_k<P, HOP_BARE>(grid, nthreads, lds, st, g, a, pd);
+        else launch_plane_k<P, HOP_BARE_DAG>(grid, nthreads, lds, st, g, a, pd);
         return true;
     }
 }
@@ -377,31 +433,6 @@ bool launch_hop_plane(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStream_
         case P16: return launch_plane_p<P16>(g, gs, L, st);
         default: return false;
     }
-}
-
-// Dynamic LDS the plane kernels may take: every instantiation is allowed the
-// whole of a CU's LDS (set once per process).
-size_t plane_lds_limit() {
-    static size_t limit = [] {
-        int dev = 0, v = 0;
-        size_t lim = 64 * 1024;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-            lim = size_t(v);
-        (void)hipGetLastError();
-        const int li = int(lim);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P32, HOP_BARE>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P32, HOP_BARE_DAG>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P16, HOP_BARE>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane<P16, HOP_BARE_DAG>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, li);
-        (void)hipGetLastError();
-        return lim;
-    }();
-    return limit;
 }
 
 }  // namespace mdwf

@@ -194,6 +194,9 @@ struct HopDev {
     const void* centre;
     const char* links_out;   // segments (mu = 0..3) of the output parity
     const char* links_in;    // segments of the input parity
+    const char* rows_out;    // FP16 link rows of U at the output parity (matrix-core hop)
+    const char* rows_in;     // FP16 link rows of U^+ at the input parity
+    size_t rseg;             // bytes of one link-row segment
     size_t lseg;
     size_t stride;
     int nrhs;
@@ -515,5 +518,109 @@ __device__ __forceinline__ void dir_term(cx<typename Real<P>::T> acc[12], const 
 constexpr int kStageSites = 8;
 // 16-byte parts gathered by lane exchange (the short tail is loaded by every lane)
 template <Prec P> constexpr int link_parts() { return P == P64 ? 9 : P == P32 ? 4 : 2; }
+
+}  // namespace mdwf
+
+namespace mdwf {
+
+// ------------------------------------------ FP16 hop on the matrix cores
+// v_mfma_f32_4x4x4_16b_f16 multiplies 16 independent 4x4 blocks: block b is
+// lanes 4b..4b+3; lane 4b+i holds row i of the block's A (4 halves, index
+// k), lane 4b+j holds column j of its B (4 halves) and receives column j of
+// the FP32 result D = A B + C (4 floats, index i).  With L5 a multiple of 4,
+// the four lanes of a block are four slices of one 4D site, so they share
+// its link: A = one row of the link per lane (stored that way, see
+// LinkRowsF16), B = each lane's own colour vector, and D accumulates each
+// lane's own result.  Real and imaginary parts are separate products:
+//   (U h)_re = U_re h_re - U_im h_im,  (U h)_im = U_re h_im + U_im h_re.
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nu2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f4 mma(h4 a, h4 b, f4 c) { return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ h4 h4_of(uint32_t lo, uint32_t hi) { return __builtin_bit_cast(h4, nu2{lo, hi}); }
+
+// The link row a lane uses as its A operand: Re and Im of row (lane & 3) of
+// U (forward hop) or of U^+ (backward hop), and their negatives.
+struct RowA {
+    h4 re, im, nre, nim;
+    __device__ __forceinline__ void set(nu4 w) {
+        re = h4_of(w.x, w.y);
+        im = h4_of(w.z, w.w);
+        nre = h4_of(w.x ^ 0x80008000u, w.y ^ 0x80008000u);
+        nim = h4_of(w.z ^ 0x80008000u, w.w ^ 0x80008000u);
+    }
+};
+
+// acc (re, im) += c w with w = A h and c = +1, -1, +i or -i (C = 0..3).
+template <int C>
+__device__ __forceinline__ void mma_cw(f4& ar, f4& ai, const RowA& A, h4 hr, h4 hi) {
+    if constexpr (C == 0) {        // +w
+        ar = mma(A.re, hr, ar); ar = mma(A.nim, hi, ar);
+        ai = mma(A.re, hi, ai); ai = mma(A.im, hr, ai);
+    } else if constexpr (C == 1) { // -w
+        ar = mma(A.nre, hr, ar); ar = mma(A.im, hi, ar);
+        ai = mma(A.nre, hi, ai); ai = mma(A.nim, hr, ai);
+    } else if constexpr (C == 2) { // +i w = (-w_im, w_re)
+        ar = mma(A.nre, hi, ar); ar = mma(A.nim, hr, ar);
+        ai = mma(A.re, hr, ai); ai = mma(A.nim, hi, ai);
+    } else {                       // -i w = (w_im, -w_re)
+        ar = mma(A.re, hi, ar); ar = mma(A.im, hr, ar);
+        ai = mma(A.nre, hr, ai); ai = mma(A.im, hi, ai);
+    }
+}
+// code of the factor -s (s = +1 / -1) and -s i, +s i
+template <int S> constexpr int neg_code() { return S > 0 ? 1 : 0; }
+template <int S> constexpr int negi_code() { return S > 0 ? 3 : 2; }
+template <int S> constexpr int posi_code() { return S > 0 ? 2 : 3; }
+
+// One direction's term on the matrix cores: project the stored binary16
+// spinor (u +- X d per spin pair, the chiral basis of project<MU>), scale it
+// by the neighbour's norm relative to the site's largest (f <= 1), split the
+// two colour vectors into real and imaginary halves and accumulate
+// U h into the upper spins and the reconstructed lower spins, as
+// reconstruct_add<MU> does.  acc: re / im of spins 0..3, colour in the f4.
+template <int MU, int SG>
+__device__ __forceinline__ void mma_term(f4 acc[8], const RowA& A, const nu4 s[3], float f) {
+    h2 v[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[4 * k] = as_h2(s[k].x);
+        v[4 * k + 1] = as_h2(s[k].y);
+        v[4 * k + 2] = as_h2(s[k].z);
+        v[4 * k + 3] = as_h2(s[k].w);
+    }
+    const h2 fs = splat_h2(f);
+    h2 h[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const h2 u0 = v[a], u1 = v[3 + a], d0 = v[6 + a], d1 = v[9 + a];
+        const h2 id0 = h2{-d0.y, d0.x}, id1 = h2{-d1.y, d1.x};   // i d
+        if (MU == 0) { h[a] = SG > 0 ? u0 + id1 : u0 - id1; h[3 + a] = SG > 0 ? u1 + id0 : u1 - id0; }
+        else if (MU == 1) { h[a] = SG > 0 ? u0 + d1 : u0 - d1; h[3 + a] = SG > 0 ? u1 - d0 : u1 + d0; }
+        else if (MU == 2) { h[a] = SG > 0 ? u0 + id0 : u0 - id0; h[3 + a] = SG > 0 ? u1 - id1 : u1 + id1; }
+        else { h[a] = SG > 0 ? u0 - d0 : u0 + d0; h[3 + a] = SG > 0 ? u1 - d1 : u1 + d1; }
+        h[a] = h[a] * fs;
+        h[3 + a] = h[3 + a] * fs;
+    }
+    const _Float16 z = _Float16(0.f);
+    const h4 hr0 = h4{h[0].x, h[1].x, h[2].x, z}, hi0 = h4{h[0].y, h[1].y, h[2].y, z};
+    const h4 hr1 = h4{h[3].x, h[4].x, h[5].x, z}, hi1 = h4{h[3].y, h[4].y, h[5].y, z};
+    mma_cw<0>(acc[0], acc[1], A, hr0, hi0);   // upper spins: + w
+    mma_cw<0>(acc[2], acc[3], A, hr1, hi1);
+    if (MU == 0) {        // spin 2 += -sg i w1, spin 3 += -sg i w0
+        mma_cw<negi_code<SG>()>(acc[4], acc[5], A, hr1, hi1);
+        mma_cw<negi_code<SG>()>(acc[6], acc[7], A, hr0, hi0);
+    } else if (MU == 1) { // spin 2 += -sg w1, spin 3 += sg w0
+        mma_cw<neg_code<SG>()>(acc[4], acc[5], A, hr1, hi1);
+        mma_cw<neg_code<-SG>()>(acc[6], acc[7], A, hr0, hi0);
+    } else if (MU == 2) { // spin 2 += -sg i w0, spin 3 += sg i w1
+        mma_cw<negi_code<SG>()>(acc[4], acc[5], A, hr0, hi0);
+        mma_cw<posi_code<SG>()>(acc[6], acc[7], A, hr1, hi1);
+    } else {              // spin 2 += -sg w0, spin 3 += -sg w1
+        mma_cw<neg_code<SG>()>(acc[4], acc[5], A, hr0, hi0);
+        mma_cw<neg_code<SG>()>(acc[6], acc[7], A, hr1, hi1);
+    }
+}
 
 }  // namespace mdwf

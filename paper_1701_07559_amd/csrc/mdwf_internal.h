@@ -343,7 +343,15 @@ __device__ __forceinline__ void* at_rhs(void* base, size_t stride, int r) {
 struct GaugeSet {
     char* seg[3] = {nullptr, nullptr, nullptr};   // per precision: 8 segments (parity*4+mu)
     size_t seg_bytes[3] = {0, 0, 0};
+    // FP16 links as matrix-core operands (LinkRowsF16): 16 segments
+    // (form*8 + parity*4 + mu), form 0 rows of U, form 1 rows of U^+
+    char* mrow = nullptr;
+    size_t mrow_bytes = 0;
 };
+// FP16 link rows for the matrix-core hop: per (form, parity, mu) segment
+// [4 rows][Vh4] 16-byte entries, a row r < 3 as halves (Re A[r][0..2], 0,
+// Im A[r][0..2], 0) with A = U (form 0) or U^+ (form 1); row 3 is zero.
+inline size_t link_rows_bytes(size_t Vh4) { return align256(64 * Vh4); }
 
 enum HopKind {
     HOP_BARE = 0,    // out = Dslash in
