@@ -75,7 +75,7 @@ SERVE_FIELDS = [((16, 16, 16, 48), 12, 201, 401), ((24, 24, 24, 64), 8, 202, 402
                 ((32, 32, 32, 64), 10, 203, 403), ((48, 48, 48, 64), 10, 204, 404)]
 SERVE_MASSES = (0.0048, 0.0102, 0.02)
 SERVE_WEIGHTS = (0.35, 0.3, 0.2, 0.15)
-SERVE_MAX_RHS = (12, 12, 12, 2)
+SERVE_MAX_RHS = (12, 12, 12, 12)
 ARRIVAL_SEED = 501
 FORMS = {"asym": 0, "sym": 1, "rp": 2}
 FORM_NAMES = {"asym": "asymmetric", "sym": "symmetric", "rp": "right-B-preconditioned"}
@@ -584,13 +584,16 @@ def _digest(a):
         return hashlib.blake2b(memoryview(a).cast("B"), digest_size=16).hexdigest()
 
 
-def run_phase(M, srv, fids, cols, reqs, arrivals, opts, host_cap, serial=False, digest=True):
+def run_phase(M, srv, fids, sites, qshapes, reqs, arrivals, opts, host_cap, serial=False, digest=True):
     """Submit reqs at the given arrival offsets (s) while a waiter thread
-    collects them in submission order; a request's solutions are hashed
-    (digest) and freed once it is collected.  Outstanding solution memory on
-    the host is bounded by host_cap bytes (a submission past it waits, and the
-    wait is recorded).  serial: submit each request only after the previous
-    one finished (no overlap).  Returns (records, wall seconds from the first
+    collects them in submission order.  A request of k RHS solves the
+    spin-colour columns 0..k-1 of its field's point source at sites[f]; the
+    server generates the sources on the device and returns the 4D wall
+    fields (shape qshapes[f]), which are hashed (digest) and freed once the
+    request is collected.  Outstanding output memory on the host is bounded
+    by host_cap bytes (a submission past it waits, and the wait is
+    recorded).  serial: submit each request only after the previous one
+    finished (no overlap).  Returns (records, wall seconds from the first
     submission to the last completion the server recorded)."""
     import threading
     cv = threading.Condition()
@@ -607,6 +610,7 @@ def run_phase(M, srv, fids, cols, reqs, arrivals, opts, host_cap, serial=False, 
                 rid, idx, xs, nbytes, held, t_sub = queue[i]
             i += 1
             st, info, times = srv.wait(rid)
+            log("request %d: status %d, %d RHS, latency %.2f s" % (idx, st, len(info), times[2]))
             recs[idx] = dict(status=st, info=info, times=times, held=held, t_end=t_sub + times[2],
                              digest=[_digest(x) for x in xs] if digest else None)
             xs.clear()
@@ -622,8 +626,8 @@ def run_phase(M, srv, fids, cols, reqs, arrivals, opts, host_cap, serial=False, 
         delay = ta - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        dims, l5 = SERVE_FIELDS[f][0], SERVE_FIELDS[f][1]
-        nbytes = k * cols[f][0].nbytes
+        l5 = SERVE_FIELDS[f][1]
+        nbytes = k * int(np.prod(qshapes[f])) * 16
         with cv:
             if serial:
                 cv.wait_for(lambda: state["done"] == idx)
@@ -631,10 +635,10 @@ def run_phase(M, srv, fids, cols, reqs, arrivals, opts, host_cap, serial=False, 
             cv.wait_for(lambda: state["out"] == 0 or state["out"] + nbytes <= host_cap)
             state["out"] += nbytes
         held = time.perf_counter() - t_ready
-        xs = [np.empty_like(cols[f][0]) for _ in range(k)]
+        xs = [np.empty(qshapes[f], complex) for _ in range(k)]
         t_sub = time.perf_counter() - t0
-        rid = srv.submit(fids[f], ACTION["M5"], ACTION["b5"], ACTION["c5"], masses[0], l5, cols[f][:k], xs,
-                         masses=masses, opts=opts)
+        rid = srv.submit_point(fids[f], ACTION["M5"], ACTION["b5"], ACTION["c5"], masses[0], l5, sites[f],
+                               list(range(k)), xs, masses=masses, opts=opts)
         with cv:
             queue.append((rid, idx, xs, nbytes, held, t_sub))
             cv.notify_all()
@@ -668,6 +672,11 @@ def phase_summary(reqs, recs, wall):
                 p99_latency_s=round(float(np.percentile(lat, 99)), 3),
                 mean_queued_s=round(float(np.mean([r["times"][0] for r in recs])), 3),
                 host_cap_wait_s=round(float(sum(r["held"] for r in recs)), 3),
+                # RHS per operator launch, averaged over RHS (more than the
+                # request's own when it shared a solve with queued requests)
+                mean_launch_rhs=round(float(np.mean([i.get("launch_rhs", 0) for r in recs for i in r["info"]])), 2),
+                shared_requests=sum(1 for (_, k, _), r in zip(reqs, recs)
+                                    if any(i.get("launch_rhs", 0) > k for i in r["info"])),
                 model_GBps=round(sum(i["model_bytes"] for r in recs for i in r["info"]) / wall / 1e9, 1),
                 max_true_resid=max(i["true_resid"] for r in recs for i in r["info"]),
                 all_ok=all(r["status"] == 0 and all(i["true_resid"] <= 1e-10 for i in r["info"]) for r in recs))
@@ -700,10 +709,8 @@ def serve_main(args):
             fids.append(srv.add_field(dims, U))
             if i > 0:
                 links[i] = None
-        cols = []
-        for f, (dims, l5, _, sseed) in enumerate(SERVE_FIELDS):
-            site = I.random_point_site(dims, sseed)
-            cols.append([I.point_source(dims, l5, site, c // 3, c % 3) for c in range(SERVE_MAX_RHS[f])])
+        sites = [I.random_point_site(dims, sseed) for dims, _, _, sseed in SERVE_FIELDS]
+        qshapes = [tuple(reversed(dims)) + (4, 3) for dims, _, _, _ in SERVE_FIELDS]
         st0 = srv.stats()
         log("server: budget %.1f GB after %d resident fields" % (st0["budget"] / 1e9, len(fids)))
         inner = M.MDWF_F16 if args.inner == "f16" else M.MDWF_F32
@@ -714,10 +721,10 @@ def serve_main(args):
 
         serial = None
         if not args.no_serial:
-            rs, ws = run_phase(M, srv, fids, cols, burst, [0.0] * len(burst), opts, cap, serial=True)
+            rs, ws = run_phase(M, srv, fids, sites, qshapes, burst, [0.0] * len(burst), opts, cap, serial=True)
             serial = phase_summary(burst, rs, ws)
             log("one at a time: %s" % serial)
-        ra, wa = run_phase(M, srv, fids, cols, burst, [0.0] * len(burst), opts, cap)
+        ra, wa = run_phase(M, srv, fids, sites, qshapes, burst, [0.0] * len(burst), opts, cap)
         conc = phase_summary(burst, ra, wa)
         log("burst: %s" % conc)
         same = None
@@ -730,7 +737,7 @@ def serve_main(args):
         arrivals = list(np.cumsum(gaps / rate))
         for f, k, ms in stream:
             log("poisson request: %s L5=%d nrhs=%d" % (SERVE_FIELDS[f][0], SERVE_FIELDS[f][1], k))
-        rp, wp = run_phase(M, srv, fids, cols, stream, arrivals, opts, cap, digest=False)
+        rp, wp = run_phase(M, srv, fids, sites, qshapes, stream, arrivals, opts, cap, digest=False)
         pois = phase_summary(stream, rp, wp)
         pois["arrival_rate_per_s"] = round(rate, 4)
         log("poisson: %s" % pois)
@@ -757,7 +764,8 @@ def serve_main(args):
         "data": "synthetic",
         "config": {
             "workload": "serving: %d resident exp(i0.25H) fields %s, M5=1.3 b5=1.5 c5=0.5, m_q per RHS from %s, "
-                        "point-source columns, %s inner, %s Schur form, every solve to true residual 1e-10; a burst of %d "
+                        "point-source requests (columns 0..k-1 of the field's point source generated on the device, 4D wall fields "
+                        "returned), %s inner, %s Schur form, every solve to true residual 1e-10; a burst of %d "
                         "requests (throughput) then %d Poisson arrivals offering %.2f x that throughput in RHS x 5D sites (latency)" %
                         (len(SERVE_FIELDS), ["%dx%dx%dx%d L5=%d" % (tuple(d) + (l5,)) for d, l5, _, _ in SERVE_FIELDS],
                          list(SERVE_MASSES), args.inner, FORM_NAMES[args.schur_form], len(burst), len(stream),

@@ -274,6 +274,20 @@ mdwf_status mdwf_solve_dev(mdwf_ctx *ctx, int nrhs, const double *const *b_dev, 
                            const double *mq, const mdwf_solver_opts *opts, mdwf_solve_info *info,
                            void *stream);
 
+/* The propagator solves of a point source (Sec. III.A: MDWF propagators from
+ * point and smeared sources): column k < ncols is the 5D right-hand side of
+ * spin-colour column cols[k] (NULL: k; c = spin * 3 + colour) of a unit
+ * point source eta at site = (x, y, z, t): P+ eta on slice L5-1 for spins
+ * 0, 1 and P- eta on slice 0 for spins 2, 3.  The sources are generated on
+ * the device and no 5D field crosses to the host: q[k] (host, canonical 4D
+ * [t][z][y][x][spin][col] complex) receives the wall field
+ * q = P- x_0 + P+ x_{L5-1} of the solution, from which the 4D propagator
+ * and the pseudoscalar correlator follow (mdwf_pion_correlator_dev).
+ * Otherwise as mdwf_solve (opts.x_ref must be NULL).  ERR_ARG on a site
+ * outside the lattice or a column outside 0..11. */
+mdwf_status mdwf_solve_point(mdwf_ctx *ctx, const int *site, int ncols, const int *cols, const double *mq,
+                             const mdwf_solver_opts *opts, double *const *q, mdwf_solve_info *info);
+
 /* Fill opts with defaults: tol 1e-10, max_iter 100000, inner F64, delta 0.1,
  * check_every 1, use_graph 0, profile_iters 0, schur_form 0, max_seconds 0,
  * x_ref NULL. */
@@ -282,9 +296,12 @@ void mdwf_default_opts(mdwf_solver_opts *opts);
 /* Device bytes a solve of nrhs RHS on this lattice at fifth-dimension extent
  * L5 allocates (its memory plan: per RHS x_hi and b' in FP64, r, p, p', s, q
  * in the inner precision and an FP32 x_lo when mixed; shared FP64 scratch,
- * the hop temporary, the canonical staging field when host_io, and a
- * margin for small tables).  Host arithmetic only, no device needed.
- * ERR_ARG on a bad geometry, L5, precision or nrhs < 1. */
+ * the hop temporary, a canonical staging field and a margin for small
+ * tables).  host_io: 0 device fields (mdwf_solve_dev, no staging), 1 host
+ * fields (mdwf_solve, a 5D staging field), 2 point sources with host wall
+ * fields (mdwf_solve_point, a 4D staging field).  Host arithmetic only, no
+ * device needed.  ERR_ARG on a bad geometry, L5, precision, host_io or
+ * nrhs < 1. */
 mdwf_status mdwf_solve_footprint(const mdwf_geometry *geom, int L5, mdwf_prec inner, int nrhs, int host_io,
                                  size_t *bytes);
 
@@ -474,6 +491,18 @@ mdwf_status mdwf_server_add_field(mdwf_server *srv, const mdwf_geometry *geom, c
 mdwf_status mdwf_server_submit(mdwf_server *srv, int field_id, const mdwf_action *act, int nrhs,
                                const double *const *b, double *const *x, const double *mq,
                                const mdwf_solver_opts *opts, int *req_id);
+
+/* Queue the point-source propagator solves of mdwf_solve_point on field_id:
+ * ncols columns (cols: spin-colour indices, NULL = 0..ncols-1) of a unit
+ * point source at site[4], generated on the device; q[k] receives the
+ * wall field of column k (host canonical 4D, valid until mdwf_server_wait
+ * returns).  No 5D field crosses the host, so a request costs its solver
+ * state on the device and 4D fields on the host.  Admitted, split and
+ * shared like mdwf_server_submit (point requests share solves with point
+ * requests).  ERR_ARG on bad arguments, ERR_OOM if not even one RHS fits. */
+mdwf_status mdwf_server_submit_point(mdwf_server *srv, int field_id, const mdwf_action *act, const int *site,
+                                     int ncols, const int *cols, const double *mq, const mdwf_solver_opts *opts,
+                                     double *const *q, int *req_id);
 
 /* Block until request req_id has finished; fill info[nrhs] (may be NULL) and
  * times[3] (may be NULL): seconds queued, seconds running, total latency.

@@ -487,7 +487,8 @@ mdwf_status mdwf_solve_footprint(const mdwf_geometry* geom, int L5, mdwf_prec in
     const int L[4] = {geom->X, geom->Y, geom->Z, geom->T};
     for (int k = 0; k < 4; ++k)
         if (L[k] < 2 || (L[k] & 1)) return MDWF_ERR_ARG;
-    *bytes = solve_footprint(plan_geo(*geom, L5), Prec(inner), nrhs, host_io != 0);
+    if (host_io < 0 || host_io > 2) return MDWF_ERR_ARG;
+    *bytes = solve_footprint(plan_geo(*geom, L5), Prec(inner), nrhs, host_io);
     return MDWF_OK;
 }
 
@@ -907,6 +908,17 @@ mdwf_status mdwf_solve_dev(mdwf_ctx* c, int nrhs, const double* const* b, double
     if (s) return s;
     hipStream_t st = stream ? static_cast<hipStream_t>(stream) : c->stream;
     return mdwf_solve_impl(c, nrhs, b, x, false, mq, o, info, st);
+}
+
+mdwf_status mdwf_solve_point(mdwf_ctx* c, const int* site, int ncols, const int* cols, const double* mq,
+                             const mdwf_solver_opts* o, double* const* q, mdwf_solve_info* info) {
+    mdwf_status s = ready(c);
+    if (s) return s;
+    if (!site || !q || ncols < 1) return fail(c, MDWF_ERR_ARG, "need a site, ncols >= 1 and outputs");
+    std::vector<int> src;
+    for (int k = 0; k < ncols; ++k) src.insert(src.end(), {site[0], site[1], site[2], site[3], cols ? cols[k] : k});
+    const PointIO pt{src.data(), q};
+    return mdwf_solve_impl(c, ncols, nullptr, nullptr, true, mq, o, info, c->stream, &pt);
 }
 
 mdwf_status mdwf_solve(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, const double* mq,

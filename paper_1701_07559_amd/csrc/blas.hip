@@ -190,6 +190,54 @@ void launch_unpack_parity(const Geo& g, Prec p, int full, int par, const void* s
     }
 }
 
+// ------------------------------------------------- point sources and wall fields
+// The 5D right-hand side of one spin-colour column of a unit point source
+// at 4D site (x, y, z, t): P+ eta on slice L5-1 (spins 0, 1) or P- eta on
+// slice 0 (spins 2, 3), in the FP64 native halves `even` and `odd` (zeroed
+// by the caller); one thread writes the single non-zero entry.
+__global__ void k_point_source(const Geo g, int x, int y, int z, int t, int col, void* even, void* odd) {
+    const int par = (x + y + z + t) & 1;
+    const int i = (x >> 1) + g.Xh * (y + g.Y * (z + g.Z * t));
+    const int s = col / 3 < 2 ? g.L5 - 1 : 0;
+    double2* dst = static_cast<double2*>(par ? odd : even);
+    dst[size_t(col) * g.Vh + size_t(i) * g.L5 + s] = make_double2(1.0, 0.0);
+}
+
+void launch_point_source(const Geo& g, const int src[5], void* even, void* odd, hipStream_t st) {
+    hipLaunchKernelGGL(k_point_source, dim3(1), dim3(1), 0, st, g, src[0], src[1], src[2], src[3], src[4], even, odd);
+}
+
+// The wall field q = P- x_0 + P+ x_{L5-1} of a 5D solution held as FP64
+// native halves, written as a canonical 4D field [t][z][y][x][spin][col].
+__global__ void k_wall_field(const Geo g, const void* even, const void* odd, double* q) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * g.Vh4) return;
+    const int par = idx >= g.Vh4;
+    const int i = idx - par * g.Vh4;
+    uint32_t r = uint32_t(i);
+    uint32_t qd = g.fXh.div(r);
+    const int xh = int(r - qd * uint32_t(g.Xh));
+    r = qd;
+    qd = g.fY.div(r);
+    const int y = int(r - qd * uint32_t(g.Y));
+    r = qd;
+    qd = g.fZ.div(r);
+    const int z = int(r - qd * uint32_t(g.Z));
+    const int t = int(qd);
+    const int x = 2 * xh + ((y + z + t + par) & 1);
+    const size_t lex = size_t(x) + size_t(g.X) * (y + size_t(g.Y) * (z + size_t(g.Z) * t));
+    const double2* src = static_cast<const double2*>(par ? odd : even);
+    const size_t up = size_t(i) * g.L5 + (g.L5 - 1), dn = size_t(i) * g.L5;
+    double2* dst = reinterpret_cast<double2*>(q) + lex * 12;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) dst[c] = src[size_t(c) * g.Vh + (c < 6 ? up : dn)];
+}
+
+void launch_wall_field(const Geo& g, const void* even, const void* odd, double* q, hipStream_t st) {
+    const int n = 2 * g.Vh4;
+    hipLaunchKernelGGL(k_wall_field, dim3((n + 255) / 256), dim3(256), 0, st, g, even, odd, q);
+}
+
 void launch_pack(const Geo& g, Prec p, int kind, const double* canon, void* native, hipStream_t st) {
     const size_t hb = half_field_bytes(p, g.Vh);
     if (kind == 0) {

@@ -75,9 +75,20 @@ double link_site_bytes(Prec p, int L5);
 
 }  // namespace mdwf
 
-// host_io: b and x are host pointers, streamed through one device staging field
+// Point-source solves: RHS k is spin-colour column src[5k+4] of a unit point
+// source at (x, y, z, t) = src[5k..5k+3], generated on the device; its
+// solution's wall field q = P- x_0 + P+ x_{L5-1} goes to q[k] (host
+// canonical 4D) instead of a 5D x.
+struct PointIO {
+    const int* src;
+    double* const* q;
+};
+
+// host_io: b and x are host pointers, streamed through one device staging
+// field; pt (b, x unused): point sources and wall-field outputs on the host
 mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b, double* const* x, bool host_io,
-                            const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st);
+                            const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info, hipStream_t st,
+                            const PointIO* pt = nullptr);
 
 namespace mdwf {
 // Device memory plan of a solve (bytes): per_rhs resident vectors of one RHS,
@@ -86,10 +97,14 @@ namespace mdwf {
 struct SolvePlan {
     size_t per_rhs, shared, tmp_per_rhs, margin;
 };
-SolvePlan solve_plan(const Geo& g, Prec inner, bool host_io);
+// Where a solve's right-hand sides and solutions live: device canonical 5D
+// fields, host canonical 5D fields (one 5D staging field), or point sources
+// with host 4D wall fields (one 4D staging field).
+enum SolveIo { IO_DEVICE = 0, IO_HOST = 1, IO_POINT = 2 };
+SolvePlan solve_plan(const Geo& g, Prec inner, int io);
 // Device bytes a solve of nrhs RHS allocates (solver vectors, shared
 // scratch, hop temporary for all RHS at once), as its memory plan counts them.
-size_t solve_footprint(const Geo& g, Prec inner, int nrhs, bool host_io);
+size_t solve_footprint(const Geo& g, Prec inner, int nrhs, int io);
 // Geometry of a lattice at fifth-dimension extent L5 (sizes only: enough for
 // memory plans, not for launches).
 Geo plan_geo(const mdwf_geometry& geom, int L5);

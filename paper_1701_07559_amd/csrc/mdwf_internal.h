@@ -428,6 +428,10 @@ void launch_cg_xpend(const Geo& g, Prec px, Prec pi, void* x, size_t sx, const v
 void launch_flush(const Geo& g, Prec px, void* xhi, size_t shi, void* xlo, size_t slo, int nrhs,
                   const int* active, hipStream_t st);
 int blas_blocks_per_rhs(const Geo& g);
+// Point-source columns and wall fields (blas.hip): src = x, y, z, t and the
+// spin-colour column; even / odd are FP64 native halves.
+void launch_point_source(const Geo& g, const int src[5], void* even, void* odd, hipStream_t st);
+void launch_wall_field(const Geo& g, const void* even, const void* odd, double* q, hipStream_t st);
 
 // Per-RHS scalar state of the CG recursion, in device memory.
 struct CGScal {

@@ -38,9 +38,13 @@ double wall() {
 
 struct Request {
     int field = 0;
+    int n = 0;                  // RHS
+    int kind = 0;               // 0: 5D b / x fields; 1: point sources, 4D wall-field outputs
     mdwf_action act{};
     std::vector<const double*> b;
     std::vector<double*> x;
+    std::vector<int> src;       // kind 1: x, y, z, t, spin-colour column per RHS
+    std::vector<double*> q;     // kind 1: wall-field outputs
     std::vector<double> mq;
     std::vector<const double*> xref;   // reference solutions (opts.x_ref), or empty
     mdwf_solver_opts opts{};
@@ -84,14 +88,22 @@ mdwf_status sfail(mdwf_server* s, mdwf_status st, const std::string& msg) {
 }
 
 // footprint of a request (solver buffers with host I/O; links are resident)
-size_t footprint(const GaugeField& f, const mdwf_action& a, int nrhs, mdwf_prec inner) {
-    return solve_footprint(plan_geo(f.geom, a.L5), Prec(inner), nrhs, true);
+size_t footprint(const GaugeField& f, const mdwf_action& a, int nrhs, mdwf_prec inner, int kind = 0) {
+    return solve_footprint(plan_geo(f.geom, a.L5), Prec(inner), nrhs, kind ? IO_POINT : IO_HOST);
+}
+
+// One solve of RHS [k0, k0 + k) of the given arrays (5D fields or point sources).
+mdwf_status solve_part(mdwf_ctx* c, int kind, int k, const double* const* b, double* const* x, const int* src,
+                       double* const* q, const double* mq, const mdwf_solver_opts* o, mdwf_solve_info* info) {
+    if (kind == 0) return mdwf_solve(c, k, b, x, mq, o, info);
+    const PointIO pt{src, q};
+    return mdwf_solve_impl(c, k, nullptr, nullptr, true, mq, o, info, c->stream, &pt);
 }
 
 // Requests that can share one solve, so that every hop launch of it reads
 // the links once for all their RHS: the same field, the same action apart
 // from the masses (each RHS keeps its own), the same solver options, and
-// neither split into sub-batches.
+// neither split into sub-batches; 5D-field and point requests do not mix.
 bool same_opts(const mdwf_solver_opts& a, const mdwf_solver_opts& b) {
     return a.tol == b.tol && a.max_iter == b.max_iter && a.inner == b.inner && a.delta == b.delta &&
            a.check_every == b.check_every && a.schur_form == b.schur_form && a.max_seconds == b.max_seconds;
@@ -99,7 +111,7 @@ bool same_opts(const mdwf_solver_opts& a, const mdwf_solver_opts& b) {
 bool can_share(const Request& a, const Request& b) {
     return a.field == b.field && a.act.L5 == b.act.L5 && a.act.M5 == b.act.M5 && a.act.b5 == b.act.b5 &&
            a.act.c5 == b.act.c5 && same_opts(a.opts, b.opts) && a.xref.empty() == b.xref.empty() &&
-           a.batch == int(a.b.size()) && b.batch == int(b.b.size());
+           a.kind == b.kind && a.batch == a.n && b.batch == b.n;
 }
 
 // Status of one request of a shared solve from its RHS's records.
@@ -134,12 +146,12 @@ void worker_loop(mdwf_server* s) {
             f = s->fields[r->field];   // copied: add_field may grow the list meanwhile
             // queued requests that can share this solve join it while the
             // combined footprint fits (they would otherwise wait behind it)
-            int n = int(r->b.size());
+            int n = r->n;
             if (r->batch == n) {
                 for (auto it = s->pending.begin(); it != s->pending.end() && n < kMaxShared;) {
                     Request& q = s->reqs[*it];
-                    const int nq = int(q.b.size());
-                    const size_t fq = footprint(f, r->act, n + nq, r->opts.inner);
+                    const int nq = q.n;
+                    const size_t fq = footprint(f, r->act, n + nq, r->opts.inner, r->kind);
                     if (can_share(*r, q) && n + nq <= kMaxShared && s->reserved + fq <= s->budget) {
                         grp.push_back(&q);
                         n += nq;
@@ -169,7 +181,7 @@ void worker_loop(mdwf_server* s) {
         if (st == MDWF_OK) st = mdwf_set_action(c, &r->act);
         std::string msg = st == MDWF_OK ? std::string() : std::string(mdwf_last_error(c));
         if (grp.size() == 1) {
-            const int n = int(r->b.size());
+            const int n = r->n;
             // sub-batches in order; one that did not converge still wrote its
             // results, so the rest still run; a hard error stops the request
             for (int k0 = 0; st == MDWF_OK || st == MDWF_ERR_NOCONV || st == MDWF_ERR_NUMERIC; k0 += r->batch) {
@@ -179,8 +191,10 @@ void worker_loop(mdwf_server* s) {
                 if (r->opts.max_seconds > 0.0)
                     ok.max_seconds = std::max(1e-9, r->opts.max_seconds - (wall() - r->t_start));
                 ok.x_ref = r->xref.empty() ? nullptr : r->xref.data() + k0;
-                const mdwf_status sk = mdwf_solve(c, k, r->b.data() + k0, r->x.data() + k0, r->mq.data() + k0, &ok,
-                                                  r->info.data() + k0);
+                const mdwf_status sk =
+                    solve_part(c, r->kind, k, r->kind ? nullptr : r->b.data() + k0, r->kind ? nullptr : r->x.data() + k0,
+                               r->kind ? r->src.data() + 5 * k0 : nullptr, r->kind ? r->q.data() + k0 : nullptr,
+                               r->mq.data() + k0, &ok, r->info.data() + k0);
                 if (sk == MDWF_OK) continue;
                 const bool hard = sk != MDWF_ERR_NOCONV && sk != MDWF_ERR_NUMERIC;
                 if (st == MDWF_OK || hard) {
@@ -194,27 +208,33 @@ void worker_loop(mdwf_server* s) {
             // one solve for the whole group: RHS of every request side by
             // side, each with its own mass; its results go back per request
             std::vector<const double*> b;
-            std::vector<double*> x;
+            std::vector<double*> x, qo;
+            std::vector<int> src;
             std::vector<double> mq;
             std::vector<const double*> xref;
+            int total = 0;
             for (Request* q : grp) {
                 b.insert(b.end(), q->b.begin(), q->b.end());
                 x.insert(x.end(), q->x.begin(), q->x.end());
+                src.insert(src.end(), q->src.begin(), q->src.end());
+                qo.insert(qo.end(), q->q.begin(), q->q.end());
                 mq.insert(mq.end(), q->mq.begin(), q->mq.end());
                 xref.insert(xref.end(), q->xref.begin(), q->xref.end());
+                total += q->n;
             }
-            std::vector<mdwf_solve_info> info(b.size());
+            std::vector<mdwf_solve_info> info(total);
             if (st == MDWF_OK) {
                 mdwf_solver_opts ok = r->opts;
                 ok.x_ref = xref.empty() ? nullptr : xref.data();
-                st = mdwf_solve(c, int(b.size()), b.data(), x.data(), mq.data(), &ok, info.data());
+                st = solve_part(c, r->kind, total, b.data(), x.data(), src.data(), qo.data(), mq.data(), &ok,
+                                info.data());
                 if (st != MDWF_OK) msg = mdwf_last_error(c);
             }
             const bool hard = st != MDWF_OK && st != MDWF_ERR_NOCONV && st != MDWF_ERR_NUMERIC;
             size_t k0 = 0;
             for (Request* q : grp) {
-                std::copy(info.begin() + k0, info.begin() + k0 + q->b.size(), q->info.begin());
-                k0 += q->b.size();
+                std::copy(info.begin() + k0, info.begin() + k0 + q->n, q->info.begin());
+                k0 += q->n;
                 q->status = hard ? st : request_status(*q);
                 q->err = q->status == MDWF_OK ? std::string() : msg;
             }
@@ -293,15 +313,15 @@ mdwf_status mdwf_server_add_field(mdwf_server* s, const mdwf_geometry* geom, con
         for (auto it = s->pending.begin(); it != s->pending.end();) {
             Request& r = s->reqs[*it];
             const GaugeField& fld = s->fields[r.field];
-            while (r.batch > 0 && footprint(fld, r.act, r.batch, r.opts.inner) > s->budget) --r.batch;
+            while (r.batch > 0 && footprint(fld, r.act, r.batch, r.opts.inner, r.kind) > s->budget) --r.batch;
             if (r.batch > 0) {
-                r.footprint = footprint(fld, r.act, r.batch, r.opts.inner);
+                r.footprint = footprint(fld, r.act, r.batch, r.opts.inner, r.kind);
                 ++it;
                 continue;
             }
             r.status = MDWF_ERR_OOM;
             r.err = "after a gauge field was added, one RHS of this request needs " +
-                    std::to_string(footprint(fld, r.act, 1, r.opts.inner)) + " device bytes, the budget is " +
+                    std::to_string(footprint(fld, r.act, 1, r.opts.inner, r.kind)) + " device bytes, the budget is " +
                     std::to_string(s->budget);
             r.t_start = r.t_end = wall();
             r.done = true;
@@ -313,11 +333,12 @@ mdwf_status mdwf_server_add_field(mdwf_server* s, const mdwf_geometry* geom, con
     return MDWF_OK;
 }
 
-mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* act, int nrhs,
-                               const double* const* b, double* const* x, const double* mq,
-                               const mdwf_solver_opts* opts, int* req_id) {
-    if (!s || !act || !b || !x || !req_id || nrhs < 1) return sfail(s, MDWF_ERR_ARG, "bad request arguments");
-    Request r;
+}  // extern "C"
+
+namespace {
+// Validate and queue a request whose kind-specific arrays are filled in.
+mdwf_status enqueue(mdwf_server* s, int field_id, const mdwf_action* act, Request&& r, const double* mq,
+                    const mdwf_solver_opts* opts, int* req_id) {
     {
         std::lock_guard<std::mutex> lk(s->m);
         if (field_id < 0 || field_id >= int(s->fields.size())) return sfail(s, MDWF_ERR_ARG, "unknown field");
@@ -325,32 +346,30 @@ mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* 
     }
     if (act->L5 < 1 || act->L5 > kMaxL5) return sfail(s, MDWF_ERR_ARG, "need 1 <= L5 <= 32");
     r.act = *act;
-    r.b.assign(b, b + nrhs);
-    r.x.assign(x, x + nrhs);
-    for (int k = 0; k < nrhs; ++k)
-        if (!r.b[k] || !r.x[k]) return sfail(s, MDWF_ERR_ARG, "null right-hand side or solution pointer");
-    r.mq.assign(nrhs, act->mq);
-    if (mq) r.mq.assign(mq, mq + nrhs);
+    r.mq.assign(r.n, act->mq);
+    if (mq) r.mq.assign(mq, mq + r.n);
     mdwf_default_opts(&r.opts);
     if (opts) r.opts = *opts;
     if (r.opts.x_ref) {   // copied like b and x; the fields stay the caller's
-        r.xref.assign(r.opts.x_ref, r.opts.x_ref + nrhs);
-        for (int k = 0; k < nrhs; ++k)
+        if (r.kind) return sfail(s, MDWF_ERR_ARG, "reference solutions need 5D solutions (not point solves)");
+        r.xref.assign(r.opts.x_ref, r.opts.x_ref + r.n);
+        for (int k = 0; k < r.n; ++k)
             if (!r.xref[k]) return sfail(s, MDWF_ERR_ARG, "null reference solution pointer");
     }
     r.opts.x_ref = nullptr;
     r.opts.use_graph = 0;       // each solve runs eagerly on its worker's stream
     r.opts.profile_iters = 0;
-    r.info.assign(nrhs, mdwf_solve_info{});
+    r.info.assign(r.n, mdwf_solve_info{});
     std::lock_guard<std::mutex> lk(s->m);
     // the most RHS per sub-batch whose footprint fits the budget
     const GaugeField& fld = s->fields[field_id];
-    r.batch = nrhs;
-    while (r.batch > 0 && footprint(fld, r.act, r.batch, r.opts.inner) > s->budget) --r.batch;
+    r.batch = r.n;
+    while (r.batch > 0 && footprint(fld, r.act, r.batch, r.opts.inner, r.kind) > s->budget) --r.batch;
     if (r.batch == 0)
-        return sfail(s, MDWF_ERR_OOM, "one RHS needs " + std::to_string(footprint(fld, r.act, 1, r.opts.inner)) +
-                                          " device bytes, the budget is " + std::to_string(s->budget));
-    r.footprint = footprint(fld, r.act, r.batch, r.opts.inner);
+        return sfail(s, MDWF_ERR_OOM,
+                     "one RHS needs " + std::to_string(footprint(fld, r.act, 1, r.opts.inner, r.kind)) +
+                         " device bytes, the budget is " + std::to_string(s->budget));
+    r.footprint = footprint(fld, r.act, r.batch, r.opts.inner, r.kind);
     r.t_submit = wall();
     const int id = s->next_id++;
     s->reqs.emplace(id, std::move(r));
@@ -358,6 +377,47 @@ mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* 
     *req_id = id;
     s->cv_work.notify_all();
     return MDWF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mdwf_status mdwf_server_submit(mdwf_server* s, int field_id, const mdwf_action* act, int nrhs,
+                               const double* const* b, double* const* x, const double* mq,
+                               const mdwf_solver_opts* opts, int* req_id) {
+    if (!s || !act || !b || !x || !req_id || nrhs < 1) return sfail(s, MDWF_ERR_ARG, "bad request arguments");
+    Request r;
+    r.n = nrhs;
+    r.b.assign(b, b + nrhs);
+    r.x.assign(x, x + nrhs);
+    for (int k = 0; k < nrhs; ++k)
+        if (!r.b[k] || !r.x[k]) return sfail(s, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+    return enqueue(s, field_id, act, std::move(r), mq, opts, req_id);
+}
+
+mdwf_status mdwf_server_submit_point(mdwf_server* s, int field_id, const mdwf_action* act, const int* site,
+                                     int ncols, const int* cols, const double* mq, const mdwf_solver_opts* opts,
+                                     double* const* q, int* req_id) {
+    if (!s || !act || !site || !q || !req_id || ncols < 1) return sfail(s, MDWF_ERR_ARG, "bad request arguments");
+    Request r;
+    r.n = ncols;
+    r.kind = 1;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        if (field_id < 0 || field_id >= int(s->fields.size())) return sfail(s, MDWF_ERR_ARG, "unknown field");
+        const mdwf_geometry& g = s->fields[field_id].geom;
+        const int ext[4] = {g.X, g.Y, g.Z, g.T};
+        for (int d = 0; d < 4; ++d)
+            if (site[d] < 0 || site[d] >= ext[d]) return sfail(s, MDWF_ERR_ARG, "point source site outside the lattice");
+    }
+    for (int k = 0; k < ncols; ++k) {
+        const int col = cols ? cols[k] : k;
+        if (col < 0 || col > 11) return sfail(s, MDWF_ERR_ARG, "spin-colour column must be in 0..11");
+        if (!q[k]) return sfail(s, MDWF_ERR_ARG, "null wall-field output pointer");
+        r.src.insert(r.src.end(), {site[0], site[1], site[2], site[3], col});
+    }
+    r.q.assign(q, q + ncols);
+    return enqueue(s, field_id, act, std::move(r), mq, opts, req_id);
 }
 
 mdwf_status mdwf_server_wait(mdwf_server* s, int req_id, mdwf_solve_info* info, double* times) {

@@ -96,6 +96,7 @@ struct Solver {
     double* const* x;
     bool host_io;
     size_t canon_bytes;
+    const PointIO* pt = nullptr;   // point sources and wall-field outputs
 
     ~Solver() {
         for (hipEvent_t e : pev) (void)hipEventDestroy(e);
@@ -150,6 +151,12 @@ struct Solver {
 
     // source k, packed into the shared scratch be / bo
     void load_b(int k) {
+        if (pt) {   // a point-source column, generated in place
+            hipok(hipMemsetAsync(be, 0, H64, st), "memset");
+            hipok(hipMemsetAsync(bo, 0, H64, st), "memset");
+            launch_point_source(g, pt->src + 5 * k, be, bo, st);
+            return;
+        }
         const double* src = b[k];
         if (host_io) {
             hipok(hipMemcpyAsync(canon, b[k], canon_bytes, hipMemcpyHostToDevice, st), "b H2D");
@@ -187,7 +194,7 @@ double now() {
 namespace mdwf {
 // The solver's device memory plan, shared by the allocation below and by
 // every footprint estimate (the server's admission, mdwf_solve_footprint).
-SolvePlan solve_plan(const Geo& g, Prec inner, bool host_io) {
+SolvePlan solve_plan(const Geo& g, Prec inner, int io) {
     const bool mixed = inner != P64;
     const size_t H64 = half_field_bytes(P64, g.Vh), Hi = half_field_bytes(inner, g.Vh);
     const size_t Hx = half_field_bytes(P32, g.Vh);
@@ -196,7 +203,10 @@ SolvePlan solve_plan(const Geo& g, Prec inner, bool host_io) {
     // inner solution x_lo when mixed
     pl.per_rhs = 2 * H64 + (mixed ? 5 * Hi + Hx : 5 * H64);
     // FP64 scratch be, bo, r_hi, t64, ye, xo; the canonical staging field
-    pl.shared = 6 * H64 + (host_io ? size_t(2) * g.Vh * 24 * sizeof(double) : 0);
+    // (5D for host fields, 4D for wall-field outputs)
+    const size_t stage = io == IO_HOST ? size_t(2) * g.Vh * 24 * sizeof(double)
+                       : io == IO_POINT ? size_t(2) * g.Vh4 * 24 * sizeof(double) : 0;
+    pl.shared = 6 * H64 + stage;
     pl.tmp_per_rhs = mixed ? Hi : H64;   // hop temporary of one RHS of a chunk
     pl.margin = size_t(64) << 20;        // coefficient tables, scalars, partials
     return pl;
@@ -212,18 +222,33 @@ Geo plan_geo(const mdwf_geometry& geom, int L5) {
     return g;
 }
 
-size_t solve_footprint(const Geo& g, Prec inner, int n, bool host_io) {
-    const SolvePlan pl = solve_plan(g, inner, host_io);
+size_t solve_footprint(const Geo& g, Prec inner, int n, int io) {
+    const SolvePlan pl = solve_plan(g, inner, io);
     return pl.per_rhs * n + pl.shared + pl.tmp_per_rhs * n + pl.margin;
 }
 }  // namespace mdwf
 
 mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, double* const* x_out, bool host_io,
-                            const double* mq, const mdwf_solver_opts* o_in, mdwf_solve_info* info, hipStream_t st) {
+                            const double* mq, const mdwf_solver_opts* o_in, mdwf_solve_info* info, hipStream_t st,
+                            const PointIO* pt) {
     const double t_start = now();
-    if (nrhs < 1 || !b_in || !x_out) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
-    for (int k = 0; k < nrhs; ++k)
-        if (!b_in[k] || !x_out[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+    if (pt) {
+        if (nrhs < 1 || !pt->src || !pt->q) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1, sources and outputs");
+        const int ext[4] = {c->geo.X, c->geo.Y, c->geo.Z, c->geo.T};
+        for (int k = 0; k < nrhs; ++k) {
+            if (!pt->q[k]) return fail(c, MDWF_ERR_ARG, "null wall-field output pointer");
+            for (int d = 0; d < 4; ++d)
+                if (pt->src[5 * k + d] < 0 || pt->src[5 * k + d] >= ext[d])
+                    return fail(c, MDWF_ERR_ARG, "point source site outside the lattice");
+            if (pt->src[5 * k + 4] < 0 || pt->src[5 * k + 4] > 11)
+                return fail(c, MDWF_ERR_ARG, "spin-colour column must be in 0..11");
+        }
+        host_io = true;
+    } else {
+        if (nrhs < 1 || !b_in || !x_out) return fail(c, MDWF_ERR_ARG, "need nrhs >= 1 and b, x arrays");
+        for (int k = 0; k < nrhs; ++k)
+            if (!b_in[k] || !x_out[k]) return fail(c, MDWF_ERR_ARG, "null right-hand side or solution pointer");
+    }
     mdwf_solver_opts o;
     mdwf_default_opts(&o);
     if (o_in) o = *o_in;
@@ -232,6 +257,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         return fail(c, MDWF_ERR_ARG,
                     "bad solver options (tol > 0, max_iter >= 1, 0 < delta < 1, schur_form 0-2, max_seconds >= 0)");
     if (o.check_every < 1) o.check_every = 1;
+    if (pt && o.x_ref) return fail(c, MDWF_ERR_ARG, "reference solutions need 5D solutions (not point solves)");
     std::vector<double> masses(nrhs, c->act.mq);
     if (mq)
         for (int k = 0; k < nrhs; ++k) {
@@ -256,12 +282,13 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
     S.Hx = half_field_bytes(S.px, g.Vh);
     S.nbh = hop_blocks_per_rhs(g);
     S.nbb = blas_blocks_per_rhs(g);
-    S.canon_bytes = size_t(2) * g.Vh * 24 * sizeof(double);
+    S.canon_bytes = pt ? size_t(2) * g.Vh4 * 24 * sizeof(double) : size_t(2) * g.Vh * 24 * sizeof(double);
+    S.pt = pt;
     const int n = nrhs;
 
     // memory plan: the hop temporary is shared by `chunk` RHS; shrink the
     // chunk when the whole batch would not fit next to the resident state
-    const SolvePlan plan = solve_plan(g, S.pi, host_io);
+    const SolvePlan plan = solve_plan(g, S.pi, pt ? IO_POINT : host_io ? IO_HOST : IO_DEVICE);
     const size_t per_rhs = plan.per_rhs, shared = plan.shared;
     size_t held = 0;
     for (auto& kv : c->bufs)
@@ -285,8 +312,11 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
                 mdwf_solver_opts ok = o;   // the time limit covers the whole call
                 if (o.max_seconds > 0.0) ok.max_seconds = std::max(1e-9, o.max_seconds - (now() - t_start));
                 if (o.x_ref) ok.x_ref = o.x_ref + k0;
-                const mdwf_status r = mdwf_solve_impl(c, nk, b_in + k0, x_out + k0, host_io, mq ? mq + k0 : nullptr,
-                                                      &ok, info ? info + k0 : nullptr, st);
+                PointIO pk{};
+                if (pt) pk = PointIO{pt->src + 5 * k0, pt->q + k0};
+                const mdwf_status r = mdwf_solve_impl(c, nk, pt ? nullptr : b_in + k0, pt ? nullptr : x_out + k0, host_io,
+                                                      mq ? mq + k0 : nullptr, &ok, info ? info + k0 : nullptr, st,
+                                                      pt ? &pk : nullptr);
                 if (r != MDWF_OK && r != MDWF_ERR_NOCONV && r != MDWF_ERR_NUMERIC) return r;
                 if (r != MDWF_OK && worst == MDWF_OK) worst = r;
             }
@@ -460,7 +490,11 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         const double se = S.fetch_sums(S.nbb, 1, nullptr)[0];
         launch_axpby(g, P64, 1.0, S.bo, -1.0, S.t64, S.t64, S.H64, 1, nullptr, S.part, st);
         const double so = S.fetch_sums(S.nbb, 1, nullptr)[0];
-        if (write_x) {
+        if (write_x && S.pt) {   // the wall field of the solution, to the host
+            launch_wall_field(g, xk, S.xo, S.canon, st);
+            S.hipok(hipMemcpyAsync(S.pt->q[k], S.canon, S.canon_bytes, hipMemcpyDeviceToHost, st), "q D2H");
+            S.hipok(hipStreamSynchronize(st), "q write");
+        } else if (write_x) {
             double* dst = host_io ? S.canon : x_out[k];
             launch_unpack_parity(g, P64, 1, 0, xk, dst, st);
             launch_unpack_parity(g, P64, 1, 1, S.xo, dst, st);

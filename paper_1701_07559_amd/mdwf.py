@@ -126,6 +126,8 @@ def _load():
                         C.POINTER(mdwf_solve_info)], ip),
         "mdwf_solve_dev": ([vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
                             C.POINTER(mdwf_solve_info), vp], ip),
+        "mdwf_solve_point": ([vp, C.POINTER(ip), ip, C.POINTER(ip), C.POINTER(dp), C.POINTER(mdwf_solver_opts),
+                              C.POINTER(vp), C.POINTER(mdwf_solve_info)], ip),
         "mdwf_default_opts": ([C.POINTER(mdwf_solver_opts)], None),
         "mdwf_op_model": ([vp, ip, ip, C.POINTER(dp), C.POINTER(dp)], ip),
         "mdwf_autotune": ([vp, C.POINTER(mdwf_launch_tune)], ip),
@@ -147,6 +149,8 @@ def _load():
         "mdwf_server_add_field": ([vp, C.POINTER(mdwf_geometry), vp, C.POINTER(ip)], ip),
         "mdwf_server_submit": ([vp, ip, C.POINTER(mdwf_action), ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(dp),
                                 C.POINTER(mdwf_solver_opts), C.POINTER(ip)], ip),
+        "mdwf_server_submit_point": ([vp, ip, C.POINTER(mdwf_action), C.POINTER(ip), ip, C.POINTER(ip),
+                                      C.POINTER(dp), C.POINTER(mdwf_solver_opts), C.POINTER(vp), C.POINTER(ip)], ip),
         "mdwf_server_wait": ([vp, ip, C.POINTER(mdwf_solve_info), C.POINTER(dp)], ip),
         "mdwf_server_stats": ([vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(ip)], ip),
     }
@@ -241,11 +245,12 @@ def mdwf_apply_batch_dev(ctx, op, prec, nrhs, in_ptr, out_ptr, stride, mq=None, 
                                          int(stride), m, stream))
 
 
-def mdwf_solve_footprint(dims, L5, inner, nrhs, host_io=True):
-    """Device bytes a solve of nrhs RHS would allocate (no device needed)."""
+def mdwf_solve_footprint(dims, L5, inner, nrhs, host_io=1):
+    """Device bytes a solve of nrhs RHS would allocate (no device needed);
+    host_io 0 device fields, 1 host fields, 2 point sources / wall fields."""
     g = mdwf_geometry(*[int(d) for d in dims], 1)
     n = C.c_size_t()
-    st = lib.mdwf_solve_footprint(C.byref(g), int(L5), int(inner), int(nrhs), int(bool(host_io)), C.byref(n))
+    st = lib.mdwf_solve_footprint(C.byref(g), int(L5), int(inner), int(nrhs), int(host_io), C.byref(n))
     if st != MDWF_OK:
         raise MdwfError(st, "bad footprint arguments")
     return int(n.value)
@@ -304,6 +309,25 @@ def mdwf_solve_dev(ctx, b_ptrs, x_ptrs, mq=None, opts=None, stream=None):
     infos = (mdwf_solve_info * n)()
     o = _opts(opts)
     st = lib.mdwf_solve_dev(ctx, n, bp, xp, m, C.byref(o), infos, stream)
+    _check(ctx, st, allow=(MDWF_ERR_NOCONV, MDWF_ERR_NUMERIC))
+    return st, [i.as_dict() for i in infos]
+
+
+def mdwf_solve_point(ctx, site, cols, q_list, mq=None, opts=None):
+    """Point-source propagator solves: q_list[k] (host complex128 4D canonical
+    [T, Z, Y, X, 4, 3], written in place) receives the wall field of the
+    solution for spin-colour column cols[k]; returns (status, [info dicts])."""
+    n = len(cols)
+    for q in q_list:
+        if not (q.flags.c_contiguous and q.dtype == np.complex128):
+            raise ValueError("q must be C-contiguous complex128 arrays")
+    s = (C.c_int * 4)(*[int(v) for v in site])
+    cl = (C.c_int * n)(*[int(c) for c in cols])
+    qp = (C.c_void_p * n)(*[q.ctypes.data for q in q_list])
+    m = (C.c_double * n)(*mq) if mq is not None else None
+    infos = (mdwf_solve_info * n)()
+    o = _opts(opts)
+    st = lib.mdwf_solve_point(ctx, s, n, cl, m, C.byref(o), qp, infos)
     _check(ctx, st, allow=(MDWF_ERR_NOCONV, MDWF_ERR_NUMERIC))
     return st, [i.as_dict() for i in infos]
 
@@ -471,6 +495,26 @@ class Server:
         self._keep[rid.value] = (bs, list(x_list), bp, xp, m, n)
         return rid.value
 
+    def submit_point(self, field, M5, b5, c5, mq, L5, site, cols, q_list, masses=None, opts=None):
+        """Queue point-source propagator solves; q_list are host complex128 4D
+        canonical fields written in place (kept alive until wait)."""
+        n = len(cols)
+        for q in q_list:
+            if not (q.flags.c_contiguous and q.dtype == np.complex128):
+                raise ValueError("q must be C-contiguous complex128 arrays")
+        a = mdwf_action(float(M5), float(b5), float(c5), float(mq), int(L5))
+        s = (C.c_int * 4)(*[int(v) for v in site])
+        cl = (C.c_int * n)(*[int(c) for c in cols])
+        qp = (C.c_void_p * n)(*[q.ctypes.data for q in q_list])
+        m = (C.c_double * n)(*masses) if masses is not None else None
+        o = _opts(opts)
+        rid = C.c_int()
+        st = lib.mdwf_server_submit_point(self.h, int(field), C.byref(a), s, n, cl, m, C.byref(o), qp, C.byref(rid))
+        if st != MDWF_OK:
+            raise MdwfError(st, self._err())
+        self._keep[rid.value] = (list(q_list), qp, cl, s, m, n)
+        return rid.value
+
     def wait(self, rid):
         """(status, [info dicts], (queued s, running s, latency s))."""
         n = self._keep[rid][5]
@@ -497,7 +541,8 @@ def exported_symbols():
     """Names of the C entry points declared in include/mdwf.h."""
     return ["mdwf_create", "mdwf_destroy", "mdwf_last_error", "mdwf_load_gauge", "mdwf_load_gauge_dev",
             "mdwf_set_action", "mdwf_field_bytes", "mdwf_pack_dev", "mdwf_unpack_dev", "mdwf_apply",
-            "mdwf_apply_dev", "mdwf_apply_dev_noalloc", "mdwf_apply_batch_dev", "mdwf_solve_footprint", "mdwf_solve", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
+            "mdwf_apply_dev", "mdwf_apply_dev_noalloc", "mdwf_apply_batch_dev", "mdwf_solve_footprint", "mdwf_solve",
+            "mdwf_solve_point", "mdwf_server_submit_point", "mdwf_solve_dev", "mdwf_default_opts", "mdwf_op_model",
             "mdwf_autotune", "mdwf_autotune_solve", "mdwf_get_tune", "mdwf_set_tune", "mdwf_wilson_flow", "mdwf_wilson_flow_dev",
             "mdwf_plaquette_dev", "mdwf_gauss_smear_dev", "mdwf_wall_source_dev", "mdwf_project_4d_dev",
             "mdwf_mres_correlators_dev", "mdwf_pion_correlator_dev", "mdwf_server_create", "mdwf_server_destroy",

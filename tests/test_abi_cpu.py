@@ -142,10 +142,12 @@ def test_solve_footprint_counts_every_solver_vector():
         H = {0: a256(192 * Vh), 1: a256(96 * Vh), 2: a256(48 * Vh) + a256(4 * Vh)}
         for inner in (0, 1, 2):
             for n in (1, 3, 12):
-                for host_io in (False, True):
+                for host_io in (0, 1, 2):
                     mixed = inner != 0
                     per = 2 * H[0] + (5 * H[inner] + H[1] if mixed else 5 * H[0])
-                    shared = 6 * H[0] + (2 * Vh * 24 * 8 if host_io else 0)
+                    # staging: none, a 5D canonical field, a 4D canonical field
+                    stage = (0, 2 * Vh * 24 * 8, int(np.prod(dims)) * 24 * 8)[host_io]
+                    shared = 6 * H[0] + stage
                     want = per * n + shared + n * H[inner] + (64 << 20)
                     assert mdwf.mdwf_solve_footprint(dims, L5, inner, n, host_io) == want
     with pytest.raises(mdwf.MdwfError):
@@ -154,3 +156,5 @@ def test_solve_footprint_counts_every_solver_vector():
         mdwf.mdwf_solve_footprint((4, 4, 4, 4), 0, 0, 1)
     with pytest.raises(mdwf.MdwfError):
         mdwf.mdwf_solve_footprint((4, 4, 4, 4), 8, 0, 0)
+    with pytest.raises(mdwf.MdwfError):
+        mdwf.mdwf_solve_footprint((4, 4, 4, 4), 8, 0, 1, host_io=3)

@@ -21,8 +21,8 @@ class FakeServer:
         self.out = 0       # bytes of solutions submitted and not yet collected
         self.max_out = 0
 
-    def submit(self, field, M5, b5, c5, mq, L5, bs, xs, masses=None, opts=None):
-        assert len(bs) == len(xs) == len(masses)
+    def submit_point(self, field, M5, b5, c5, mq, L5, site, cols, xs, masses=None, opts=None):
+        assert len(cols) == len(xs) == len(masses) and cols == list(range(len(xs))) and len(site) == 4
         with self.lock:
             rid = self.next
             self.next += 1
@@ -51,28 +51,28 @@ class FakeServer:
         with self.lock:
             self.out -= nbytes
         lat = time.perf_counter() - t0
-        info = [dict(model_bytes=1e6, true_resid=1e-11, iters=10) for _ in range(n)]
+        info = [dict(model_bytes=1e6, true_resid=1e-11, iters=10, launch_rhs=n) for _ in range(n)]
         return 0, info, (0.0, lat, lat)
 
 
-def cols_for_test():
-    # field f: columns of 8 * (f + 1) complex numbers
-    return [[np.zeros(8 * (f + 1), complex) for _ in range(12)] for f in range(4)]
+SITES = [(0, 0, 0, 0)] * 4
+# field f: outputs of 8 * (f + 1) complex numbers
+QSHAPES = [(8 * (f + 1),) for f in range(4)]
 
 
 def test_serving_driver_collects_every_request_within_the_host_cap():
     rng = np.random.default_rng(1)
     reqs = bench.serve_requests(10, rng)
     assert all(1 <= k <= bench.SERVE_MAX_RHS[f] and len(m) == k for f, k, m in reqs)
-    cols = cols_for_test()
-    biggest = max(k * cols[f][0].nbytes for f, k, _ in reqs)
+    biggest = max(k * 16 * QSHAPES[f][0] for f, k, _ in reqs)
     cap = biggest  # at most one of the largest requests' solutions outstanding
     srv = FakeServer()
-    recs, wall = bench.run_phase(None, srv, [0, 1, 2, 3], cols, reqs, [0.0] * len(reqs), {}, cap)
+    recs, wall = bench.run_phase(None, srv, [0, 1, 2, 3], SITES, QSHAPES, reqs, [0.0] * len(reqs), {}, cap)
     assert wall > 0 and all(r is not None for r in recs)
     assert all(len(r["digest"]) == k for r, (_, k, _) in zip(recs, reqs))
     s = bench.phase_summary(reqs, recs, wall)
     assert s["requests"] == 10 and s["all_ok"] and s["rhs"] == sum(k for _, k, _ in reqs)
+    assert s["shared_requests"] == 0 and s["mean_launch_rhs"] >= 1
     assert not srv.jobs and srv.max_out <= cap
 
 
@@ -80,11 +80,11 @@ def test_serving_driver_one_at_a_time_never_overlaps():
     rng = np.random.default_rng(2)
     reqs = bench.serve_requests(6, rng)
     srv = FakeServer()
-    recs, _ = bench.run_phase(None, srv, [0, 1, 2, 3], cols_for_test(), reqs, [0.0] * 6, {}, 1 << 40,
+    recs, _ = bench.run_phase(None, srv, [0, 1, 2, 3], SITES, QSHAPES, reqs, [0.0] * 6, {}, 1 << 40,
                               serial=True)
     assert srv.max_active == 1 and len(recs) == 6
     srv2 = FakeServer(solve_s=0.05)
-    bench.run_phase(None, srv2, [0, 1, 2, 3], cols_for_test(), reqs, [0.0] * 6, {}, 1 << 40)
+    bench.run_phase(None, srv2, [0, 1, 2, 3], SITES, QSHAPES, reqs, [0.0] * 6, {}, 1 << 40)
     assert srv2.max_active > 1
 
 
