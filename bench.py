@@ -1076,8 +1076,8 @@ def main():
     if not args.no_tune:
         tune = M.mdwf_autotune(ctx)
         for pn, t in zip(("f64", "f32", "f16"), tune):
-            log("autotune %s: tile %s xcd_remap %d nt_store %d link_mode %d  schur %.1f us" %
-                (pn, t["tile"], t["xcd_remap"], t["nt_store"], t["link_mode"], t["us"]))
+            log("autotune %s: tile %s xcd_remap %d nt_store %d link_mode %d plane_bt %d  schur %.1f us" %
+                (pn, t["tile"], t["xcd_remap"], t["nt_store"], t["link_mode"], t["plane_bt"], t["us"]))
 
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

@@ -328,16 +328,19 @@ typedef struct {
                         a 4x4x4 spatial block and its faces into LDS once and
                         marches plane_bt planes along t (spatial extents
                         multiples of 4, L5 <= 16, else the lane-per-site
-                        kernel runs); 0 = off */
+                        kernel runs); 0 = off.  mdwf_autotune sets it for
+                        FP32 / FP16 when it times faster on one bare hop. */
 } mdwf_launch_tune;
 
 /* Autotuner: for each precision (index mdwf_prec), time one Schur operator
  * application (the two fused hop kernels) on scratch fields, choosing in turn
  * the traversal tile (z-blocks and compact 4D tiles), the link mode, then
  * non-temporal stores and workgroup numbering, and keep the fastest in the
- * context.  out[3] (may be NULL) receives the chosen shapes.  Needs the
- * action and gauge field; allocates scratch device memory (three half fields
- * of each precision). */
+ * context; for FP32 and FP16 it then times one bare hop with the lane-per-site
+ * kernel and with plane_bt 4, 8, 16 (those dividing T) and keeps a plane run
+ * that is at least 2 % faster.  out[3] (may be NULL) receives the chosen
+ * shapes.  Needs the action and gauge field; allocates scratch device memory
+ * (three half fields of each precision). */
 mdwf_status mdwf_autotune(mdwf_ctx *ctx, mdwf_launch_tune *out);
 
 /* Autotuner for the launches of one solve shape: the inner precision

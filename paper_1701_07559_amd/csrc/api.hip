@@ -740,6 +740,8 @@ namespace {
 // `with_dag`): traversal tile (z-blocks and compact 4D tiles), link mode,
 // non-temporal stores and workgroup numbering, then (nrhs > 1) the RHS
 // grouping.  Each candidate: 2 warm-up applications, the mean of 5 timed.
+// For one RHS without the adjoint (the operator tuning), FP32 and FP16 also
+// choose the kernel of the bare hop (lane-per-site or plane-staged).
 mdwf_status tune_precision(mdwf_ctx* c, Prec p, int form, int nrhs, bool with_dag, const double* cin,
                            hipEvent_t e0, hipEvent_t e1, mdwf_launch_tune* out) {
     Geo& g = c->geo;
@@ -806,6 +808,7 @@ mdwf_status tune_precision(mdwf_ctx* c, Prec p, int form, int nrhs, bool with_da
     for (int k = 0; k < 4; ++k) best.tile[k] = g.trav[p].b[k];
     best.xcd_remap = 1;
     best.rhs_group = g.rhs_group[p];
+    best.plane_bt = g.plane_bt[p];   // bare hops only: kept unless chosen below
     best.us = 1e30;
     for (const auto& tl : tiles) {
         mdwf_launch_tune tn = best;
@@ -842,6 +845,34 @@ mdwf_status tune_precision(mdwf_ctx* c, Prec p, int form, int nrhs, bool with_da
             if (tn.us < best.us) best = tn;
         }
     set_tune(g, p, best);
+    // The bare hops (MDWF_OP_HOP_*) can also run plane-staged: keep the
+    // plane run that times fastest on one bare hop (0 = the lane kernel).
+    // Only the single-RHS operator tuning does this: the solver launches no
+    // bare hop.
+    if (p != P64 && nrhs == 1 && !with_dag) {
+        HopLaunch L{};
+        L.kind = HOP_BARE; L.prec = p; L.out_parity = 0; L.out = b; L.in = a; L.centre = nullptr;
+        L.stride = hb; L.nrhs = 1; L.coef = cf; L.active = nullptr; L.partials = nullptr;
+        float best_ms = 1e30f;
+        int best_bt = 0;
+        for (int bt : {0, 4, 8, 16}) {
+            if (bt && g.T % bt) continue;
+            mdwf_launch_tune tn = best;
+            tn.plane_bt = bt;
+            set_tune(g, p, tn);
+            const int warm = 2, reps = 10;
+            for (int r = 0; r < warm; ++r) launch_hop(g, c->gs, L, st);
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps; ++r) launch_hop(g, c->gs, L, st);
+            (void)hipEventRecord(e1, st);
+            if ((s = hip_check(c, hipEventSynchronize(e1), "autotune bare hop"))) return s;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (bt == 0 ? ms < best_ms : ms < 0.98f * best_ms) best_ms = ms, best_bt = bt;   // a clear win only
+        }
+        best.plane_bt = best_bt;
+        set_tune(g, p, best);
+    }
     c->tuned_us[p] = best.us;
     if (out) *out = best;
     return MDWF_OK;

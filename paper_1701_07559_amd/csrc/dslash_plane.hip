@@ -356,6 +356,259 @@ __global__ void __launch_bounds__(kPlaneMaxThreads) k_hop_plane(const Geo g, con
     }
 }
 
+// ------------------------------------------------ register-buffered variant
+// FP32 with L5 = 8: the same 4x4x4 blocks and plane march, but the copies of
+// the next plane go to registers while the current plane is computed from
+// LDS, and are written to LDS between two barriers at the end of the step.
+// So their latency hides behind a whole plane of arithmetic instead of
+// stalling the workgroup, in the same 80.5 KB of LDS (two workgroups per CU).
+// Each thread owns fixed staging elements: the 16-byte spinor units
+// c * 256 + tid (c < 15; a unit is (slot, block, slice), slice fastest) and
+// the link id tid (four 16-byte parts and the 8-byte tail).  The step loop
+// is unrolled by three so that the three planes' accumulators change roles
+// without copies.
+constexpr int kRbThreads = 256;                                   // 32 sites x 8 slices
+constexpr int kRbUnits = kPlaneSlots * 6 * 8 / kRbThreads;        // 15 spinor units per thread
+constexpr int kRbSlotBytes = 6 * 8 * 16;                          // one staged site, all slices
+constexpr int kRbLinkOff = kPlaneSlots * kRbSlotBytes;            // 61440
+constexpr int kRbTailOff = kRbLinkOff + 4 * kPlaneLinks * 16;     // link parts [4][256]
+constexpr int kRbTabOff = kRbTailOff + kPlaneLinks * 8;           // link tails [256] float2
+constexpr int kRbLdsBytes = kRbTabOff + 2 * kPlaneSlots * 4;      // slot table [2][80]
+static_assert(kRbUnits * kRbThreads == kPlaneSlots * 6 * 8, "whole units per thread");
+
+// The staged spinor of a slot (layout [block][slice] of 16-byte units) at
+// slice s, and one hop term of it with a staged link id.
+// Block k of an odd slot sits at position k ^ 1, so that the 128-byte rows
+// read together by neighbouring site groups fall in different LDS bank
+// halves.
+__device__ __forceinline__ void rb_spinor(const unsigned char* sp, int slot, int s, cx<float> psi[12]) {
+    const int b = (slot & 1) * 128;
+    const unsigned char* base = sp + slot * kRbSlotBytes + s * 16;
+    const nf4* qe = reinterpret_cast<const nf4*>(base + b);   // even k
+    const nf4* qo = reinterpret_cast<const nf4*>(base - b);   // odd k
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const nf4 w = (k & 1) ? qo[k * 8] : qe[k * 8];
+        psi[2 * k] = {w.x, w.y};
+        psi[2 * k + 1] = {w.z, w.w};
+    }
+}
+template <bool DAG, int MU, int DIR>
+__device__ __forceinline__ void rb_term(cx<float> acc[12], const cx<float> psi[12], const unsigned char* lk,
+                                        int lid) {
+    cx<float> U[9];
+    const nf4* l = reinterpret_cast<const nf4*>(lk) + lid;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const nf4 w = l[k * kPlaneLinks];
+        U[2 * k] = {w.x, w.y};
+        U[2 * k + 1] = {w.z, w.w};
+    }
+    const nf2 tl = reinterpret_cast<const nf2*>(lk + 4 * kPlaneLinks * 16)[lid];
+    U[8] = {tl.x, tl.y};
+    constexpr float sg = ((DIR > 0) != DAG) ? 1.f : -1.f;
+    cx<float> h[6], w[6];
+    project<MU>(sg, psi, h);
+    su3_mul<(DIR > 0)>(U, h, w);
+    reconstruct_add<MU>(sg, w, acc);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kRbThreads, 2) k_hop_plane_rb(const Geo g, const HopDev a, const PlaneDev pd) {
+    constexpr bool DAG = HopTraits<K>::dag;
+    extern __shared__ __align__(16) unsigned char plane_lds[];
+    unsigned char* const sp = plane_lds;
+    unsigned char* const lk = plane_lds + kRbLinkOff;
+    int* const tab = reinterpret_cast<int*>(plane_lds + kRbTabOff);
+
+    // workgroup -> right-hand side (fastest), block, t-run
+    const int lb = g.xcd_remap[P32] ? xcd_logical_block(blockIdx.x, gridDim.x) : int(blockIdx.x);
+    const int rhs = lb % a.nrhs;
+    int rest = lb / a.nrhs;
+    const int bx = rest % pd.nbx;
+    rest /= pd.nbx;
+    const int by = rest % pd.nby;
+    rest /= pd.nby;
+    const int bz = rest % pd.nbz;
+    const int btr = rest / pd.nbz;
+    if (a.active && !a.active[rhs]) return;   // uniform over the workgroup
+    const int x0 = 4 * bx, y0 = 4 * by, z0 = 4 * bz;
+    const int t0 = btr * pd.bt, t1 = t0 + pd.bt;
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int s = lane & 7;
+    const int kk = (wave << 3) + (lane >> 3);   // output site of the plane
+    const int kx = kk & 1, ky = (kk >> 1) & 3, kz = kk >> 3;
+    const int p = a.out_parity, ip = 1 - p;
+    const char* src = static_cast<const char*>(at_rhs(a.in, a.stride, rhs));
+    char* dst = static_cast<char*>(at_rhs(a.out, a.stride, rhs));
+    const size_t sblk = size_t(g.Vh) * 16;
+    const size_t lblk = size_t(g.Vh4) * 16;
+    const uint32_t plane_sites = uint32_t(g.Xh * g.Y * g.Z);
+    auto wrapT = [&](int t) { return t < 0 ? t + g.T : (t >= g.T ? t - g.T : t); };
+    auto gidx = [&](int lx, int ly, int lz, int t) -> uint32_t {
+        int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        gx = gx < 0 ? gx + g.X : (gx >= g.X ? gx - g.X : gx);
+        gy = gy < 0 ? gy + g.Y : (gy >= g.Y ? gy - g.Y : gy);
+        gz = gz < 0 ? gz + g.Z : (gz >= g.Z ? gz - g.Z : gz);
+        return uint32_t((gx >> 1) + g.Xh * (gy + g.Y * (gz + g.Z * t)));
+    };
+
+    // spatial part of the parity-compressed index of every slot, both classes
+    for (int e = tid; e < 2 * kPlaneSlots; e += kRbThreads) {
+        int lx, ly, lz;
+        slot_position(e % kPlaneSlots, e / kPlaneSlots, lx, ly, lz);
+        tab[e] = int(gidx(lx, ly, lz, 0));
+    }
+
+    // this thread's spinor units: unit c*256 + tid is slot uslot[c % 3] +
+    // 16 (c / 3), block and slice from ubase[c % 3] and usl[c % 3] (768
+    // units = 16 slots, so the parity of the slot depends on c % 3 only)
+    int uslot[3], usl[3], uswz[3];
+    const char* ubase[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int u = c * kRbThreads + tid;
+        uslot[c] = u / 48;
+        const int r = u - 48 * uslot[c];
+        ubase[c] = src + size_t(r >> 3) * sblk;
+        usl[c] = r & 7;
+        // LDS position of the unit: block (r >> 3) ^ 1 in odd slots (see rb_spinor)
+        uswz[c] = (uslot[c] & 1) ? (((r >> 3) & 1) ? -8 : 8) : 0;
+    }
+    // this thread's link id: set lset (0/1 x fwd/bwd, 2/3 y, 4/5 z, 6 t fwd at
+    // the output site of plane t-1, 7 t bwd at the input site of plane t),
+    // site lw of the set
+    const int lset = tid >> 5, lw = tid & 31;
+    const int lwy = (lw >> 1) & 3, lwz = lw >> 3, lmu = lset >> 1;
+    const bool lfwd = (lset & 1) == 0;
+    const char* lseg = (lfwd ? a.links_out : a.links_in) + size_t(lmu) * a.lseg;
+
+    nf4 pre[kRbUnits], lpre[4];
+    nf2 ltail;
+    // kind of a staged plane: 0 the plane before the run (t- hops of its
+    // first plane), 1 inside the run, 2 the plane after it (t+ hops of its
+    // last plane); the edge planes need the 32 inner slots and one link set
+    auto prefetch = [&](int t, int kind) {
+        const int cls = (ip + t) & 1;
+        const uint32_t tofs = plane_sites * uint32_t(t);
+        const int* ctab = tab + cls * kPlaneSlots;
+#pragma unroll
+        for (int c = 0; c < kRbUnits; ++c) {
+            if (kind != 1 && c >= 6) break;   // units below 1536: the 32 inner slots
+            const int slot = uslot[c % 3] + 16 * (c / 3);
+            const uint32_t j = (uint32_t(ctab[slot]) + tofs) * 8u + uint32_t(usl[c % 3]);
+            pre[c] = ldu<nf4>(ubase[c % 3], j * 16u);
+        }
+        if (kind == 1 || wave == 3) {   // wave 3 holds sets 6 and 7
+            int lx, ly = lwy, lz = lwz, tl = t;
+            if (lset < 6) {
+                lx = 2 * (lw & 1) + ((p + t + lwy + lwz) & 1);   // output site lw of plane t
+                if (!lfwd) {
+                    if (lmu == 0) lx -= 1;
+                    else if (lmu == 1) ly -= 1;
+                    else lz -= 1;
+                }
+            } else {
+                lx = 2 * (lw & 1) + ((cls + lwy + lwz) & 1);      // input slot lw of plane t
+                if (lfwd) tl = t == 0 ? g.T - 1 : t - 1;
+            }
+            const uint32_t li = gidx(lx, ly, lz, tl);
+            // each link is read once per hop: streamed past the caches when
+            // the launch shape asks for non-temporal accesses
+            if (g.nt_store[P32]) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    lpre[e] = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(lseg + e * lblk + size_t(li) * 16));
+                ltail = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(lseg + 4 * lblk + size_t(li) * 8));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) lpre[e] = ldu<nf4>(lseg + e * lblk, li * 16u);
+                ltail = ldu<nf2>(lseg + 4 * lblk, li * 8u);
+            }
+        }
+    };
+    auto commit = [&](int kind) {
+#pragma unroll
+        for (int c = 0; c < kRbUnits; ++c) {
+            if (kind != 1 && c >= 6) break;
+            reinterpret_cast<nf4*>(sp)[c * kRbThreads + tid + uswz[c % 3]] = pre[c];
+        }
+        if (kind == 1 || wave == 3) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) reinterpret_cast<nf4*>(lk)[e * kPlaneLinks + tid] = lpre[e];
+            reinterpret_cast<nf2*>(lk + 4 * kPlaneLinks * 16)[tid] = ltail;
+        }
+    };
+    auto kind_of = [&](int tp) { return tp < t0 ? 0 : (tp >= t1 ? 2 : 1); };
+    auto store = [&](const cx<float> acc[12], int tpl) {
+        const int lx = 2 * kx + ((p + tpl + ky + kz) & 1);
+        const int j = int(gidx(lx, ky, kz, tpl)) * 8 + s;
+        if (g.nt_store[P32]) Field<P32>::store<true>(dst, g.Vh, j, acc);
+        else Field<P32>::store(dst, g.Vh, j, acc);
+    };
+
+    __syncthreads();   // slot table written
+    prefetch(wrapT(t0 - 1), 0);
+    commit(0);
+    __syncthreads();
+
+    cx<float> A[12], B[12], C[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) A[c] = B[c] = C[c] = {-0.f, -0.f};
+
+    // One step: plane tp is in LDS and the copies of plane tp + 1 are issued
+    // first.  The inner slot at the thread's site gives the t+ term of plane
+    // tp - 1 (PR, then stored and cleared) and the t- term of plane tp + 1
+    // (NX); CU, plane tp, takes the six spatial terms.
+#define MDWF_RB_STEP(i, PR, CU, NX)                                                                     \
+    {                                                                                                   \
+        const int tp = t0 - 1 + (i);                                                                    \
+        const int t = wrapT(tp);                                                                        \
+        const int kind = kind_of(tp);                                                                   \
+        if (tp + 1 <= t1) prefetch(wrapT(tp + 1), kind_of(tp + 1));                                     \
+        if (tp - 1 >= t0 || tp + 1 < t1) {                                                              \
+            cx<float> psi[12];                                                                          \
+            rb_spinor(sp, kk, s, psi);                                                                  \
+            if (tp - 1 >= t0) {                                                                         \
+                rb_term<DAG, 3, +1>(PR, psi, lk, 6 * 32 + kk);                                          \
+                store(PR, wrapT(tp - 1));                                                               \
+            }                                                                                           \
+            if (tp + 1 < t1) rb_term<DAG, 3, -1>(NX, psi, lk, 7 * 32 + kk);                             \
+        }                                                                                               \
+        _Pragma("unroll") for (int c = 0; c < 12; ++c) PR[c] = {-0.f, -0.f};                            \
+        if (kind == 1) {                                                                                \
+            const int lx = 2 * kx + ((p + t + ky + kz) & 1);                                            \
+            const int sxp = lx < 3 ? inner_slot(lx + 1, ky, kz) : 40 + 2 * kz + (ky >> 1);              \
+            const int sxm = lx > 0 ? inner_slot(lx - 1, ky, kz) : 32 + 2 * kz + (ky >> 1);              \
+            const int syp = ky < 3 ? inner_slot(lx, ky + 1, kz) : 56 + 2 * kz + (lx >> 1);              \
+            const int sym = ky > 0 ? inner_slot(lx, ky - 1, kz) : 48 + 2 * kz + (lx >> 1);              \
+            const int szp = kz < 3 ? inner_slot(lx, ky, kz + 1) : 72 + 2 * ky + (lx >> 1);              \
+            const int szm = kz > 0 ? inner_slot(lx, ky, kz - 1) : 64 + 2 * ky + (lx >> 1);              \
+            cx<float> psi[12];                                                                          \
+            rb_spinor(sp, sxp, s, psi); rb_term<DAG, 0, +1>(CU, psi, lk, 0 * 32 + kk);                  \
+            rb_spinor(sp, sxm, s, psi); rb_term<DAG, 0, -1>(CU, psi, lk, 1 * 32 + kk);                  \
+            rb_spinor(sp, syp, s, psi); rb_term<DAG, 1, +1>(CU, psi, lk, 2 * 32 + kk);                  \
+            rb_spinor(sp, sym, s, psi); rb_term<DAG, 1, -1>(CU, psi, lk, 3 * 32 + kk);                  \
+            rb_spinor(sp, szp, s, psi); rb_term<DAG, 2, +1>(CU, psi, lk, 4 * 32 + kk);                  \
+            rb_spinor(sp, szm, s, psi); rb_term<DAG, 2, -1>(CU, psi, lk, 5 * 32 + kk);                  \
+        }                                                                                               \
+        __syncthreads();   /* every wave is done with plane tp */                                       \
+        if (tp + 1 <= t1) commit(kind_of(tp + 1));                                                      \
+        __syncthreads();                                                                                \
+    }
+    const int nsteps = pd.bt + 2;
+    for (int i = 0; i < nsteps; i += 3) {
+        MDWF_RB_STEP(i, A, B, C)
+        if (i + 1 >= nsteps) break;
+        MDWF_RB_STEP(i + 1, B, C, A)
+        if (i + 2 >= nsteps) break;
+        MDWF_RB_STEP(i + 2, C, A, B)
+    }
+#undef MDWF_RB_STEP
+}
+
 // Dynamic LDS the plane kernels may take: a CU's whole LDS.
 size_t plane_lds_limit() {
     static size_t limit = [] {
@@ -381,6 +634,18 @@ static void launch_plane_k(const dim3& grid, int nthreads, size_t lds, hipStream
     }();
     (void)attr;
     hipLaunchKernelGGL((k_hop_plane<P, K>), grid, dim3(nthreads), lds, st, g, a, pd);
+}
+
+template <int K>
+static void launch_plane_rb(const dim3& grid, hipStream_t st, const Geo& g, const HopDev& a, const PlaneDev& pd) {
+    static const bool attr = [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hop_plane_rb<K>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kRbLdsBytes);
+        (void)hipGetLastError();
+        return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL((k_hop_plane_rb<K>), grid, dim3(kRbThreads), kRbLdsBytes, st, g, a, pd);
 }
 
 // The plane-staged kernel applies when the launch shape asks for it, the
@@ -421,6 +686,11 @@ static bool launch_plane_p(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipSt
         a.nblk = pd.nbx * pd.nby * pd.nbz * pd.nbt;
         L.nblocks_per_rhs = a.nblk;
         const dim3 grid(a.nblk * L.nrhs);
+        if (P == P32 && g.L5 == 8 && size_t(kRbLdsBytes) <= plane_lds_limit()) {   // register-buffered variant
+            if (L.kind == HOP_BARE) launch_plane_rb<HOP_BARE>(grid, st, g, a, pd);
+            else launch_plane_rb<HOP_BARE_DAG>(grid, st, g, a, pd);
+            return true;
+        }
         if (L.kind == HOP_BARE) launch_plane_k<P, HOP_BARE>(grid, nthreads, lds, st, g, a, pd);
         else launch_plane_k<P, HOP_BARE_DAG>(grid, nthreads, lds, st, g, a, pd);
         return true;
