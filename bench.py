@@ -233,10 +233,38 @@ def hop_launch_bytes(inner, Vh, nr):
 # What the counters show limits the hop kernels below the HBM roofline
 # (rocprofv3 summaries under profiles/).
 LIMITER = {
-    "f16": "vector-ALU issue: 82-90% VALU busy in the 12-RHS FP16 hop kernels (profiles/hop_valu_busy_24c64_L8.md)",
-    "f32": "neighbour gather through the texture path (profiles/hop_f32_24c64_L8_counters.md)",
-    "f64": "neighbour gather through the texture path (profiles/hop_f32_24c64_L8_counters.md)",
+    "f16": "co-limited: 82-90% VALU busy (profiles/hop_valu_busy_24c64_L8.md) while moving 6.3-6.6 TB/s to and "
+           "from memory beyond L2, 2.2x the algorithmic bytes (profiles/schur_rp_f16_24c64_L8_12rhs_counters.md); "
+           "13% fewer VALU instructions in kernel A did not make it faster",
+    "f32": "re-reads of the input field beyond L2 (2.26x) at a rate near the streaming limit "
+           "(profiles/hop_f32_plane_24c64_L8_counters.md)",
+    "f64": "re-reads of the input field beyond L2 (profiles/hop_f32_24c64_L8_counters.md)",
 }
+
+# Vector-ALU roofline of the FP16-storage hop kernels, which the counters show
+# issue-bound.  Per 5D site and RHS the model flops of kernel A / B of the
+# CG operator are 1320 + 48 L5 (+ 48 for B's combination).  The fewest gfx950
+# VALU instructions that execute them, without packed FP32: the eight SU(3)
+# products (8 x 132 flops) as v_dot2_f32_f16 at 4 flops per lane, the eight
+# projections (8 x 12) as packed-half adds at 2, the sum over directions
+# (168) as FP32 adds at 1, the dense fifth-dimension polynomial (48 L5) and
+# B's combination (48) as FP32 FMAs at 2.  One VALU instruction per lane and
+# cycle on 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz then gives the peak flop
+# rate of this instruction mix.
+VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
+
+
+def alu_peak_tflops(l5):
+    flops = (1320 + 48 * l5) + (1320 + 48 * l5 + 48)
+    instr = 2 * (1056 / 4 + 96 / 2 + 168) + 2 * (48 * l5 / 2) + 48 / 2
+    return flops / instr * VALU_LANE_RATE / 1e12
+
+
+def hop_launch_flops(Vh, nr, form):
+    """Model flops of one batched launch of kernel A and of kernel B."""
+    a = 1320 + 48 * L5 + (72 if form != "rp" else 0)
+    b = 1320 + 48 * L5 + 48 if form == "rp" else 1320 + 72 + 48
+    return [Vh * nr * a, Vh * nr * b]
 
 
 def roofline(info, inner, Vh, form):
@@ -249,23 +277,34 @@ def roofline(info, inner, Vh, form):
     by = hop_launch_bytes(inner, Vh, nr)
     ach = (by[0] + by[1]) / ((us[0] + us[1]) * 1e-6) / 1e9
     names = ("A", "B", "A_dag", "B_dag")
-    return dict(bound="hbm",
-                kernel="%s Schur operator: k_hop<%s, %d> (kernel A) + k_hop<%s, %d> (kernel B), %d RHS per "
-                       "launch, mean of %d sampled CG iterations" %
-                       (FORM_NAMES[form], inner.upper(), FORM_KINDS[form][0], inner.upper(), FORM_KINDS[form][1],
-                        nr, info["hop_samples"]),
-                achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
-                traffic=None,
-                limiter=LIMITER.get(inner),
-                launches={n: dict(us=round(u, 1), algorithmic_bytes=int(b), GBps=round(b / (u * 1e-6) / 1e9, 1))
-                          for n, u, b in zip(names, us, by)})
+    kernel = ("%s Schur operator: k_hop<%s, %d> (kernel A) + k_hop<%s, %d> (kernel B), %d RHS per "
+              "launch, mean of %d sampled CG iterations" %
+              (FORM_NAMES[form], inner.upper(), FORM_KINDS[form][0], inner.upper(), FORM_KINDS[form][1],
+               nr, info["hop_samples"]))
+    launches = {n: dict(us=round(u, 1), algorithmic_bytes=int(b), GBps=round(b / (u * 1e-6) / 1e9, 1))
+                for n, u, b in zip(names, us, by)}
+    hbm = dict(achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4))
+    if inner == "f16" and form == "rp":
+        # issue-bound (VALU busy 82-90 %): priced against the vector ALUs,
+        # the HBM fraction kept beside it
+        fl = hop_launch_flops(Vh, nr, form)
+        tf = (fl[0] + fl[1]) / ((us[0] + us[1]) * 1e-6) / 1e12
+        pk = alu_peak_tflops(L5)
+        return dict(bound="alu", kernel=kernel, achieved=round(tf, 2), peak=round(pk, 1), unit="TFLOP/s",
+                    frac=round(tf / pk, 4),
+                    peak_derivation="model flops of kernels A+B over the fewest VALU instructions that execute "
+                                    "them (SU(3) products as v_dot2_f32_f16, FP32 sums, packed-half projections), "
+                                    "one VALU instruction per lane and cycle, 256 CUs x 64 lanes x 2.4 GHz",
+                    frac_of_fp32_vector_peak=round(tf / 157.3, 4),
+                    traffic=None, hbm=hbm, limiter=LIMITER.get(inner), launches=launches)
+    return dict(bound="hbm", kernel=kernel, traffic=None, limiter=LIMITER.get(inner), launches=launches, **hbm)
 
 
 _PKG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1701_07559_amd")
 # what decides the hop kernels' machine code: their source, the shared
 # device header and the compiler flags
 KERNEL_SRC = os.path.join(_PKG, "csrc", "dslash.hip")
-KERNEL_DEPS = [KERNEL_SRC, os.path.join(_PKG, "csrc", "mdwf_internal.h")]
+KERNEL_DEPS = [KERNEL_SRC, os.path.join(_PKG, "csrc", "hop_device.h"), os.path.join(_PKG, "csrc", "mdwf_internal.h")]
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "schur_rp_f16_24c64_L8_12rhs_counters.md")
 # hop kinds (HopKind) of kernels A, B, A^+, B^+ of each CG operator
@@ -1310,7 +1349,7 @@ def main():
         "fp64_cg": fp64,
         "mixed_solve": other,
         "speedup_mixed_multirhs_vs_fp64": (round(fp64["seconds_all_columns"] / t_step, 3) if fp64 else None),
-        "dslash_GBps": roof["achieved"] if roof else None,
+        "dslash_GBps": ((roof["hbm"] if "hbm" in roof else roof)["achieved"]) if roof else None,
         "dslash": {k: dict(ms=round(v["ms"], 4), GBps=round(v["GBps"], 1), frac=round(v["GBps"] / HBM_PEAK_GBS, 4),
                            GFLOPs=round(v["GFLOPs"], 1)) for k, v in micro.items()},
         "roofline": roof,
