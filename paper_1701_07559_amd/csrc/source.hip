@@ -129,10 +129,18 @@ struct SmearIdx {
 
 // WAVE: one wavefront per site (nvec <= 16; lanes 4 nvec .. 63 idle), so the
 // site and its links are wave-uniform and the links come by scalar loads.
+// in / out are addressed as base + vector * vs + site * ss (complex units):
+// the canonical layout has vs = 12 * sites, ss = 12; the site-major layout
+// the steps between the first and the last use has vs = 12, ss = 12 * nvec,
+// so a wave's neighbour reads of all vectors are one contiguous run.
+struct SmearLayout {
+    size_t in_vs, in_ss, out_vs, out_ss;
+};
+
 template <bool WAVE>
 __global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const SmearIdx ix, const double2* U,
                                                           const double2* in, double2* out, double kappa,
-                                                          uint32_t nsites, uint32_t ntot) {
+                                                          uint32_t nsites, uint32_t ntot, const SmearLayout lay) {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t i, r;
     if constexpr (WAVE) {
@@ -148,7 +156,7 @@ __global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const 
     const uint32_t q1 = ix.fX.div(i), x = i - q1 * g.X;
     const uint32_t q2 = ix.fY.div(q1), y = q1 - q2 * g.Y;
     const uint32_t t = ix.fZ.div(q2), z = q2 - t * g.Z;
-    const double2* f = in + size_t(v) * nsites * 12 + sp * 3;
+    const double2* f = in + size_t(v) * lay.in_vs + sp * 3;
     const uint32_t sy = g.X, sz = uint32_t(g.X) * g.Y;
     cx<double> acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}}, u[9], nb[3], w[3];
 #pragma unroll 1
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const 
         for (int dir = 0; dir < 2; ++dir) {
             const uint32_t xn = dir == 0 ? xp : xm;
             ld_link_op(U, dir == 0 ? i : xn, mu, dir != 0, u);
-            const double2* p = f + size_t(xn) * 12;
+            const double2* p = f + size_t(xn) * lay.in_ss;
 #pragma unroll
             for (int b = 0; b < 3; ++b) nb[b] = {p[b].x, p[b].y};
             link_times(u, nb, w, 1);
@@ -170,8 +178,8 @@ __global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const 
             for (int a = 0; a < 3; ++a) acc[a] = acc[a] + w[a];
         }
     }
-    const double2* p = f + size_t(i) * 12;
-    double2* o = out + size_t(v) * nsites * 12 + size_t(i) * 12 + sp * 3;
+    const double2* p = f + size_t(i) * lay.in_ss;
+    double2* o = out + size_t(v) * lay.out_vs + size_t(i) * lay.out_ss + sp * 3;
     const double cc = 1.0 - 6.0 * kappa;
 #pragma unroll
     for (int a = 0; a < 3; ++a) o[a] = make_double2(fma(cc, p[a].x, kappa * acc[a].re), fma(cc, p[a].y, kappa * acc[a].im));
@@ -434,14 +442,22 @@ mdwf_status mdwf_gauss_smear_dev(const mdwf_geometry* geom, const double* U_dev,
     const auto* U = reinterpret_cast<const double2*>(U_dev);
     const double2* src = reinterpret_cast<const double2*>(in_dev);
     double2* out = reinterpret_cast<double2*>(out_dev);
+    // the steps between the first and the last keep the fields site-major
+    // (all vectors of a site contiguous) when a wavefront holds one site;
+    // the last step lands in out, canonical
+    const size_t canon_vs = size_t(nsites) * 12, site_ss = size_t(nvec) * 12;
     for (int k = 1; k <= niter && !s; ++k) {
-        double2* dst = ((niter - k) % 2 == 0) ? out : tmp;   // the last step lands in out
-        if (wave)
+        double2* dst = ((niter - k) % 2 == 0) ? out : tmp;
+        SmearLayout lay{canon_vs, 12, canon_vs, 12};
+        if (wave) {
+            if (k > 1) lay.in_vs = 12, lay.in_ss = site_ss;
+            if (k < niter) lay.out_vs = 12, lay.out_ss = site_ss;
             hipLaunchKernelGGL(k_gauss_step<true>, dim3(blocks_for(nthr)), dim3(kSrcBlock), 0, st, g, ix, U, src, dst,
-                               kappa, uint32_t(nsites), nthr);
-        else
+                               kappa, uint32_t(nsites), nthr, lay);
+        } else {
             hipLaunchKernelGGL(k_gauss_step<false>, dim3(blocks_for(nthr)), dim3(kSrcBlock), 0, st, g, ix, U, src,
-                               dst, kappa, uint32_t(nsites), nthr);
+                               dst, kappa, uint32_t(nsites), nthr, lay);
+        }
         s = hip_check(nullptr, hipGetLastError(), "smearing kernel");
         src = dst;
     }
