@@ -141,13 +141,20 @@ template <bool NT, typename V> __device__ __forceinline__ void st16(V* p, V v) {
 
 template <Prec P> struct Field;
 
+// 16-byte load, optionally non-temporal (streamed past the caches)
+template <bool NT, typename V> __device__ __forceinline__ V ld16(const V* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
 template <> struct Field<P64> {
     using R = double;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const void* base, int Vh, int j, cx<R> v[12]) {
-        const double2* p = static_cast<const double2*>(base);
+        const nd2* p = static_cast<const nd2*>(base);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            double2 w = p[size_t(k) * Vh + j];
+            const nd2 w = ld16<NT>(p + size_t(k) * Vh + j);
             v[k] = {w.x, w.y};
         }
     }
@@ -161,11 +168,12 @@ template <> struct Field<P64> {
 
 template <> struct Field<P32> {
     using R = float;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const void* base, int Vh, int j, cx<R> v[12]) {
-        const float4* p = static_cast<const float4*>(base);
+        const nf4* p = static_cast<const nf4*>(base);
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            float4 w = p[size_t(k) * Vh + j];
+            const nf4 w = ld16<NT>(p + size_t(k) * Vh + j);
             v[2 * k] = {w.x, w.y};
             v[2 * k + 1] = {w.z, w.w};
         }
@@ -195,13 +203,14 @@ __device__ __forceinline__ uint32_t pack_h2(cx<float> c, float inv) {
 
 template <> struct Field<P16> {
     using R = float;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const void* base, int Vh, int j, cx<R> v[12]) {
-        const uint4* p = static_cast<const uint4*>(base);
+        const nu4* p = static_cast<const nu4*>(base);
         const float* nrm = reinterpret_cast<const float*>(static_cast<const char*>(base) + norm_offset(Vh));
-        const float s = nrm[j];
+        const float s = NT ? __builtin_nontemporal_load(nrm + j) : nrm[j];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            uint4 w = p[size_t(k) * Vh + j];
+            const nu4 w = ld16<NT>(p + size_t(k) * Vh + j);
             unpack_h2(w.x, s, v[4 * k]);
             unpack_h2(w.y, s, v[4 * k + 1]);
             unpack_h2(w.z, s, v[4 * k + 2]);
