@@ -486,6 +486,8 @@ def pmc_summary(args):
         agg[key]["valu"].append(100.0 * sum(cs["SQ_ACTIVE_INST_VALU"]) / cu_num / g)
         if "SQ_ACTIVE_INST_LDS" in cs:
             agg[key]["lds"].append(100.0 * sum(cs["SQ_ACTIVE_INST_LDS"]) / cu_num / g)
+        if "SQ_INSTS_VALU" in cs and sum(cs.get("SQ_WAVES", [0])) > 0:
+            agg[key]["ipw"].append(sum(cs["SQ_INSTS_VALU"]) / sum(cs["SQ_WAVES"]))
     lines = ["# rocprofv3 counters: vector ALU and LDS busy share of the hop and CG kernels", "",
              "Commands (from the repository root on one MI355X, with `export TMPDIR=/tmp`):", ""]
     lines += ["    " + c.strip() for c in args.summary_cmds.split("||") if c.strip()]
@@ -493,14 +495,18 @@ def pmc_summary(args):
               "(rocprofv3's VALUBusy; the database sums GRBM_GUI_ACTIVE over the 8 XCDs, divided back "
               "here), LDS busy likewise from SQ_ACTIVE_INST_LDS; means over the dispatches of each "
               "kernel and grid.", "",
-              "| kernel | grid (threads) | dispatches | VALU busy % | LDS busy % |", "|---|---|---|---|---|"]
+              "VALU instructions per wave = SQ_INSTS_VALU / SQ_WAVES (a wave covers 64 lanes: 64 / L5 "
+              "sites of the hop kernels, 64 sites of the vector kernels).", "",
+              "| kernel | grid (threads) | dispatches | VALU busy % | LDS busy % | VALU instr. per wave |",
+              "|---|---|---|---|---|---|"]
     rows = sorted(agg.items(), key=lambda kv: -len(kv[1]["valu"]))
     for (name, gs), d in rows:
         if not (name.startswith("mdwf::k_hop") or name.startswith("mdwf::k_cg")):
             continue
         lds = "%.1f" % (sum(d["lds"]) / len(d["lds"])) if d["lds"] else "-"
-        lines.append("| `%s` | %d | %d | %.1f | %s |" % (name, gs, len(d["valu"]),
-                                                          sum(d["valu"]) / len(d["valu"]), lds))
+        ipw = "%.0f" % (sum(d["ipw"]) / len(d["ipw"])) if d["ipw"] else "-"
+        lines.append("| `%s` | %d | %d | %.1f | %s | %s |" % (name, gs, len(d["valu"]),
+                                                               sum(d["valu"]) / len(d["valu"]), lds, ipw))
     text = "\n".join(lines) + "\n"
     if args.summary_out:
         with open(args.summary_out, "w") as f:
