@@ -1270,6 +1270,7 @@ def main():
         measured_all = len(cols) == nrhs
         fp64 = dict(form=FORM_NAMES[args.fp64_form], columns_solved=len(cols), seconds=[round(t, 4) for t in t64],
                     iters=it64, max_true_resid=max(r64),
+                    cg_iteration_ms=round(1e3 * sum(t64) / max(1, sum(it64)), 4),
                     seconds_all_columns=round(sum(t64) if measured_all else float(np.mean(t64)) * nrhs, 4),
                     note="measured: sum over the %d columns" % nrhs if measured_all else
                     "sum over %d columns = mean of %d measured columns x %d" % (nrhs, len(cols), nrhs))
@@ -1351,6 +1352,9 @@ def main():
             "model_GFLOPs": round(step_flops / (ms_per_step * 1e-3) / 1e9, 1),
             "model_bytes": step_bytes,
             "err_vs_fp64": [float("%.3g" % e) for e in errs] if errs else None,
+            # wall time of one iteration of the batched solve (all its RHS),
+            # source preparation, reliable updates and verification included
+            "cg_iteration_ms": round(ms_per_step / max(i["iters"] for i in infos), 4),
         },
         "fp64_cg": fp64,
         "mixed_solve": other,
