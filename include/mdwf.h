@@ -145,6 +145,13 @@ typedef struct {
                             of the same systems.  Each is read once, after its
                             RHS has been solved, to fill info.err_vs_ref */
 } mdwf_solver_opts;
+/* There is no switch for deterministic solves: every solve is.  The CG dot
+ * products are summed per RHS in a fixed order (wavefront butterfly, then the
+ * workgroup, then the workgroup partials in index order), no reduction
+ * crosses right-hand sides, and no atomics are used, so a solve repeated with
+ * the same inputs, launch shape and device gives the same bits, and an RHS
+ * gives the same bits alone, in any batch, chunk or sub-batch and in a served
+ * request. */
 
 typedef struct {
     int iters;            /* inner CG iterations                                  */
