@@ -13,8 +13,16 @@
 
 namespace mdwf {
 
+// Waves per SIMD the hop kernels are compiled for: kernels B / B^+ of the
+// right-preconditioned FP16 CG operator fit six waves (80 VGPRs, no spills)
+// with the table-driven centre term; the others take what their registers
+// allow (held to six, kernels A / A^+ would spill).
+template <Prec P, int K> constexpr int hop_waves_per_eu() {
+    return (P == P16 && (K == HOP_SCHUR_B_RP || K == HOP_SCHUR_B_DAG_RP)) ? 6 : 1;
+}
+
 template <Prec P, int K, int LM>
-__global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(hop_waves_per_eu<P, K>()))) k_hop(const Geo g, const HopDev a) {
     using R = typename Real<P>::T;
     using TR = HopTraits<K>;
     const int L5 = g.L5;
@@ -111,10 +119,33 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     constexpr int NP = LinkStage<P>::NP;
     constexpr int kDirBytes = kStageSites * NP * 16;
     constexpr int kLinkBytes = LM == 1 ? kWaves * 8 * kDirBytes : 0;
-    constexpr int kEpiBytes = (TR::epi == 1 || TR::epi == 2 || TR::cen == 4 || TR::cen == 5)
-                                  ? 12 * kBlock * int(sizeof(cx<R>)) : 0;
+    // the dense polynomials' tile: all twelve components for the epilogue of
+    // kernels A / A^+, six (two passes) for the centre term of B / B^+
+    constexpr int kEpiBytes = (TR::epi == 1 || TR::epi == 2) ? 12 * kBlock * int(sizeof(cx<R>))
+                            : (TR::cen == 4 || TR::cen == 5) ? 6 * kBlock * int(sizeof(cx<R>)) : 0;
     constexpr int kSmem = kLinkBytes > kEpiBytes ? kLinkBytes : kEpiBytes;
     __shared__ __align__(16) unsigned char smem[kSmem > 0 ? kSmem : 16];
+    // Dense centre term sum_k w_k C^k (or its adjoint) of kernels B / B^+:
+    // the workgroup's RHS gets a table (dynamic LDS, L5 x L5 entries) of the
+    // coefficient each lane applies to each source slice, dtab[s][j] = (P+
+    // coefficient, P- coefficient) with the -m_q of the wrap folded in, so
+    // the sums run over source slices with no index arithmetic.  C^k moves
+    // the P+ spins up (slice s reads s - k) and the P- spins down (s reads
+    // s + k); the adjoint swaps the two.  (The same table in the epilogue of
+    // kernels A / A^+ cost them occupancy and made them slower.)
+    constexpr bool kDense = dense_centre<K>();
+    constexpr bool kDenseAdj = TR::cen == 5;
+    extern __shared__ __align__(16) unsigned char hop_dyn_lds[];
+    cx<R>* const dtab = reinterpret_cast<cx<R>*>(hop_dyn_lds);
+    if constexpr (kDense) {
+        const double* poly = cf.w;
+        for (int e = tid; e < L5 * L5; e += kBlock) {
+            const int ss = e / L5, j = e - ss * L5;
+            const R dn = (j <= ss) ? R(poly[ss - j]) : -mq * R(poly[ss - j + L5]);   // read j = s - k
+            const R up = (j >= ss) ? R(poly[j - ss]) : -mq * R(poly[j - ss + L5]);   // read j = s + k
+            dtab[e] = kDenseAdj ? cx<R>{up, dn} : cx<R>{dn, up};
+        }
+    }
     unsigned char* lslot = smem + size_t(wave) * 8 * kDirBytes + size_t(sw) * NP * 16;
     const int a0 = gbase << 2;
     if constexpr (LM == 1) {
@@ -241,35 +272,11 @@ __global__ void __launch_bounds__(kBlock) k_hop(const Geo g, const HopDev a) {
     // the L5 lanes of a site exchange their values through LDS
     cx<R> cd[12];
     if constexpr (TR::cen == 4 || TR::cen == 5) {
-        cx<R>* sh = reinterpret_cast<cx<R>*>(smem);
         cx<R> cv[12];
         // lanes past the lattice load site 0 (in bounds; no valid lane reads them)
         Field<P>::load(at_rhs(a.centre, a.stride, rhs), g.Vh, valid ? i * L5 + s : 0, cv);
         if constexpr (LM == 1) __syncthreads();   // every wave is past the link stage
-#pragma unroll
-        for (int c = 0; c < 12; ++c) sh[c * kBlock + tid] = cv[c];
-        __syncthreads();
-        if (valid) {
-            const int tbase = tid - s;
-            const R w0 = R(cf.w[0]);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) cd[c] = w0 * cv[c];   // k = 0 starts the sums
-            for (int k = 1; k < L5; ++k) {
-                const R wk = R(cf.w[k]);
-                // C^k on P+ reads slice s-k, on P- slice s+k (adjoint: swapped)
-                int su = (TR::cen == 4) ? s - k : s + k;
-                int sd = (TR::cen == 4) ? s + k : s - k;
-                R fu = wk, fd = wk;
-                if (su < 0) { su += L5; fu = -mq * wk; }
-                if (su >= L5) { su -= L5; fu = -mq * wk; }
-                if (sd < 0) { sd += L5; fd = -mq * wk; }
-                if (sd >= L5) { sd -= L5; fd = -mq * wk; }
-#pragma unroll
-                for (int c = 0; c < 6; ++c) cd[c] = cd[c] + fu * sh[c * kBlock + tbase + su];
-#pragma unroll
-                for (int c = 6; c < 12; ++c) cd[c] = cd[c] + fd * sh[c * kBlock + tbase + sd];
-            }
-        }
+        dense_poly_lanes(cv, cd, reinterpret_cast<cx<R>*>(smem), dtab + s * L5, tid, s, L5, valid);
     }
 
     double n2 = 0.0;
@@ -354,15 +361,17 @@ static void launch_hop_t(const Geo& g, const GaugeSet& gs, HopLaunch& L, hipStre
     a.partials = L.partials;
     L.nblocks_per_rhs = a.nblk;
     dim3 grid(a.nblk * L.nrhs);
+    // the dense polynomial's coefficient table (see k_hop)
+    const size_t dyn = dense_centre<K>() ? size_t(g.L5) * g.L5 * sizeof(cx<typename Real<P>::T>) : 0;
     if (lm == 1) {
-        hipLaunchKernelGGL((k_hop<P, K, 1>), grid, dim3(kBlock), 0, st, g, a);
+        hipLaunchKernelGGL((k_hop<P, K, 1>), grid, dim3(kBlock), dyn, st, g, a);
     } else if (lm == 2) {
-        if constexpr (P != P64) hipLaunchKernelGGL((k_hop<P, K, 2>), grid, dim3(kBlock), 0, st, g, a);
+        if constexpr (P != P64) hipLaunchKernelGGL((k_hop<P, K, 2>), grid, dim3(kBlock), dyn, st, g, a);
     } else if (lm == 3) {
         if constexpr (P == P16 && !HopTraits<K>::preB)
-            hipLaunchKernelGGL((k_hop<P, K, 3>), grid, dim3(kBlock), 0, st, g, a);
+            hipLaunchKernelGGL((k_hop<P, K, 3>), grid, dim3(kBlock), dyn, st, g, a);
     } else {
-        hipLaunchKernelGGL((k_hop<P, K, 0>), grid, dim3(kBlock), 0, st, g, a);
+        hipLaunchKernelGGL((k_hop<P, K, 0>), grid, dim3(kBlock), dyn, st, g, a);
     }
 }
 

@@ -516,6 +516,44 @@ __device__ __forceinline__ void dir_term(cx<typename Real<P>::T> acc[12], const 
 // Link modes (see dir_term): the LDS stage needs at most kStageSites sites per
 // wave (L5 >= 8), the lane gather needs L5 >= the number of 16-byte parts.
 constexpr int kStageSites = 8;
+
+// Hop kinds with a dense fifth-dimension polynomial as their centre term
+template <int K> constexpr bool dense_centre() { return HopTraits<K>::cen == 4 || HopTraits<K>::cen == 5; }
+
+// out = sum_j T[s][j] v_j across the L5 lanes of each site (lane s of the
+// site's group holds slice s), with ct = T[s] the lane's row of coefficient
+// pairs (P+ components use .re, P- components .im).  The values go through
+// an LDS tile of six components per thread in two passes, the P+ spins and
+// then the P- spins; every thread of the workgroup calls this (barriers).
+template <typename R>
+__device__ __forceinline__ void dense_poly_lanes(const cx<R> v[12], cx<R> out[12], cx<R>* tile, const cx<R>* ct,
+                                                 int tid, int s, int L5, bool valid) {
+    const cx<R>* col = tile + (tid - s);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        if (half) __syncthreads();   // every lane is done with the P+ pass
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tile[c * kBlock + tid] = v[6 * half + c];
+        __syncthreads();
+        if (valid) {
+            {
+                const cx<R> f = ct[0];
+                const R fh = half ? f.im : f.re;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) out[6 * half + c] = fh * col[c * kBlock];
+            }
+            // rolled: the six component reads share one address with
+            // immediate offsets
+#pragma unroll 1
+            for (int j = 1; j < L5; ++j) {
+                const cx<R> f = ct[j];
+                const R fh = half ? f.im : f.re;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) out[6 * half + c] = out[6 * half + c] + fh * col[c * kBlock + j];
+            }
+        }
+    }
+}
 // 16-byte parts gathered by lane exchange (the short tail is loaded by every lane)
 template <Prec P> constexpr int link_parts() { return P == P64 ? 9 : P == P32 ? 4 : 2; }
 
