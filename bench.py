@@ -233,9 +233,10 @@ def hop_launch_bytes(inner, Vh, nr):
 # What the counters show limits the hop kernels below the HBM roofline
 # (rocprofv3 summaries under profiles/).
 LIMITER = {
-    "f16": "co-limited: 82-90% VALU busy (profiles/hop_valu_busy_24c64_L8.md) while moving 6.3-6.6 TB/s to and "
-           "from memory beyond L2, 2.2x the algorithmic bytes (profiles/schur_rp_f16_24c64_L8_12rhs_counters.md); "
-           "13% fewer VALU instructions in kernel A did not make it faster",
+    "f16": "co-limited: 89% VALU busy in kernels A / A_dag, 73-76% in B / B_dag (profiles/hop_valu_busy_24c64_L8.md), "
+           "while moving 5.9-6.7 TB/s to and from memory beyond L2, 2.2x the algorithmic bytes "
+           "(profiles/schur_rp_f16_24c64_L8_12rhs_counters.md); 13% fewer VALU instructions in kernel A did "
+           "not make it faster",
     "f32": "re-reads of the input field beyond L2 (2.26x) at a rate near the streaming limit "
            "(profiles/hop_f32_plane_24c64_L8_counters.md)",
     "f64": "re-reads of the input field beyond L2 (profiles/hop_f32_24c64_L8_counters.md)",
@@ -285,7 +286,7 @@ def roofline(info, inner, Vh, form):
                 for n, u, b in zip(names, us, by)}
     hbm = dict(achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4))
     if inner == "f16" and form == "rp":
-        # issue-bound (VALU busy 82-90 %): priced against the vector ALUs,
+        # issue-bound (VALU busy 73-90 %): priced against the vector ALUs,
         # the HBM fraction kept beside it
         fl = hop_launch_flops(Vh, nr, form)
         tf = (fl[0] + fl[1]) / ((us[0] + us[1]) * 1e-6) / 1e12
