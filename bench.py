@@ -518,10 +518,11 @@ def pmc_summary(args):
 # Gradient flow model per link and Runge-Kutta stage: 26 products of 3x3
 # complex matrices (12 for the six staples, one for the link times their sum,
 # 12 for the degree-12 Taylor exponential, one for the update; 216 flops each)
-# and, in FP64, the input link and the output link read / written once and
-# the exponent accumulator read and written (written only by the first stage).
+# and, in FP64, the input link and the output link read / written once (144 B
+# each) and the exponent accumulator, eight reals (64 B), read and written
+# (written only by the first stage).
 FLOW_FLOPS_PER_LINK = 26 * 216
-FLOW_BYTES_PER_LINK = (144 * 3 + 144 * 4 + 144 * 4) / 3.0
+FLOW_BYTES_PER_LINK = ((144 + 144 + 64) + 2 * (144 + 144 + 64 + 64)) / 3.0
 
 
 def flow_main(args):

@@ -382,8 +382,11 @@ mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, doubl
  * steps of size eps (flow time nsteps * eps).  U is a canonical gauge field
  * (layout of mdwf_load_gauge), flowed in place; all directions periodic (the
  * fermion boundary condition plays no part).  plaq (may be NULL) receives
- * the average plaquette before and after.  Extents >= 2; ERR_ARG on eps <= 0
- * or nsteps < 0.  Synchronous; allocates two link fields of scratch. */
+ * the average plaquette before and after.  The links must be SU(3) to
+ * rounding (unitary, det 1): the staple links enter through their first two
+ * rows, the third being the conjugated cross product of those.  Extents >= 2;
+ * ERR_ARG on eps <= 0 or nsteps < 0.  Synchronous; allocates one link field
+ * and eight reals per link of scratch. */
 mdwf_status mdwf_wilson_flow(const mdwf_geometry *geom, int hip_device, double *U, double eps, int nsteps,
                              double *plaq);
 /* Same on a device field, on `stream` (NULL = the null stream). */

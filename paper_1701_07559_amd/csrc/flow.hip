@@ -10,7 +10,8 @@
 // and W_{i+1} = exp(E_i) W_i with (a, b) = (1/4, 0), (8/9, -17/9), (3/4, -1).
 //
 // One kernel launch per stage: a thread per link reads the stage's input
-// field (the link and its six staples), writes E_i for that link and the
+// field (the link and its six staples; staple links by their first two
+// rows), writes E_i for that link (its eight independent reals) and the
 // updated link into a second buffer, so every staple sees the stage's input.
 // The exponential of the small traceless antihermitian E is a degree-12
 // Taylor polynomial after scaling by a power of two with squaring back.
@@ -37,6 +38,60 @@ __device__ __forceinline__ Su3 ld_link(const double2* U, long link) {
         r.m[k] = {v.x, v.y};
     }
     return r;
+}
+
+// A staple link from its first two rows: for U in SU(3) (unitary, det U = 1)
+// the third row is the complex conjugate of the cross product of the first
+// two, so six of the nine entries are loaded and three are computed.  The
+// flow keeps every link in SU(3) up to rounding, and the staple gathers, not
+// the arithmetic, bound the stage.
+__device__ __forceinline__ cx<double> conj_cross(cx<double> a, cx<double> b, cx<double> c, cx<double> d) {
+    const cx<double> v = cmadd(cmul(a, b), cx<double>{-c.re, -c.im}, d);   // a b - c d
+    return {v.re, -v.im};
+}
+__device__ __forceinline__ Su3 ld_link12(const double2* U, long link) {
+    Su3 r;
+    const double2* p = U + link * 9;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double2 v = p[k];
+        r.m[k] = {v.x, v.y};
+    }
+    r.m[6] = conj_cross(r.m[1], r.m[5], r.m[2], r.m[4]);
+    r.m[7] = conj_cross(r.m[2], r.m[3], r.m[0], r.m[5]);
+    r.m[8] = conj_cross(r.m[0], r.m[4], r.m[1], r.m[3]);
+    return r;
+}
+
+// The Runge-Kutta accumulator E is traceless antihermitian: eight reals per
+// link, stored as four double2 (Im E00, Im E11; E01; E02; E12).
+// complete_alg fills in the other entries from those eight.
+__device__ __forceinline__ void complete_alg(Su3& r) {
+    r.m[0].re = 0.0;
+    r.m[4].re = 0.0;
+    r.m[8] = {0.0, -(r.m[0].im + r.m[4].im)};
+    r.m[3] = {-r.m[1].re, r.m[1].im};
+    r.m[6] = {-r.m[2].re, r.m[2].im};
+    r.m[7] = {-r.m[5].re, r.m[5].im};
+}
+__device__ __forceinline__ Su3 ld_alg(const double2* E, long link) {
+    const double2* p = E + link * 4;
+    const double2 d = p[0], e01 = p[1], e02 = p[2], e12 = p[3];
+    Su3 r;
+    r.m[0] = {0.0, d.x};
+    r.m[4] = {0.0, d.y};
+    r.m[1] = {e01.x, e01.y};
+    r.m[2] = {e02.x, e02.y};
+    r.m[5] = {e12.x, e12.y};
+    complete_alg(r);
+    return r;
+}
+__device__ __forceinline__ void st_alg(double2* E, long link, const Su3& a) {
+    double2* p = E + link * 4;
+    p[0] = make_double2(a.m[0].im, a.m[4].im);
+    p[1] = make_double2(a.m[1].re, a.m[1].im);
+    p[2] = make_double2(a.m[2].re, a.m[2].im);
+    p[3] = make_double2(a.m[5].re, a.m[5].im);
 }
 
 __device__ __forceinline__ void st_link(double2* U, long link, const Su3& a) {
@@ -152,19 +207,19 @@ __global__ void __launch_bounds__(kFlowBlock) k_flow_stage(const FlowGeo g, cons
         if (nu == mu) continue;
         // upper staple U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
         const long xn = nbr(g, x, y, z, t, nu, 1);
-        Su3 s1 = mul_nd(ld_link(Win, xp * 4 + nu), ld_link(Win, xn * 4 + mu));
-        s1 = mul_nd(s1, ld_link(Win, site * 4 + nu));
+        Su3 s1 = mul_nd(ld_link12(Win, xp * 4 + nu), ld_link12(Win, xn * 4 + mu));
+        s1 = mul_nd(s1, ld_link12(Win, site * 4 + nu));
         // lower staple U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
         const long xm = nbr(g, x, y, z, t, nu, -1);
         int cx_[4] = {x, y, z, t};
         cx_[nu] = (cx_[nu] - 1 + (nu == 0 ? g.X : nu == 1 ? g.Y : nu == 2 ? g.Z : g.T)) %
                   (nu == 0 ? g.X : nu == 1 ? g.Y : nu == 2 ? g.Z : g.T);
         const long xpm = nbr(g, cx_[0], cx_[1], cx_[2], cx_[3], mu, 1);
-        const Su3 a1 = ld_link(Win, xpm * 4 + nu);
-        const Su3 a2 = ld_link(Win, xm * 4 + mu);
+        const Su3 a1 = ld_link12(Win, xpm * 4 + nu);
+        const Su3 a2 = ld_link12(Win, xm * 4 + mu);
         // (U_mu(x-nu) U_nu(x+mu-nu))^+ U_nu(x-nu)
         Su3 s2 = mul(a2, a1);
-        s2 = mul_dn(s2, ld_link(Win, xm * 4 + nu));
+        s2 = mul_dn(s2, ld_link12(Win, xm * 4 + nu));
 #pragma unroll
         for (int k = 0; k < 9; ++k) S.m[k] = S.m[k] + s1.m[k] + s2.m[k];
     }
@@ -172,18 +227,22 @@ __global__ void __launch_bounds__(kFlowBlock) k_flow_stage(const FlowGeo g, cons
     const Su3 O = mul(U, S);
     // Z = -1/2 (O - O^+) + 1/6 tr(O - O^+); tr(O - O^+) = 2 i Im tr O
     const double itr = (O.m[0].im + O.m[4].im + O.m[8].im) / 3.0;
-    Su3 Ev = (b != 0.0) ? ld_link(E, l) : Su3{};
+    // the eight independent entries of E (upper triangle, first two
+    // diagonal ones); the rest follow from antihermiticity and zero trace
+    Su3 Ev = (b != 0.0) ? ld_alg(E, l) : Su3{};
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int j = i; j < 3; ++j) {
+            if (i == 2) continue;
             const cx<double> oij = O.m[i * 3 + j], oji = O.m[j * 3 + i];
             cx<double> zij = {-0.5 * (oij.re - oji.re), -0.5 * (oij.im + oji.im)};
             if (i == j) zij.im += itr;
             const cx<double> prev = (b != 0.0) ? Ev.m[i * 3 + j] : cx<double>{0.0, 0.0};
             Ev.m[i * 3 + j] = {a * zij.re + b * prev.re, a * zij.im + b * prev.im};
         }
-    st_link(E, l, Ev);
+    st_alg(E, l, Ev);
+    complete_alg(Ev);
     st_link(Wout, l, mul(expm_small(Ev), U));
 }
 
@@ -279,7 +338,7 @@ mdwf_status mdwf_wilson_flow_dev(const mdwf_geometry* geom, double* U_dev, doubl
     double2 *W2 = nullptr, *E = nullptr;
     double* part = nullptr;
     if ((s = hip_check(nullptr, hipMalloc(&W2, bytes), "flow buffer"))) return s;
-    if ((s = hip_check(nullptr, hipMalloc(&E, bytes), "flow buffer"))) {
+    if ((s = hip_check(nullptr, hipMalloc(&E, size_t(nlinks) * 4 * sizeof(double2)), "flow buffer"))) {
         (void)hipFree(W2);
         return s;
     }

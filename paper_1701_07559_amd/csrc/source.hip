@@ -10,9 +10,11 @@
 // * The 5D right-hand side of a 4D source for the Moebius operator
 //   D5 = D_W (b5 + c5 C) + 1 - C:  b = (1 - c5 D_W) Pbar eta with
 //   (Pbar eta)_{L5-1} = P- eta, (Pbar eta)_0 = P+ eta, whose solution's wall
-//   field q = P- x_0 + P+ x_{L5-1} is the 4D quark propagator.  One thread
-//   per 4D site and vector applies the Wilson hop to both chiral halves of
-//   eta at once (each neighbour is loaded once) and writes every slice of b.
+//   field q = P- x_0 + P+ x_{L5-1} is the 4D quark propagator.  One
+//   wavefront per 4D site (up to 16 vectors; one thread per site and vector
+//   beyond) applies the Wilson hop to both chiral halves of eta, each
+//   neighbour spinor loaded once, and writes the two wall slices of b; a
+//   fill kernel zeroes the others.
 // * The wall and midpoint fields q and Q = P- x_{L5/2} + P+ x_{L5/2-1} of 5D
 //   solutions, and per time slice the pseudoscalar and midpoint correlators
 //   C_PP(t) = sum |q|^2, C_mp(t) = sum |Q|^2 over the slice's sites, spins,
@@ -138,7 +140,7 @@ struct SmearLayout {
 };
 
 template <bool WAVE>
-__global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const SmearIdx ix, const double2* U,
+__global__ void __launch_bounds__(kSrcBlock) __attribute__((amdgpu_waves_per_eu(WAVE ? 4 : 1, WAVE ? 4 : 8))) k_gauss_step(const SrcGeo g, const SmearIdx ix, const double2* U,
                                                           const double2* in, double2* out, double kappa,
                                                           uint32_t nsites, uint32_t ntot, const SmearLayout lay) {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,31 +160,50 @@ __global__ void __launch_bounds__(kSrcBlock) k_gauss_step(const SrcGeo g, const 
     const uint32_t t = ix.fZ.div(q2), z = q2 - t * g.Z;
     const double2* f = in + size_t(v) * lay.in_vs + sp * 3;
     const uint32_t sy = g.X, sz = uint32_t(g.X) * g.Y;
-    cx<double> acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}}, u[9], nb[3], w[3];
-#pragma unroll 1
+    // neighbours x+mu, x-mu for mu = x, y, z, in that order
+    uint32_t xn[6];
+#pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
         const uint32_t c = mu == 0 ? x : mu == 1 ? y : z;
         const uint32_t L = mu == 0 ? g.X : mu == 1 ? g.Y : g.Z;
         const uint32_t st = mu == 0 ? 1u : mu == 1 ? sy : sz;
-        const uint32_t xp = c + 1 == L ? i - (L - 1) * st : i + st;
-        const uint32_t xm = c == 0 ? i + (L - 1) * st : i - st;
-#pragma unroll
-        for (int dir = 0; dir < 2; ++dir) {
-            const uint32_t xn = dir == 0 ? xp : xm;
-            ld_link_op(U, dir == 0 ? i : xn, mu, dir != 0, u);
-            const double2* p = f + size_t(xn) * lay.in_ss;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) nb[b] = {p[b].x, p[b].y};
-            link_times(u, nb, w, 1);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) acc[a] = acc[a] + w[a];
-        }
+        xn[2 * mu] = c + 1 == L ? i - (L - 1) * st : i + st;
+        xn[2 * mu + 1] = c == 0 ? i + (L - 1) * st : i - st;
     }
-    const double2* p = f + size_t(i) * lay.in_ss;
+    cx<double> acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}}, u[9], nb[3], w[3];
+    double2 cv[3];
+    auto hop = [&](int k, const double2* nv) {   // acc += U_mu(x) psi(x+mu) or U_mu(x-mu)^+ psi(x-mu)
+        ld_link_op(U, (k & 1) == 0 ? i : xn[k], k >> 1, (k & 1) != 0, u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nb[c] = {nv[c].x, nv[c].y};
+        link_times(u, nb, w, 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = acc[c] + w[c];
+    };
+    if constexpr (WAVE) {
+        // wave-uniform links (scalar loads): the six neighbours and the
+        // centre are all requested before the first product
+        double2 nv[6][3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) nv[k][c] = f[size_t(xn[k]) * lay.in_ss + c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cv[c] = f[size_t(i) * lay.in_ss + c];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) hop(k, nv[k]);
+    } else {
+#pragma unroll 1
+        for (int mu = 0; mu < 3; ++mu)
+#pragma unroll
+            for (int dir = 0; dir < 2; ++dir) hop(2 * mu + dir, f + size_t(xn[2 * mu + dir]) * lay.in_ss);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cv[c] = f[size_t(i) * lay.in_ss + c];
+    }
     double2* o = out + size_t(v) * lay.out_vs + size_t(i) * lay.out_ss + sp * 3;
     const double cc = 1.0 - 6.0 * kappa;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) o[a] = make_double2(fma(cc, p[a].x, kappa * acc[a].re), fma(cc, p[a].y, kappa * acc[a].im));
+    for (int c = 0; c < 3; ++c) o[c] = make_double2(fma(cc, cv[c].x, kappa * acc[c].re), fma(cc, cv[c].y, kappa * acc[c].im));
 }
 
 // ----------------------------------------------------------- wall source
@@ -258,6 +279,119 @@ __global__ void __launch_bounds__(kSrcBlock) k_wall_source(const SrcGeo g, const
     } else {
         st_spinor(out, i, b0);
         st_spinor(out + size_t(L5 - 1) * nsites * 12, i, bl);
+    }
+}
+
+// The value of another lane of the same quad (quad_perm DPP control: xor 1
+// swaps the lanes of a spin pair, xor 2 the two pairs), moved by the VALU
+// with no LDS round trip.
+template <int CTRL> __device__ __forceinline__ double quad_swap(double x) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(x));
+    const int lo = __builtin_amdgcn_mov_dpp(int(uint32_t(u)), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(uint32_t(hi)) << 32) |
+                                                       uint32_t(lo)));
+}
+constexpr int kQuadXor1 = 0xB1;   // lanes (1, 0, 3, 2)
+constexpr int kQuadXor2 = 0x4E;   // lanes (2, 3, 0, 1)
+
+// One wavefront per site (nvec <= 16), so the site, its neighbours and its
+// links are wave-uniform and the links come by scalar loads.  Lane
+// 4 v + 2 h + j (lanes 4 nvec .. 63 idle) carries spin 2 h + j of vector v:
+// it multiplies that spin of each neighbour of eta by the link, i.e. its
+// share of the hop of P+ eta (h = 0) or of P- eta (h = 1), and keeps two
+// outputs of the slice its half feeds (0 for P+, L5 - 1 for P-): spin
+// 2 h + j itself and spin 2 (1 - h) + j, the (1 -+ g_mu) image.  That image
+// is G_mu^+ (h = 0) or G_mu (h = 1) applied to the spin pair, which for
+// mu = x, y takes the other lane of the pair (lane ^ 1, a DPP quad
+// permute).  Same sums, same order as the thread-per-vector kernel above.
+__global__ void __launch_bounds__(kSrcBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_wall_source_wave(const SrcGeo g, const SmearIdx ix, const double2* U,
+                                                                const double2* eta, double2* b, double cdiag,
+                                                                double chop, int L5, uint32_t nsites) {
+    const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = uint32_t(__builtin_amdgcn_readfirstlane(int(id >> 6)));
+    const uint32_t r = id & 63;
+    if (i >= nsites || r >= ix.G) return;   // ix.G = 4 nvec: whole spin quads stay
+    const uint32_t v = r >> 2, sp = r & 3, h = sp >> 1, j = sp & 1;
+    const double2* f = eta + size_t(v) * nsites * 12 + sp * 3;
+    Site st;
+    const uint32_t q1 = ix.fX.div(i), q2 = ix.fY.div(q1);
+    st.x = int(i - q1 * g.X);
+    st.y = int(q1 - q2 * g.Y);
+    st.t = int(ix.fZ.div(q2));
+    st.z = int(q2 - uint32_t(st.t) * g.Z);
+    // the pair image's phase per direction: G^+ for h = 0, G for h = 1
+    // (G_x = -i s1, G_y = -i s2, G_z = -i s3, G_t = 1); for x and y it acts
+    // on the other spin of the pair
+    const double dg = h == 0 ? 1.0 : -1.0, js = j == 0 ? 1.0 : -1.0;
+    cx<double> own[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}}, oth[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    // all eight neighbours' spins are requested before the first product
+    long xn[8];
+    double bc[8];
+    double2 nv[8][3];
+#pragma unroll
+    for (int hop = 0; hop < 8; ++hop) {
+        const int mu = hop >> 1, dir = hop & 1;
+        xn[hop] = neighbour(g, st, mu, dir == 0 ? +1 : -1);
+        const bool wrap = mu == 3 && ((dir == 0 && st.t == g.T - 1) || (dir == 1 && st.t == 0));
+        bc[hop] = (g.antiperiodic && wrap) ? -1.0 : 1.0;
+        const double2* p = f + xn[hop] * 12;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nv[hop][c] = p[c];
+    }
+    double2 cv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cv[c] = f[size_t(i) * 12 + c];
+    cx<double> u[9], nb[3], w[3];
+#pragma unroll
+    for (int hop = 0; hop < 8; ++hop) {
+        const int mu = hop >> 1, dir = hop & 1;
+        const double sg = dir == 0 ? 1.0 : -1.0;
+        ld_link_op(U, dir == 0 ? long(i) : xn[hop], mu, dir != 0, u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nb[c] = {bc[hop] * nv[hop][c].x, bc[hop] * nv[hop][c].y};
+        link_times(u, nb, w, 1);
+        // image = (fr + i fi) * (mu < 2 ? the pair's other w : w)
+        double fr, fi;
+        if (mu == 0) fr = 0.0, fi = dg;               // G^+ = i s1, G = -i s1
+        else if (mu == 1) fr = dg * js, fi = 0.0;     // G^+ = [[0, 1], [-1, 0]], G = -G^+
+        else if (mu == 2) fr = 0.0, fi = dg * js;     // G^+ = diag(i, -i), G = -G^+
+        else fr = 1.0, fi = 0.0;                      // G = G^+ = 1
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<double> src = w[c];
+            if (mu < 2) src = {quad_swap<kQuadXor1>(w[c].re), quad_swap<kQuadXor1>(w[c].im)};
+            const cx<double> im = {fr * src.re - fi * src.im, fr * src.im + fi * src.re};
+            own[c] = own[c] + w[c];
+            oth[c] = oth[c] - sg * im;
+        }
+    }
+    // slice 0: (1 - c5 (4 - M5)) P+ eta + c5/2 hop(P+ eta); slice L5 - 1 likewise with P-
+    cx<double> o1[3], o2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o1[c] = cdiag * cx<double>{cv[c].x, cv[c].y} + chop * own[c];
+        o2[c] = chop * oth[c];
+    }
+    double2* out = b + size_t(v) * L5 * nsites * 12 + size_t(i) * 12;
+    if (L5 == 1) {   // both halves land on the one slice: lane h = 0 adds lane h = 1's outputs
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cx<double> a1 = {quad_swap<kQuadXor2>(o2[c].re), quad_swap<kQuadXor2>(o2[c].im)};
+            const cx<double> a2 = {quad_swap<kQuadXor2>(o1[c].re), quad_swap<kQuadXor2>(o1[c].im)};
+            o1[c] = o1[c] + a1;
+            o2[c] = o2[c] + a2;
+        }
+        if (h) return;
+    } else if (h) {
+        out += size_t(L5 - 1) * nsites * 12;
+    }
+    double2* p1 = out + sp * 3;
+    double2* p2 = out + (2 * (1 - h) + j) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        p1[c] = make_double2(o1[c].re, o1[c].im);
+        p2[c] = make_double2(o2[c].re, o2[c].im);
     }
 }
 
@@ -490,9 +624,17 @@ mdwf_status mdwf_wall_source_dev(const mdwf_geometry* geom, const mdwf_action* a
     ix.fZ = FastDiv(uint32_t(g.Z));
     hipStream_t st = static_cast<hipStream_t>(stream);
     double2* b = reinterpret_cast<double2*>(b_dev);
-    hipLaunchKernelGGL(k_wall_source, dim3(blocks_for(ntot)), dim3(kSrcBlock), 0, st, g, ix,
-                       reinterpret_cast<const double2*>(U_dev), reinterpret_cast<const double2*>(eta_dev), b, cdiag,
-                       chop, act->L5, uint32_t(nsites), uint32_t(ntot));
+    const auto* U = reinterpret_cast<const double2*>(U_dev);
+    const auto* eta = reinterpret_cast<const double2*>(eta_dev);
+    if (nvec <= 16 && double(nsites) * 64.0 < double(1u << 31)) {   // one wavefront per site
+        SmearIdx iw = ix;
+        iw.G = uint32_t(4 * nvec);
+        hipLaunchKernelGGL(k_wall_source_wave, dim3(blocks_for(size_t(nsites) * 64)), dim3(kSrcBlock), 0, st, g, iw,
+                           U, eta, b, cdiag, chop, act->L5, uint32_t(nsites));
+    } else {
+        hipLaunchKernelGGL(k_wall_source, dim3(blocks_for(ntot)), dim3(kSrcBlock), 0, st, g, ix, U, eta, b, cdiag,
+                           chop, act->L5, uint32_t(nsites), uint32_t(ntot));
+    }
     s = hip_check(nullptr, hipGetLastError(), "wall source kernel");
     if (!s && act->L5 > 2) {
         const size_t field = size_t(act->L5) * nsites * 12, n2 = size_t(act->L5 - 2) * nsites * 12;

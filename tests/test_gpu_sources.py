@@ -97,6 +97,25 @@ def test_wall_source_matches_oracle(M, dims, L5, b5, c5, ap):
         assert np.abs(out[k] - ref).max() <= 1e-14 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("nvec,L5,ap", [(16, 4, True), (17, 4, True), (5, 1, True), (1, 2, False)])
+def test_wall_source_vector_counts_match_oracle(M, nvec, L5, ap):
+    """Up to 16 vectors one wavefront per site (lanes of the spin pairs
+    exchange their link products), 17 and more one thread per vector: both
+    against the oracle, on a ragged lattice with the time wrap."""
+    dims = (5, 3, 2, 4)
+    U = I.random_links(dims, 0.3, 109)
+    eta = spinors(dims, nvec, 110)
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.03, antiperiodic_t=ap)
+    Ud, ed, bd = dev(U), dev(eta), empty((nvec,) + act.shape5)
+    bd.fill_(7.0)
+    M.mdwf_wall_source_dev(dims, (1.3, 1.5, 0.5, 0.03, L5), Ud.data_ptr(), nvec, ed.data_ptr(), bd.data_ptr(),
+                           antiperiodic_t=ap)
+    out = host(bd, (nvec,) + act.shape5)
+    for k in range(nvec):
+        ref = SRC.wall_source(act, U, eta[k])
+        assert np.abs(out[k] - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
 def test_projections_and_correlators_match_oracle(M):
     dims, L5, n = (5, 3, 4, 6), 6, 3
     x5 = np.stack([I.gaussian_source(dims, L5, 107 + k) for k in range(n)])
