@@ -239,7 +239,8 @@ LIMITER = {
            "not make it faster",
     "f32": "re-reads of the input field beyond L2 (2.26x) at a rate near the streaming limit "
            "(profiles/hop_f32_plane_24c64_L8_counters.md)",
-    "f64": "re-reads of the input field beyond L2 (profiles/hop_f32_24c64_L8_counters.md)",
+    "f64": "re-reads of the input field beyond L2 (1.75-2.5x) at 5.3-6.6 TB/s "
+           "(profiles/hop_f64_24c64_L8_counters.md)",
 }
 
 # Vector-ALU roofline of the FP16-storage hop kernels, which the counters show
