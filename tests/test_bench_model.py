@@ -1,0 +1,79 @@
+"""The benchmark's byte, flop and peak models and its guards, on the host:
+the per-site bytes of one Schur-operator application against the scope
+table's figures, the vector-ALU peak of the FP16 kernels against its
+instruction count, the counter record applying only to the kernel source it
+was taken on, the flow stage's byte model, and the one-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture
+def l5_8(monkeypatch):
+    monkeypatch.setattr(bench, "L5", 8)
+
+
+@pytest.mark.parametrize("inner,per_site", [("f16", 332), ("f32", 624), ("f64", 1248)])
+def test_schur_bytes_per_site_match_the_scope_table(l5_8, inner, per_site):
+    # one RHS: kernels A + B of S move (120 + 288 / L5) reals per 5D site
+    # (plus three FP16 norms), i.e. 332 / 624 / 1248 bytes at L5 = 8
+    vh = 1000
+    a, b, a_dag, b_dag = bench.hop_launch_bytes(inner, vh, 1)
+    assert a + b == pytest.approx(per_site * vh)
+    assert (a_dag, b_dag) == (a, b)
+
+
+def test_batched_launch_charges_the_links_once(l5_8):
+    # twelve RHS in one launch: twelve times the spinor bytes, one set of links
+    vh = 3538944
+    one = bench.hop_launch_bytes("f16", vh, 1)
+    twelve = bench.hop_launch_bytes("f16", vh, 12)
+    links = vh * 144 * 2 / 8
+    for k in range(4):
+        assert twelve[k] - links == pytest.approx(12 * (one[k] - links))
+    assert twelve[0] == 4544004096 and twelve[1] == 6752305152   # 1284 and 1908 bytes per 5D site
+
+
+def test_alu_peak_is_the_instruction_count_derivation():
+    # 3456 model flops per 5D site and RHS for kernels A + B at L5 = 8 over
+    # 1368 lane-instructions: 288 x 2 dot2 (4 flops), 96 x 2 packed-half adds
+    # (2), 168 x 2 FP32 adds, 384 + 24 FP32 FMAs (2), at 256 x 4 x 16 lanes
+    # and 2.4 GHz
+    flops = 1704 + 1752
+    instr = 2 * 264 + 2 * 48 + 2 * 168 + 2 * 192 + 24
+    assert instr == 1368
+    assert bench.alu_peak_tflops(8) == pytest.approx(flops / instr * 256 * 4 * 16 * 2.4e9 / 1e12)
+    assert 99.2 < bench.alu_peak_tflops(8) < 99.4
+
+
+def test_counter_record_applies_only_to_its_kernel_source(monkeypatch):
+    with open(bench.TRAFFIC_FILE) as f:
+        line = next(l for l in f if l.startswith("traffic-record: "))
+    rec = json.loads(line[len("traffic-record: "):])
+    monkeypatch.setattr(bench, "kernel_sha", lambda: rec["dslash_sha256"])
+    got = bench.stored_traffic("rp")
+    assert got is not None and got["traffic_bytes_per_launch"] == rec["traffic_bytes_per_launch"]
+    assert bench.stored_traffic("asym") is None            # another Schur form
+    monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 64)
+    assert bench.stored_traffic("rp") is None              # the hop source changed since
+
+
+def test_flow_byte_model():
+    # old and new link (144 B each) per stage, the eight-real accumulator
+    # (64 B) written by every stage and read by the second and third
+    assert bench.FLOW_BYTES_PER_LINK == pytest.approx((352 + 2 * 416) / 3)
+    assert bench.FLOW_FLOPS_PER_LINK == 26 * 216
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
