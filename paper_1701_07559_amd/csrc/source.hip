@@ -139,10 +139,13 @@ struct SmearLayout {
     size_t in_vs, in_ss, out_vs, out_ss;
 };
 
+// The one-site-per-wave path is compiled for four waves per SIMD, so the
+// compiler keeps all its loads in flight (left free, it aims at eight waves
+// and keeps two neighbours' loads in flight; a step was 5 % slower so).
 template <bool WAVE>
-__global__ void __launch_bounds__(kSrcBlock) __attribute__((amdgpu_waves_per_eu(WAVE ? 4 : 1, WAVE ? 4 : 8))) k_gauss_step(const SrcGeo g, const SmearIdx ix, const double2* U,
-                                                          const double2* in, double2* out, double kappa,
-                                                          uint32_t nsites, uint32_t ntot, const SmearLayout lay) {
+__global__ void __launch_bounds__(kSrcBlock) __attribute__((amdgpu_waves_per_eu(WAVE ? 4 : 1, WAVE ? 4 : 8)))
+k_gauss_step(const SrcGeo g, const SmearIdx ix, const double2* U, const double2* in, double2* out, double kappa,
+             uint32_t nsites, uint32_t ntot, const SmearLayout lay) {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t i, r;
     if constexpr (WAVE) {
@@ -305,9 +308,11 @@ constexpr int kQuadXor2 = 0x4E;   // lanes (2, 3, 0, 1)
 // is G_mu^+ (h = 0) or G_mu (h = 1) applied to the spin pair, which for
 // mu = x, y takes the other lane of the pair (lane ^ 1, a DPP quad
 // permute).  Same sums, same order as the thread-per-vector kernel above.
-__global__ void __launch_bounds__(kSrcBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_wall_source_wave(const SrcGeo g, const SmearIdx ix, const double2* U,
-                                                                const double2* eta, double2* b, double cdiag,
-                                                                double chop, int L5, uint32_t nsites) {
+// Compiled for three waves per SIMD, which lets all 27 loads of a lane be
+// in flight at once.
+__global__ void __launch_bounds__(kSrcBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_wall_source_wave(const SrcGeo g, const SmearIdx ix, const double2* U, const double2* eta, double2* b, double cdiag,
+                   double chop, int L5, uint32_t nsites) {
     const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t i = uint32_t(__builtin_amdgcn_readfirstlane(int(id >> 6)));
     const uint32_t r = id & 63;
