@@ -109,6 +109,10 @@ GEOMS = [
     ((2, 2, 2, 2), 4, True),
     ((4, 2, 4, 6), 1, False),
     ((2, 4, 2, 4), 5, True),
+    # long fifth dimensions: 4 sites per wavefront at L5 = 16, 2 at the
+    # largest extent the library takes (32)
+    ((2, 2, 4, 6), 16, True),
+    ((2, 2, 2, 4), 32, False),
 ]
 ALL_OPS = list(range(20))
 
@@ -369,6 +373,27 @@ def test_solve_matches_oracle(M, cfg1, inner):
         assert rel(x, x_ref) <= 1e-7
         if inner:
             assert info[0]["reliable_updates"] >= 1
+    finally:
+        M.mdwf_destroy(ctx)
+
+
+@pytest.mark.parametrize("inner,form", [(0, 0), (2, 2)], ids=["f64_asym", "f16_inner_rp"])
+def test_solve_with_long_fifth_dimension(M, inner, form):
+    """L5 = 16 on 4^4 (four sites per wavefront, dense L5 x L5 polynomials of
+    sixteen terms): the solution's true residual by the oracle's operator
+    is at most 1e-10."""
+    dims, L5 = (4, 4, 4, 4), 16
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 61)
+    b = I.gaussian_source(dims, L5, 62)
+    ctx = make_ctx(M, act, U)
+    try:
+        x = np.zeros_like(b)
+        st, info = M.mdwf_solve(ctx, [b], [x], opts=dict(tol=1e-10, inner=inner, max_iter=20000, schur_form=form))
+        assert st == M.MDWF_OK, info
+        tr = oracle.true_residual(act, U, b, x)
+        assert tr <= 1e-10, (tr, info)
+        assert abs(tr - info[0]["true_resid"]) <= 1e-11
     finally:
         M.mdwf_destroy(ctx)
 
