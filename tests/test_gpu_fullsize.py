@@ -1,9 +1,13 @@
-"""Parity at the benchmark's full size (24^3 x 64, L5 = 8), in the launch
-configuration the benchmark times.
+"""Parity at the benchmark's full size (24^3 x 64, L5 = 8): at the default
+launch shape, and at the shapes mdwf_autotune picks for the one-RHS
+operators the benchmark times (the batched CG operator of its solve is
+tested in test_gpu_benchmark_operator.py).
 
 * Sampled outputs: the oracle evaluates S, S^+ and D5 site by site at
   boundary and interior sites (t = 0, T-1, x = 0, X-1, z-block edges, random
   sites); the GPU results there must agree to the dslash tolerances.
+* The bare hop at the tuned shapes against the oracle's full-lattice hop,
+  every element.
 * Properties that hold at any size: <y, S x> = <S^+ y, x> in FP64 on the GPU;
   with unit links, D5 on a plane wave equals the momentum-space closed form
   e^{ipx} D5(p) chi at every site.
@@ -128,3 +132,35 @@ def test_free_field_plane_wave_full_size(big):
         assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= 1e-13
     finally:
         M.mdwf_destroy(ctx)
+
+
+def test_operators_at_the_tuned_shapes_full_size(big):
+    """The one-RHS operators the benchmark times, at the launch shapes
+    mdwf_autotune picks for them (the FP32 bare hop may run on the
+    plane-staged kernel): the bare hop against the oracle's full-lattice hop
+    at every site (relative norm, and every element within the tolerance
+    times the field's largest magnitude), S and S^+ at the sampled sites."""
+    M, ctx, act, U, psi = big
+    tune = M.mdwf_autotune(ctx)
+    print("[fullsize] tuned shapes %s" % tune, flush=True)
+    even = oracle.even_mask(DIMS)
+    oracle.use_threads(16)
+    try:
+        ref = np.ascontiguousarray(oracle.hop(act, U, psi, 0)[:, even])
+    finally:
+        oracle.use_threads(1)
+    po = np.ascontiguousarray(psi[:, ~even])
+    pe = even_half(psi)
+    scale = np.abs(ref).max()
+    sites = sample_sites(0)
+    sref = {dag: oracle.schur_sites(act, U, psi, sites, dag=dag) for dag in (False, True)}
+    for prec in (0, 1, 2):
+        out = np.zeros(ref.shape, complex)
+        M.mdwf_apply(ctx, M.MDWF_OP_HOP_EO, prec, po, out)
+        assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= TOL[prec], prec
+        assert np.abs(out - ref).max() <= TOL[prec] * scale, prec
+        for dag in (False, True):
+            s_out = np.zeros(pe.shape, complex)
+            M.mdwf_apply(ctx, M.MDWF_OP_SCHUR_DAG if dag else M.MDWF_OP_SCHUR, prec, pe, s_out)
+            got = s_out[:, half_index_of(sites)].transpose(1, 0, 2, 3)
+            assert np.linalg.norm(got - sref[dag]) / np.linalg.norm(sref[dag]) <= TOL[prec], (prec, dag)
