@@ -384,9 +384,11 @@ mdwf_status mdwf_op_model(const mdwf_ctx *ctx, mdwf_op op, mdwf_prec prec, doubl
  * fermion boundary condition plays no part).  plaq (may be NULL) receives
  * the average plaquette before and after.  The links must be SU(3) to
  * rounding (unitary, det 1): the staple links enter through their first two
- * rows, the third being the conjugated cross product of those.  Extents >= 2;
- * ERR_ARG on eps <= 0 or nsteps < 0.  Synchronous; allocates one link field
- * and eight reals per link of scratch. */
+ * rows, the third being the conjugated cross product of those.  A field
+ * with an entry of U U^+ - 1 or of det U - 1 beyond 1e-10 (or a NaN) is
+ * refused with ERR_ARG before anything is written.  Extents >= 2; ERR_ARG
+ * on eps <= 0 or nsteps < 0.  Synchronous; allocates one link field and
+ * eight reals per link of scratch. */
 mdwf_status mdwf_wilson_flow(const mdwf_geometry *geom, int hip_device, double *U, double eps, int nsteps,
                              double *plaq);
 /* Same on a device field, on `stream` (NULL = the null stream). */

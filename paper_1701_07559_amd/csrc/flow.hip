@@ -16,6 +16,7 @@
 // The exponential of the small traceless antihermitian E is a degree-12
 // Taylor polynomial after scaling by a power of two with squaring back.
 #include <cmath>
+#include <cstdio>
 #include <vector>
 
 #include "ctx.h"
@@ -24,6 +25,8 @@ namespace mdwf {
 namespace {
 
 constexpr int kFlowBlock = 256;
+// largest entry of U U^+ - 1 and of det U - 1 the flow accepts
+constexpr double kSu3Tol = 1e-10;
 
 struct Su3 {
     cx<double> m[9];
@@ -278,6 +281,47 @@ __global__ void __launch_bounds__(kFlowBlock) k_plaquette(const FlowGeo g, const
     }
 }
 
+// Largest deviation from SU(3) of the links of a block of sites: max over
+// each site's four links of the entries of U U^+ - 1 and of det U - 1 (re
+// and im parts), so a field the flow stage's two-row staple loads would
+// misread is refused.  NaN propagates into the partial.
+__device__ __forceinline__ double max_nan(double v, double x) { return (x > v || x != x) ? x : v; }
+
+__global__ void __launch_bounds__(kFlowBlock) k_su3_deviation(const double2* U, double* partials, long nsites) {
+    const long site = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (site < nsites) {
+        for (int mu = 0; mu < 4; ++mu) {
+            const Su3 a = ld_link(U, site * 4 + mu);
+            const Su3 p = mul_nd(a, a);   // U U^+
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                v = max_nan(v, fabs(p.m[k].re - ((k % 4 == 0) ? 1.0 : 0.0)));
+                v = max_nan(v, fabs(p.m[k].im));
+            }
+            // det U = row 2 . (row 0 x row 1)
+            const cx<double> c0 = cmadd(cmul(a.m[1], a.m[5]), cx<double>{-a.m[2].re, -a.m[2].im}, a.m[4]);
+            const cx<double> c1 = cmadd(cmul(a.m[2], a.m[3]), cx<double>{-a.m[0].re, -a.m[0].im}, a.m[5]);
+            const cx<double> c2 = cmadd(cmul(a.m[0], a.m[4]), cx<double>{-a.m[1].re, -a.m[1].im}, a.m[3]);
+            const cx<double> det = cmadd(cmadd(cmul(a.m[6], c0), a.m[7], c1), a.m[8], c2);
+            v = max_nan(v, fabs(det.re - 1.0));
+            v = max_nan(v, fabs(det.im));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max_nan(v, __shfl_xor(v, off, 64));
+    __shared__ double ws[kFlowBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) ws[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+#pragma unroll
+        for (int w = 0; w < kFlowBlock / 64; ++w) m = max_nan(m, ws[w]);
+        partials[blockIdx.x] = m;
+    }
+}
+
 mdwf_status check_geom(const mdwf_geometry* g) {
     if (!g) return fail(nullptr, MDWF_ERR_ARG, "null geometry");
     if (g->X < 2 || g->Y < 2 || g->Z < 2 || g->T < 2) return fail(nullptr, MDWF_ERR_ARG, "extents must be >= 2");
@@ -349,7 +393,21 @@ mdwf_status mdwf_wilson_flow_dev(const mdwf_geometry* geom, double* U_dev, doubl
     }
     std::vector<double> hpart(nblk_p);
     double2* W[2] = {reinterpret_cast<double2*>(U_dev), W2};
-    if (plaq) s = plaquette_dev(fg, W[0], part, hpart.data(), nsites, nblk_p, st, plaq);
+    {   // the links must be SU(3) (the stage rebuilds staple links' third rows)
+        hipLaunchKernelGGL(k_su3_deviation, dim3(nblk_p), dim3(kFlowBlock), 0, st, W[0], part, nsites);
+        s = hip_check(nullptr, hipGetLastError(), "SU(3) check kernel");
+        if (!s) s = hip_check(nullptr, hipMemcpyAsync(hpart.data(), part, sizeof(double) * nblk_p,
+                                                      hipMemcpyDeviceToHost, st), "SU(3) check D2H");
+        if (!s) s = hip_check(nullptr, hipStreamSynchronize(st), "SU(3) check");
+        double dev = 0.0;
+        for (int k = 0; k < nblk_p && !s; ++k) dev = (hpart[k] > dev || hpart[k] != hpart[k]) ? hpart[k] : dev;
+        if (!s && !(dev <= kSu3Tol)) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "gauge links are not SU(3): deviation %.3e > %.0e", dev, kSu3Tol);
+            s = fail(nullptr, MDWF_ERR_ARG, msg);
+        }
+    }
+    if (!s && plaq) s = plaquette_dev(fg, W[0], part, hpart.data(), nsites, nblk_p, st, plaq);
     const double ca[3] = {0.25, 8.0 / 9.0, 0.75}, cb[3] = {0.0, -17.0 / 9.0, -1.0};
     const unsigned grid = unsigned((nlinks + kFlowBlock - 1) / kFlowBlock);
     int cur = 0;

@@ -56,6 +56,32 @@ def test_flow_dev_entry_point_and_zero_steps(M):
     assert e.value.status == M.MDWF_ERR_ARG
 
 
+def test_flow_refuses_links_that_are_not_su3(M):
+    """The stage reads staple links by their first two rows, so a field that
+    is not SU(3) to 1e-10 (not unitary, det != 1, or NaN) is refused with
+    ERR_ARG and left as it was; one deviation of 1e-12 is accepted."""
+    import torch
+    dims = (4, 4, 2, 4)
+    U = I.random_links(dims, 0.3, 93)
+    scaled = U.copy()
+    scaled[1, 0, 1, 2, 3] *= 1.0 + 1e-6                  # not unitary
+    phased = U.copy()
+    phased[0, 1, 0, 1, 2] *= np.exp(0.1j)                # unitary, det = e^{0.1 i}
+    nan = U.copy()
+    nan[3, 1, 1, 0, 1, 2, 2] = np.nan
+    for bad in (scaled, phased, nan):
+        dev = torch.from_numpy(bad.view(np.float64).copy()).to("cuda:0")
+        torch.cuda.synchronize()
+        with pytest.raises(M.MdwfError) as e:
+            M.mdwf_wilson_flow_dev(dims, dev.data_ptr(), 0.02, 2)
+        assert e.value.status == M.MDWF_ERR_ARG and "SU(3)" in str(e.value)
+        back = dev.cpu().numpy().view(np.complex128).reshape(U.shape)
+        assert np.array_equal(back, bad, equal_nan=True)
+    near = U.copy()
+    near[2, 1, 0, 3, 0] *= 1.0 + 1e-12
+    M.mdwf_wilson_flow(dims, near, 0.02, 1)
+
+
 def test_flow_at_benchmark_volume_stays_su3_and_smooths(M):
     """24^3 x 64, the benchmark's exp(i 0.25 H) field, flowed to t = 1 in four
     legs of 0.25: the plaquette rises every leg and every link stays in SU(3)."""
