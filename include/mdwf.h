@@ -193,7 +193,9 @@ const char *mdwf_last_error(const mdwf_ctx *ctx);
  * (canonical layout, FP64) to the device, in FP64, FP32 and FP16 native link
  * layouts (the three precisions of the mixed solver, Sec. VII), with the
  * antiperiodic time sign folded into the links on the last time slice.
- * Synchronous.  ERR_ARG on a null pointer. */
+ * The FP16 copy holds the entries as binary16 with no scale, which suits
+ * SU(3) links (every entry at most 1 in magnitude); FP64 and FP32 take any
+ * links.  Synchronous.  ERR_ARG on a null pointer. */
 mdwf_status mdwf_load_gauge(mdwf_ctx *ctx, const double *U);
 
 /* Same as mdwf_load_gauge from a device pointer in the canonical layout. */
