@@ -126,9 +126,9 @@ typedef struct {
     int check_every;     /* host convergence check period in iterations (>=1)  */
     int use_graph;       /* 1: replay CG iterations from a captured hipGraph   */
     int profile_iters;   /* time the inner operator launches of this many CG
-                            iterations (from the third on) with HIP events on
-                            the solve stream; 0 = off, at most 64, ignored
-                            with use_graph                                   */
+                            iterations (from the third on, profile_every
+                            apart) with HIP events on the solve stream;
+                            0 = off, at most 64, ignored with use_graph      */
     int schur_form;      /* CG operator: 0 the asymmetric S x_e = b'_e;
                             1 the symmetric K5^-1 S x_e = K5^-1 b'_e (Sec.
                             VII); 2 S B^-1 y = b'_e, x_e = B^-1 y (right
@@ -144,6 +144,9 @@ typedef struct {
                             mdwf_solve_dev), e.g. the plain FP64 CG solutions
                             of the same systems.  Each is read once, after its
                             RHS has been solved, to fill info.err_vs_ref */
+    int profile_every;   /* > 1: the profiled iterations are the third, then
+                            every profile_every-th (so the samples can span
+                            the whole solve); 0 or 1: consecutive            */
 } mdwf_solver_opts;
 /* There is no switch for deterministic solves: every solve is.  The CG dot
  * products are summed per RHS in a fixed order (wavefront butterfly, then the

@@ -479,6 +479,7 @@ void mdwf_default_opts(mdwf_solver_opts* o) {
     o->schur_form = 0;
     o->max_seconds = 0.0;
     o->x_ref = nullptr;
+    o->profile_every = 0;
 }
 
 mdwf_status mdwf_solve_footprint(const mdwf_geometry* geom, int L5, mdwf_prec inner, int nrhs, int host_io,

@@ -540,8 +540,10 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
             return S.err;
     }
 
-    // launch timing: sampled iterations from the third on (not with a graph)
+    // launch timing: sampled iterations from the third on, profile_every
+    // apart (not with a graph)
     const int nprof = use_graph ? 0 : std::max(0, std::min(o.profile_iters, 64));
+    const int pstride = std::max(1, o.profile_every);
     int prof_done = 0;
     for (int e = 0; e < 6 * nprof; ++e) {
         hipEvent_t ev;
@@ -565,7 +567,7 @@ mdwf_status mdwf_solve_impl(mdwf_ctx* c, int nrhs, const double* const* b_in, do
         if (use_graph) {
             S.hipok(hipGraphLaunch(S.gexec[it & 1], st), "graph launch");
         } else {
-            S.prof = (it >= 2 && prof_done < nprof) ? &S.pev[6 * prof_done++] : nullptr;
+            S.prof = (it >= 2 && (it - 2) % pstride == 0 && prof_done < nprof) ? &S.pev[6 * prof_done++] : nullptr;
             S.one_iteration((it & 1) != 0);
             S.prof = nullptr;
         }

@@ -54,7 +54,8 @@ class mdwf_action(C.Structure):
 class mdwf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner", C.c_int), ("delta", C.c_double),
                 ("check_every", C.c_int), ("use_graph", C.c_int), ("profile_iters", C.c_int),
-                ("schur_form", C.c_int), ("max_seconds", C.c_double), ("x_ref", C.c_void_p)]
+                ("schur_form", C.c_int), ("max_seconds", C.c_double), ("x_ref", C.c_void_p),
+                ("profile_every", C.c_int)]
 
 
 class mdwf_solve_info(C.Structure):
