@@ -70,7 +70,8 @@ def test_dslash_matches_sparse_kron_assembly(dims):
         assert rel(out, ref) < 1e-14
 
 
-@pytest.mark.parametrize("dims,L5", [((2, 2, 2, 2), 4), ((2, 2, 4, 6), 3), ((4, 2, 2, 4), 5)])
+@pytest.mark.parametrize("dims,L5", [((2, 2, 2, 2), 4), ((2, 2, 4, 6), 3), ((4, 2, 2, 4), 5), ((2, 2, 2, 4), 16),
+                                     ((2, 2, 2, 2), 32)])
 def test_d5_matches_sparse_kron_assembly(dims, L5):
     act = oracle.Action(dims, L5, **ACT)
     U = I.random_links(dims, 0.4, 7)
@@ -307,7 +308,8 @@ def _k5inv_closed_form(L5, M5, b5, c5, mq):
     return out
 
 
-@pytest.mark.parametrize("L5,mq", [(4, 0.05), (8, 0.0102), (12, 0.0158), (5, 1.0), (1, 0.3)])
+@pytest.mark.parametrize("L5,mq", [(4, 0.05), (8, 0.0102), (12, 0.0158), (5, 1.0), (1, 0.3), (16, 0.05),
+                                   (32, 0.0102)])
 def test_k5_inverse_closed_form(L5, mq):
     dims = (2, 2, 2, 2)
     act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=mq)
@@ -496,7 +498,8 @@ def test_symmetric_schur_condition_number():
 
 
 @pytest.mark.parametrize("L5,mq,b5,c5", [(8, 0.0102, 1.5, 0.5), (12, 0.3, 2.0, 1.0), (5, 1.0, 1.5, 0.5),
-                                          (6, 0.05, 1.0, 0.0), (1, 0.2, 1.5, 0.5)])
+                                          (6, 0.05, 1.0, 0.0), (1, 0.2, 1.5, 0.5), (16, 0.05, 1.5, 0.5),
+                                          (32, 0.0102, 1.5, 0.5)])
 def test_b_inverse_closed_form(L5, mq, b5, c5):
     """B = b5 + c5 C has the same closed-form inverse as K5 with (a, b) ->
     (b5, c5): B^-1 = [b5 (1 + m z^L5)]^-1 sum_k z^k C^k, z = -c5/b5; the
