@@ -2,7 +2,8 @@
 the per-site bytes of one Schur-operator application against the scope
 table's figures, the vector-ALU peak of the FP16 kernels against its
 instruction count, the counter record applying only to the kernel source it
-was taken on, the flow stage's byte model, and the one-GPU guard."""
+was taken on, the flow stage's byte model, the one-GPU guard, and the
+counter summary that writes that record from rocprofv3 databases."""
 import json
 import os
 import subprocess
@@ -77,3 +78,52 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_counter_summary_computes_the_traffic_record(tmp_path, monkeypatch):
+    """bench.py --summarize on small stand-in rocprofv3 databases: the
+    12-RHS launches are picked by grid size, FETCH_SIZE and WRITE_SIZE are
+    scaled by what the 1 GiB copy reads and writes, and the record is A + B."""
+    import argparse
+    import sqlite3
+    monkeypatch.setattr(bench, "DIMS", (24, 24, 24, 64))
+    monkeypatch.setattr(bench, "L5", 8)
+    grid12 = 13824 * 12 * 256
+
+    def name(kind):
+        return "void mdwf::k_hop<(mdwf::Prec)2, %d, 0>(mdwf::Geo, mdwf::HopDev)" % kind
+
+    trace = str(tmp_path / "trace.db")
+    d = sqlite3.connect(trace)
+    d.execute("create table kernels (name text, duration integer, grid_x integer)")
+    d.executemany("insert into kernels values (?, ?, ?)",
+                  [(name(10), 1800000, grid12), (name(10), 1820000, grid12), (name(11), 2100000, grid12),
+                   (name(11), 2000000, 3538944), (name(5), 1700000, grid12), (name(12), 2000000, grid12),
+                   ("void mdwf::k_cg_r<(mdwf::Prec)2>(mdwf::Geo)", 1000000, 3538944)])
+    d.commit()
+    vals = {"FETCH_SIZE": {10: 4400000.0, 11: 5800000.0, "copy": 524288.0},
+            "WRITE_SIZE": {10: 2150000.0, 11: 2160000.0, "copy": 1048576.0}}
+    paths = {}
+    for cname, per in vals.items():
+        p = str(tmp_path / (cname + ".db"))
+        d = sqlite3.connect(p)
+        d.execute("create table counters_collection (kernel_name text, grid_size integer, counter_name text, "
+                  "value real)")
+        rows = [(name(k), grid12, cname, v) for k, v in per.items() if k != "copy"]
+        rows += [(name(11), 3538944, cname, 1.0),                     # a one-RHS launch: not selected
+                 ("__amd_rocclr_copyBuffer", 134217728, cname, per["copy"]),
+                 ("__amd_rocclr_copyBuffer", 64, cname, 0.5)]
+        d.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+        d.commit()
+        paths[cname] = p
+    out = tmp_path / "summary.md"
+    args = argparse.Namespace(summarize=[trace, paths["FETCH_SIZE"], paths["WRITE_SIZE"]], summary_cmds="cmd",
+                              schur_form="rp", summary_bench=None, summary_out=str(out))
+    bench.summarize(args)
+    text = out.read_text()
+    rec = json.loads(next(l for l in text.splitlines() if l.startswith("traffic-record: "))[len("traffic-record: "):])
+    expect = (4400000.0 * 2 + 2150000.0) * 1024 + (5800000.0 * 2 + 2160000.0) * 1024
+    assert rec["traffic_bytes_per_launch"] == pytest.approx(expect)
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0 and rec["form"] == "rp"
+    assert "| A (`k_hop<F16, 10, *>`) | 2 | 1810.0 |" in text
+    assert "| B (`k_hop<F16, 11, *>`) | 1 | 2100.0 |" in text
