@@ -127,3 +127,22 @@ def test_counter_summary_computes_the_traffic_record(tmp_path, monkeypatch):
     assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0 and rec["form"] == "rp"
     assert "| A (`k_hop<F16, 10, *>`) | 2 | 1810.0 |" in text
     assert "| B (`k_hop<F16, 11, *>`) | 1 | 2100.0 |" in text
+
+
+def test_roofline_of_the_batched_operator(l5_8):
+    """The roofline object from the solve's launch timing: the FP16 S B^-1
+    pair is priced against the derived vector-ALU peak with the HBM rate
+    beside it; other inner precisions against HBM."""
+    vh = 3538944
+    info = dict(hop_us=[1800.0, 2100.0, 1790.0, 2080.0], hop_rhs=12, hop_samples=46)
+    r = bench.roofline(info, "f16", vh, "rp")
+    secs = (1800.0 + 2100.0) * 1e-6
+    flops = 12 * vh * ((1320 + 48 * 8) + (1320 + 48 * 8 + 48))
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    assert r["achieved"] == pytest.approx(flops / secs / 1e12, abs=0.01)
+    assert r["frac"] == pytest.approx(flops / secs / 1e12 / bench.alu_peak_tflops(8), abs=1e-4)
+    assert r["hbm"]["achieved"] == pytest.approx((4544004096 + 6752305152) / secs / 1e9, abs=0.1)
+    assert r["launches"]["B"]["algorithmic_bytes"] == 6752305152
+    r32 = bench.roofline(info, "f32", vh, "rp")
+    assert r32["bound"] == "hbm" and r32["unit"] == "GB/s" and r32["peak"] == 8000.0
+    assert bench.roofline(dict(hop_us=[0, 0, 0, 0], hop_rhs=0), "f16", vh, "rp") is None
