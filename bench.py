@@ -236,10 +236,10 @@ def hop_launch_bytes(inner, Vh, nr):
 # What the counters show limits the hop kernels below the HBM roofline
 # (rocprofv3 summaries under profiles/).
 LIMITER = {
-    "f16": "co-limited: 89% VALU busy in kernels A / A_dag, 73-76% in B / B_dag (profiles/hop_valu_busy_24c64_L8.md), "
-           "while moving 5.9-6.7 TB/s to and from memory beyond L2, 2.2x the algorithmic bytes "
-           "(profiles/schur_rp_f16_24c64_L8_12rhs_counters.md); 13% fewer VALU instructions in kernel A did "
-           "not make it faster",
+    "f16": "co-limited: texture addresser 94-97% busy on 56-61 load instructions per wave "
+           "(profiles/hop_ta_busy_24c64_L8_12rhs.md) and VALU 89% busy in kernels A / A_dag, 73-76% in B / B_dag "
+           "(profiles/hop_valu_busy_24c64_L8.md), moving 5.9-6.7 TB/s beyond L2, 2.2x the algorithmic bytes "
+           "(profiles/schur_rp_f16_24c64_L8_12rhs_counters.md)",
     "f32": "re-reads of the input field beyond L2 (2.26x) at a rate near the streaming limit "
            "(profiles/hop_f32_plane_24c64_L8_counters.md)",
     "f64": "re-reads of the input field beyond L2 (1.75-2.5x) at 5.3-6.6 TB/s "
