@@ -47,7 +47,11 @@
  *
  * Errors: every call returns a status; nothing aborts or throws across the
  * ABI.  mdwf_last_error() describes the last failure on a context.
- * Threading: one context per host thread.  Ownership: the caller owns every
+ * Threading: one context per host thread.  A context's device temporaries
+ * (the Schur operators' odd intermediate, the batched coefficient table, the
+ * solver's vectors) serve all of its calls, so work that one context enqueues
+ * on different streams must be ordered by the caller; a temporary that has to
+ * grow waits for the device first.  Ownership: the caller owns every
  * pointer it passes; the library copies what it needs and frees only memory it
  * allocated itself.
  */

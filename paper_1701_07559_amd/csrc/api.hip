@@ -72,7 +72,12 @@ mdwf_status hip_check(mdwf_ctx* c, hipError_t e, const char* what) {
 void* buf(mdwf_ctx* c, const std::string& name, size_t n, mdwf_status* st) {
     auto& b = c->bufs[name];
     if (b.n >= n && b.p) return b.p;
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) {
+        // launches already enqueued (on any stream) may still read the
+        // smaller buffer: let them finish before it goes
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.p);
+    }
     b.p = nullptr;
     b.n = 0;
     void* p = nullptr;
