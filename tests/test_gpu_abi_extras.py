@@ -6,6 +6,10 @@
 * mdwf_set_action replaces the coefficient table that an operator launch
   already enqueued on the context's stream reads: that launch must still see
   the old action.
+* A batched apply that needs larger context temporaries than the launches
+  still queued on its stream (a coefficient table and an odd intermediate
+  for more RHS) replaces them only after those launches are done: both the
+  queued and the new results match the oracle.
 * The solver's memory plan (mdwf_solve_footprint) matches what a solve
   actually allocates.
 * A gauge field added to a server while a request is queued shrinks the
@@ -110,6 +114,53 @@ def test_set_action_waits_for_enqueued_apply(M):
         ref = oracle.schur(act, U, psi)[:, even]
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-13
     finally:
+        M.mdwf_destroy(ctx)
+
+
+def test_batched_apply_grows_temporaries_behind_queued_launches(M):
+    import torch
+    dims, L5 = (12, 12, 12, 16), 8
+    act = oracle.Action(dims, L5, M5=1.3, b5=1.5, c5=0.5, mq=0.05)
+    U = I.random_links(dims, 0.3, 113)
+    fields = [I.gaussian_source(dims, L5, 114 + k) for k in range(3)]
+    even = oracle.even_mask(dims)
+    masses = (0.05, 0.1, 0.2)
+    ctx = make_ctx(M, act, U)
+    dev = torch.device("cuda:0")
+    work = torch.cuda.Stream(device=dev)   # a caller's stream, not the context's
+    try:
+        prec, kind = M.MDWF_F64, M.MDWF_HALF_EVEN
+        stride = (M.mdwf_field_bytes(ctx, prec, kind) + 255) // 256 * 256
+        canon = [torch.from_numpy(np.ascontiguousarray(f[:, even]).view(np.float64).ravel()).to(dev)
+                 for f in fields]
+        nin = torch.zeros(3 * stride, dtype=torch.uint8, device=dev)
+        one = torch.zeros(stride, dtype=torch.uint8, device=dev)
+        three = torch.zeros(3 * stride, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        st = work.cuda_stream
+        for k in range(3):
+            M.mdwf_pack_dev(ctx, prec, kind, canon[k].data_ptr(), nin.data_ptr() + k * stride, st)
+        # first use of the batched temporaries: sized for one RHS
+        for _ in range(3):
+            M.mdwf_apply_batch_dev(ctx, M.MDWF_OP_SCHUR_RP, prec, 1, nin.data_ptr(), one.data_ptr(), stride,
+                                   mq=[masses[0]], stream=st)
+        # no synchronisation: three RHS need larger ones
+        M.mdwf_apply_batch_dev(ctx, M.MDWF_OP_SCHUR_RP, prec, 3, nin.data_ptr(), three.data_ptr(), stride,
+                               mq=list(masses), stream=st)
+        outs = [(one, 0, 0)] + [(three, k, k) for k in range(3)]
+        got = []
+        for buf, slot, _ in outs:
+            o = torch.empty_like(canon[0])
+            M.mdwf_unpack_dev(ctx, prec, kind, buf.data_ptr() + slot * stride, o.data_ptr(), st)
+            got.append(o)
+        torch.cuda.synchronize()
+        for (buf, slot, k), o in zip(outs, got):
+            g = o.cpu().numpy().view(np.complex128).reshape(L5, -1, 4, 3)
+            ref = oracle.schur_rp(act.with_mass(masses[k]), U, fields[k])[:, even]
+            e = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+            assert e <= 1e-13, "RHS %d of the %d-RHS launch: %.3e" % (k, 1 if buf is one else 3, e)
+    finally:
+        torch.cuda.synchronize()
         M.mdwf_destroy(ctx)
 
 
