@@ -1043,6 +1043,9 @@ def main():
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay CG iterations from a hipGraph (no per-launch timing then)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--delta", type=float, default=0.1,
+                    help="reliable update of the mixed solve when ||r|| falls below delta x its value "
+                         "at the last update")
     ap.add_argument("--micro-only", action="store_true", help="time the operator kernels and stop")
     ap.add_argument("--micro-reps", type=int, default=50)
     ap.add_argument("--micro-precs", default="f64,f32,f16")
@@ -1188,7 +1191,7 @@ def main():
     # launches with HIP events on the solve stream (the roofline figure) in
     # every 8th CG iteration from the third, so the samples span the whole
     # timed solve (up to 64 of them)
-    opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=0.1, use_graph=args.graph,
+    opts = dict(tol=1e-10, inner=inner, max_iter=args.max_iter, delta=args.delta, use_graph=args.graph,
                 profile_iters=0 if args.graph else 64, profile_every=PROFILE_EVERY, schur_form=FORMS[form])
     bptr = [b[rhs_col[k]].data_ptr() for k in range(nrhs)]
     xptr = [x[k].data_ptr() for k in range(per)]
@@ -1347,7 +1350,7 @@ def main():
                           GROUPS, args.inner, per, FORM_NAMES[form])),
             "name": args.workload,
             "lattice": list(DIMS), "L5": L5, "nrhs": nrhs, "masses": MASSES, "inner": inner_name,
-            "schur_form": form, "b5": ACTION["b5"], "c5": ACTION["c5"],
+            "schur_form": form, "b5": ACTION["b5"], "c5": ACTION["c5"], "delta": args.delta,
             "launch_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), tune)} if tune else None),
             "solve_tune": ({pn: t for pn, t in zip(("f64", "f32", "f16"), solve_tune)} if solve_tune else None),
         },
